@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Throughput of the MI355X Viterbi decoder on its headline workload.
+
+Workload: 4096 zero-terminated frames x 8192 info bits, K=7 (133,171) rate
+1/2, BPSK over AWGN (seeded), soft values already resident in HBM.
+A step decodes the whole batch: forward procedure (branch metrics,
+add-compare-select, packed survivor decisions) plus traceback.
+
+  value      int8 soft values, radix-4 forward (decoded info Gbit/s)
+  variants   the same for float32 radix-2 and int8 radix-2
+  roofline   the forward kernel of the headline variant against the vector
+             ALU peak: 3 ops per state per stage (add, add, compare-select)
+  cpu_baseline  the CPU oracle (exact integers) on the host cores
+
+Prints one JSON line.  --ber adds the equal-BER sweep (0..6 dB).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "decoded info Gbit/s on 1 MI355X (K=7 r1/2), int8 radix-4 vs fp32 radix-2, at equal BER"
+N_FRAMES, N_INFO = 4096, 8192
+CUS, LANES, CLOCK_HZ = 256, 64, 2.4e9
+VALU32_PEAK_TOPS = CUS * LANES * CLOCK_HZ / 1e12  # 39.32 T lane-ops/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--ebn0", type=float, default=3.0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--ber", action="store_true", help="run the equal-BER sweep")
+    ap.add_argument("--variants", default="i8r4,f32r2,i8r2")
+    return ap.parse_args()
+
+
+def time_variant(torch, mv, plan, llr, steps, warmup):
+    dev = llr.device
+    bits, metric, end = plan.empty_outputs(dev)
+    st = torch.cuda.current_stream()
+    for _ in range(warmup):
+        plan.forward(llr, metric, end)
+        plan.traceback(bits)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record(st)
+        plan.forward(llr, metric, end)
+        ev[k][1].record(st)
+        plan.traceback(bits)
+        ev[k][2].record(st)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    fwd = float(np.mean([ev[k][0].elapsed_time(ev[k][1]) for k in range(steps)]))
+    tb = float(np.mean([ev[k][1].elapsed_time(ev[k][2]) for k in range(steps)]))
+    return wall * 1e3, fwd, tb, bits, metric
+
+
+def cpu_baseline(code, llr_i8_np):
+    import oracle
+    threads = oracle.default_threads()
+    n = llr_i8_np.shape[0]
+    oracle.decode_uniform(code, llr_i8_np[:8], N_INFO, True, oracle.I64, n_threads=threads)
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.decode_uniform(code, llr_i8_np, N_INFO, True, oracle.I64, n_threads=threads)
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
+    return {"value": round(n * N_INFO / dt / 1e9, 6), "unit": "Gbit/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d frames x %d bits of the same workload, exact-integer radix-2 oracle, "
+                      "median of 3 runs (%.2f s each)" % (n, N_INFO, dt)}
+
+
+def ber_sweep(torch, mv, code, frames_plan_i8, frames_plan_f32):
+    from workload import make_uniform_batch, int8_scale_for
+    out = []
+    for db in range(0, 7):
+        b = make_uniform_batch(code, N_FRAMES, N_INFO, float(db), seed=2000 + db)
+        lf = torch.from_numpy(b.llr).to("cuda:0")
+        li = mv.quantize_i8(lf, int8_scale_for(float(db), code.beta))
+        row = {"ebn0_db": db, "bits": int(b.msg.size)}
+        for name, plan, llr in (("f32r2", frames_plan_f32, lf), ("i8r4", frames_plan_i8, li)):
+            bits, _, _ = plan.decode(llr)
+            torch.cuda.synchronize()
+            dec = mv.unpack_bits(bits.cpu().numpy()[: N_FRAMES * (N_INFO // 32)].reshape(N_FRAMES, -1), N_INFO)
+            row[name + "_errors"] = int((dec != b.msg).sum())
+            if name == "f32r2":
+                ref = dec
+            else:
+                row["paired_differing_bits"] = int((dec != ref).sum())
+        out.append(row)
+        del lf, li
+    def at(target, key):
+        pts = [(r["ebn0_db"], r[key] / r["bits"]) for r in out]
+        for (d0, b0), (d1, b1) in zip(pts, pts[1:]):
+            if b0 >= target >= b1 and b0 > 0 and b1 > 0:
+                x0, x1 = math.log10(b0), math.log10(b1)
+                return d0 + (math.log10(target) - x0) * (d1 - d0) / (x1 - x0)
+        return None
+    res = {"points": out}
+    for tgt in (1e-4, 1e-5):
+        a, c = at(tgt, "f32r2_errors"), at(tgt, "i8r4_errors")
+        res["ebn0_at_%g" % tgt] = {"f32r2": a, "i8r4": c,
+                                   "gap_db": None if a is None or c is None else round(c - a, 4)}
+    return res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (frames shard across GPUs with no "
+              "exchange; see the design notes); --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2011_13579_amd as mv
+    from workload import CODE_K7, make_uniform_batch, int8_scale_for
+
+    code = CODE_K7
+    dev = "cuda:0"
+    b = make_uniform_batch(code, N_FRAMES, N_INFO, args.ebn0, seed=2000 + int(round(args.ebn0)))
+    llr_f32 = torch.from_numpy(b.llr).to(dev)
+    llr_i8 = mv.quantize_i8(llr_f32, int8_scale_for(args.ebn0, code.beta))
+    torch.cuda.synchronize()
+    frames = mv.uniform_frames(code, N_FRAMES, N_INFO, True)
+    S = N_INFO + code.K - 1
+    ops_per_launch = 3 * (1 << (code.K - 1)) * S * N_FRAMES
+
+    plans = {}
+    results = {}
+    for v in args.variants.split(","):
+        dt, radix = ("i8", 4) if v == "i8r4" else ("f32", 2) if v == "f32r2" else ("i8", 2)
+        plans[v] = mv.Plan([code], frames, dt, radix)
+        llr = llr_i8 if dt == "i8" else llr_f32
+        ms, fwd, tb, bits, _ = time_variant(torch, mv, plans[v], llr, args.steps, args.warmup)
+        dec = mv.unpack_bits(bits.cpu().numpy()[: N_FRAMES * (N_INFO // 32)].reshape(N_FRAMES, -1), N_INFO)
+        results[v] = {
+            "gbit_s": round(N_FRAMES * N_INFO / (ms * 1e-3) / 1e9, 3),
+            "ms_per_step": round(ms, 4), "forward_ms": round(fwd, 4), "traceback_ms": round(tb, 4),
+            "forward_tops": round(ops_per_launch / (fwd * 1e-3) / 1e12, 3),
+            "forward_frac_valu32": round(ops_per_launch / (fwd * 1e-3) / 1e12 / VALU32_PEAK_TOPS, 4),
+            "bit_errors": int((dec != b.msg).sum()),
+        }
+    head = results.get("i8r4") or next(iter(results.values()))
+    hv = "i8r4" if "i8r4" in results else next(iter(results))
+    achieved = ops_per_launch / (head["forward_ms"] * 1e-3) / 1e12
+    line = {
+        "metric": METRIC,
+        "value": head["gbit_s"],
+        "unit": "Gbit/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8" if hv.startswith("i8") else "f32",
+        "data": "synthetic (seeded bits, BPSK/AWGN at %.1f dB)" % args.ebn0,
+        "config": {"workload": "%d terminated frames x %d info bits, K=7 (133,171) r1/2, %s" %
+                   (N_FRAMES, N_INFO, hv), "frames": N_FRAMES, "info_bits": N_INFO,
+                   "ebn0_db": args.ebn0, "variant": hv},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3),
+                     "peak": round(VALU32_PEAK_TOPS, 2), "unit": "Tops/s",
+                     "frac": round(achieved / VALU32_PEAK_TOPS, 4), "traffic": None,
+                     "kernel": "forward (%s)" % hv,
+                     "work": "3 ops x 64 states x %d stages x %d frames per launch" % (S, N_FRAMES)},
+        "variants": results,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(code, llr_i8.cpu().numpy())
+    if args.ber:
+        line["equal_ber"] = ber_sweep(torch, mv, code, plans.get("i8r4"), plans.get("f32r2"))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

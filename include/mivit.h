@@ -1,0 +1,175 @@
+/*
+ * mivit.h - soft-decision Viterbi decoding of convolutional codes on AMD
+ * Instinct MI355X (gfx950).  Plain C ABI: no C++ or framework types cross it.
+ *
+ * The operation is the decoder of arXiv 2011.13579 ("High-Throughput
+ * Parallel Viterbi Decoder on GPU Tensor Cores"):
+ *   - §II-A  encoder equation and trellis (K, beta, generator polynomials);
+ *   - §II-B  branch metric Eq. (BM), path metric Eq. (PM), survivor Eq. (SP0),
+ *            forward procedure (Algorithm 1) and traceback (Algorithm 2);
+ *   - §III   long streams split into frames that overlap their neighbours;
+ *   - §VI-§VIII radix-4 form: Eqs. (radix4:BM), (radix4:PM), (radix4:SP0),
+ *            two trellis stages per iteration.
+ *
+ * Conventions shared by every entry point
+ *   Trellis      state = previous K-1 input bits, most recent in the MSB;
+ *                generator bit K-1 taps the current input, bit 0 the oldest.
+ *                Output bit b of a branch uses gen[b].
+ *   Soft values  one per coded bit, time-major: stage t of a frame occupies
+ *                elements [t*beta, (t+1)*beta) after the frame's offset.
+ *                Positive favours coded bit 0 (§II-C).  float32 or int8.
+ *   Decisions    Eq. (PM) with a strict comparison: on a tie the lower-index
+ *                previous state is kept.  Radix-4 keeps the smallest local
+ *                left index y, which yields the same path.  With an unknown
+ *                final state the best final state is used, ties to the
+ *                lowest index.
+ *   Arithmetic   float32 frames run Eqs. (BM)/(PM) in IEEE single precision
+ *                (Eq. (BM) summed over b in increasing order, then one add to
+ *                the path metric).  int8 frames run them exactly in integers.
+ *   Output bits  packed 32 per uint32, least significant bit first.
+ *   Pointers     soft values, bits, metrics and gradients are DEVICE
+ *                pointers owned by the caller.  Descriptor arrays (codes,
+ *                frames, options) are HOST pointers, copied at plan time.
+ *   Streams      'stream' is a hipStream_t (NULL = the default stream).
+ *                Decoding calls are asynchronous on that stream.
+ *   Errors       every call returns a status; invalid arguments are rejected
+ *                before any device work is queued; no call aborts the process.
+ */
+#ifndef MIVIT_H
+#define MIVIT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MIVIT_OK = 0,
+  MIVIT_EINVAL = -1,       /* invalid argument or descriptor */
+  MIVIT_ENOMEM = -2,       /* device or host allocation failed */
+  MIVIT_EHIP = -3,         /* a HIP runtime call failed */
+  MIVIT_EUNSUPPORTED = -4  /* valid request this build does not implement */
+} mivit_status;
+
+typedef enum { MIVIT_F32 = 0, MIVIT_I8 = 1 } mivit_dtype;
+
+/* A convolutional code (§II-A): 3 <= K <= 9, 2 <= beta <= 4, 0 < gen[b] < 2^K,
+ * and every generator has bit K-1 and bit 0 set (the premise of the
+ * branch-output corollary of §IV, met by the standard codes); other codes are
+ * rejected with MIVIT_EUNSUPPORTED. */
+typedef struct {
+  int32_t K;
+  int32_t beta;
+  uint32_t gen[4];
+} mivit_code;
+
+/* frame flags */
+#define MIVIT_START_KNOWN 1u /* encoder started in state 0 (else: unknown start,
+                                all-zero initial path metrics as in Algorithm 1) */
+#define MIVIT_END_ZERO 2u    /* trace back from state 0 (terminated frame); else
+                                from the best final state */
+
+/* One frame: an independent run of the trellis over n_stages stages. */
+typedef struct {
+  int64_t llr_offset; /* element index (in soft values) of stage 0, value 0 */
+  int64_t bit_offset; /* bit index in the output of emitted bit 0; multiple of 32 */
+  int32_t n_stages;   /* S >= 0 trellis stages (terminated: N + K - 1) */
+  int32_t out_begin;  /* first stage whose decoded bit is emitted */
+  int32_t n_out;      /* decoded bits emitted: stages [out_begin, out_begin+n_out) */
+  int16_t code;       /* index into the plan's code array */
+  uint16_t flags;     /* MIVIT_START_KNOWN | MIVIT_END_ZERO */
+} mivit_frame;
+
+/* Plan options.  Zero-initialised means: choose automatically. */
+typedef struct {
+  int32_t dtype;    /* mivit_dtype of every frame's soft values */
+  int32_t radix;    /* 0: choose; 2: radix-2; 4: radix-4 (int8 only) */
+  int32_t chunk;    /* >0: split every frame longer than chunk stages into
+                       windows of chunk core stages plus 'overlap' stages on
+                       each side (§III); 0: decode whole frames */
+  int32_t overlap;  /* stages of overlap on each side of a chunk, >= 0 */
+  int32_t reserved[4];
+} mivit_opts;
+
+typedef struct mivit_plan mivit_plan;
+
+/* Build a plan for a fixed batch description: validates the descriptors,
+ * expands chunked frames into windows, orders the work longest first and
+ * reserves the survivor memory (bit-packed decisions, 2^(K-1) bits per stage
+ * per frame or window, §III) on the current device.  codes/frames/opts are
+ * host pointers and are copied.  On success *plan owns device memory until
+ * mivit_plan_destroy.  Errors: MIVIT_EINVAL (bad code or frame, overlapping
+ * or unaligned outputs, radix 4 with float32), MIVIT_EUNSUPPORTED,
+ * MIVIT_ENOMEM, MIVIT_EHIP. */
+mivit_status mivit_plan_create(mivit_plan** plan, const mivit_code* codes, int32_t n_codes,
+                               const mivit_frame* frames, int32_t n_frames,
+                               const mivit_opts* opts);
+
+/* Decode every frame of the plan (forward procedure, then traceback).
+ *   llr        device, float32 or int8 per the plan's dtype, read-only
+ *   bits       device uint32 words; frame f writes the words covering
+ *              [bit_offset, bit_offset + n_out), zero-padding the last one
+ *   metric     device, one per frame: float32 (float plans) or int64 (int8
+ *              plans): the path metric of the decoded path, Eq. (PM) at the
+ *              last stage.  For a chunked frame, that of its last window.
+ *              May be NULL.
+ *   end_state  device int32 per frame: the state traceback started from
+ *              (last window for chunked frames).  May be NULL.
+ * Asynchronous on 'stream'.  One plan must not be used by two overlapping
+ * calls (it owns the survivor memory). */
+mivit_status mivit_decode(mivit_plan* plan, const void* llr, uint32_t* bits, void* metric,
+                          int32_t* end_state, void* stream);
+
+/* The two phases of mivit_decode, for callers that time or overlap them.
+ * mivit_forward runs the forward procedure (Algorithm 1 / Eq. (radix4:PM)),
+ * storing the decisions in the plan and writing metric and end_state as
+ * mivit_decode does; mivit_traceback then runs Algorithm 2 and writes bits.
+ * A traceback must follow the forward call of the same plan on the same
+ * stream; between them the plan must not be used by another call. */
+mivit_status mivit_forward(mivit_plan* plan, const void* llr, void* metric, int32_t* end_state,
+                           void* stream);
+mivit_status mivit_traceback(mivit_plan* plan, uint32_t* bits, void* stream);
+
+/* Backward of the best path metric (not in the paper; follows from
+ * Eq. (BM) being linear in the soft values): for every frame f and every
+ * stage t and output bit b,
+ *   grad_llr[llr_offset_f + t*beta + b] = grad_metric[f] * (-1)^{c_{t,b}}
+ * where c is the codeword of the decoded bits (re-encoded, §II-A; tail bits
+ * of terminated frames are zero).  bits is the output of mivit_decode for the
+ * same plan; grad_metric and grad_llr are device float32.  Plans with chunked
+ * frames or frames whose emitted bits do not cover every stage but a zero
+ * tail are rejected with MIVIT_EUNSUPPORTED. */
+mivit_status mivit_decode_grad(mivit_plan* plan, const uint32_t* bits, const float* grad_metric,
+                               float* grad_llr, void* stream);
+
+/* Release a plan's device and host memory (waits for the device first). */
+mivit_status mivit_plan_destroy(mivit_plan* plan);
+
+/* Plan facts for callers and tools. */
+typedef struct {
+  int64_t n_items;         /* frames after chunking */
+  int64_t survivor_bytes;  /* device memory reserved for decisions */
+  int64_t total_stages;    /* sum of stages over work items */
+  int32_t radix;           /* radix in use */
+  int32_t dtype;
+} mivit_plan_info;
+mivit_status mivit_plan_get_info(const mivit_plan* plan, mivit_plan_info* info);
+
+/* int8 quantiser for soft values (paper silent; see the readings in the
+ * design notes): q[k] = saturate_127(round_half_even(fl32(llr[k] * scale))).
+ * llr: device float32 [n]; q: device int8 [n]; scale > 0.  NaN maps to 0. */
+mivit_status mivit_quantize_i8(const float* llr, int8_t* q, int64_t n, float scale,
+                               void* stream);
+
+/* Static text for a status code. */
+const char* mivit_strerror(mivit_status status);
+
+/* Library version string. */
+const char* mivit_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MIVIT_H */

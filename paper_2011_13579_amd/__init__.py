@@ -1,0 +1,297 @@
+"""mivit: soft-decision Viterbi decoding of convolutional codes on MI355X.
+
+Python binding of the C ABI in include/mivit.h.  Every step of decoding runs
+in the HIP library (libmivit.so); this module only marshals arguments: device
+pointers of torch tensors, the current HIP stream, descriptor arrays.  There is
+no CPU fallback: if the library is missing every call raises.
+
+Entry points
+  Plan(codes, frames, dtype, radix, chunk, overlap)  general batch
+  decode(llr, code, n_info, terminated, radix)       equal-length frames
+  decode_stream(llr, code, n_info, chunk, overlap)   one long stream, chunked
+  quantize_i8(llr, scale)                            float32 -> int8 soft values
+  ViterbiDecode.apply(llr, code, n_info)             autograd on the best metric
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _capi
+from ._capi import FRAME_DTYPE, MIVIT_END_ZERO, MIVIT_F32, MIVIT_I8, MIVIT_START_KNOWN, MivitError
+
+__all__ = ["Code", "Plan", "decode", "decode_stream", "quantize_i8", "ViterbiDecode",
+           "unpack_bits", "FRAME_DTYPE", "MivitError", "version"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+@dataclass(frozen=True)
+class Code:
+    """Convolutional code: constraint length K and one K-bit tap mask per
+    output bit (bit K-1 taps the current input)."""
+    K: int
+    gens: tuple
+
+    @property
+    def beta(self) -> int:
+        return len(self.gens)
+
+    @staticmethod
+    def from_octal(K: int, gens_octal: Sequence[str]) -> "Code":
+        return Code(K, tuple(int(str(g), 8) for g in gens_octal))
+
+    def c_struct(self) -> _capi.Code:
+        c = _capi.Code()
+        c.K = int(self.K)
+        c.beta = len(self.gens)
+        for b, g in enumerate(self.gens):
+            c.gen[b] = int(g)
+        return c
+
+
+def _as_code(code) -> Code:
+    if isinstance(code, Code):
+        return code
+    return Code(int(code.K), tuple(int(g) for g in code.gens))
+
+
+def version() -> str:
+    return _capi.load().mivit_version().decode()
+
+
+def _stream_handle(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+class Plan:
+    """A fixed batch of frames (see mivit_plan_create).
+
+    frames: numpy array of FRAME_DTYPE (llr_offset, bit_offset, n_stages,
+    out_begin, n_out, code, flags).
+    """
+
+    def __init__(self, codes: Sequence, frames: np.ndarray, dtype: str = "f32", radix: int = 0,
+                 chunk: int = 0, overlap: int = 0):
+        lib = _capi.load()
+        self.codes = [_as_code(c) for c in codes]
+        self.frames = np.ascontiguousarray(frames, dtype=FRAME_DTYPE)
+        self.dtype = {"f32": MIVIT_F32, "i8": MIVIT_I8}[dtype]
+        arr = (_capi.Code * len(self.codes))(*[c.c_struct() for c in self.codes])
+        opts = _capi.Opts()
+        opts.dtype, opts.radix, opts.chunk, opts.overlap = self.dtype, int(radix), int(chunk), int(overlap)
+        h = ctypes.c_void_p()
+        st = lib.mivit_plan_create(ctypes.byref(h), arr, len(self.codes),
+                                   self.frames.ctypes.data if len(self.frames) else None,
+                                   len(self.frames), ctypes.byref(opts))
+        _capi.check(st, "mivit_plan_create")
+        self._h = h
+        self._lib = lib
+        info = _capi.PlanInfo()
+        _capi.check(lib.mivit_plan_get_info(h, ctypes.byref(info)), "mivit_plan_get_info")
+        self.n_items = int(info.n_items)
+        self.survivor_bytes = int(info.survivor_bytes)
+        self.total_stages = int(info.total_stages)
+        self.radix = int(info.radix)
+        self.n_frames = len(self.frames)
+        if len(self.frames):
+            ends = self.frames["bit_offset"] + self.frames["n_out"]
+            self.n_bit_words = int((ends.max() + 31) // 32)
+        else:
+            self.n_bit_words = 0
+
+    @property
+    def handle(self) -> int:
+        return int(self._h.value or 0)
+
+    def empty_outputs(self, device):
+        torch = _torch()
+        bits = torch.zeros(max(self.n_bit_words, 1), dtype=torch.int32, device=device)
+        mdt = torch.float32 if self.dtype == MIVIT_F32 else torch.int64
+        metric = torch.zeros(max(self.n_frames, 1), dtype=mdt, device=device)
+        end = torch.zeros(max(self.n_frames, 1), dtype=torch.int32, device=device)
+        return bits, metric, end
+
+    def decode(self, llr, bits=None, metric=None, end_state=None, stream=None):
+        """Decode on the current stream; returns (bit words int32, metric, end state)."""
+        torch = _torch()
+        want = torch.float32 if self.dtype == MIVIT_F32 else torch.int8
+        if llr.dtype != want or not llr.is_cuda or not llr.is_contiguous():
+            raise ValueError("llr must be a contiguous device tensor of dtype %s" % want)
+        if bits is None:
+            bits, metric, end_state = self.empty_outputs(llr.device)
+        st = self._lib.mivit_decode(self._h, _dptr(llr), _dptr(bits), _dptr(metric),
+                                    _dptr(end_state), _stream_handle(stream))
+        _capi.check(st, "mivit_decode")
+        return bits, metric, end_state
+
+    def forward(self, llr, metric=None, end_state=None, stream=None):
+        """Forward procedure only (decisions stay in the plan)."""
+        st = self._lib.mivit_forward(self._h, _dptr(llr), _dptr(metric), _dptr(end_state),
+                                     _stream_handle(stream))
+        _capi.check(st, "mivit_forward")
+
+    def traceback(self, bits, stream=None):
+        """Traceback of the decisions left by the last forward call."""
+        st = self._lib.mivit_traceback(self._h, _dptr(bits), _stream_handle(stream))
+        _capi.check(st, "mivit_traceback")
+        return bits
+
+    def decode_grad(self, bits, grad_metric, grad_llr, stream=None):
+        st = self._lib.mivit_decode_grad(self._h, _dptr(bits), _dptr(grad_metric),
+                                         _dptr(grad_llr), _stream_handle(stream))
+        _capi.check(st, "mivit_decode_grad")
+        return grad_llr
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.mivit_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def uniform_frames(code, n_frames: int, n_info: int, terminated: bool = True) -> np.ndarray:
+    """Frames laid out back to back: frame f reads llr[f] and writes bit words
+    [f * ceil(N/32), (f+1) * ceil(N/32))."""
+    code = _as_code(code)
+    S = n_info + (code.K - 1 if terminated else 0)
+    wpf = (n_info + 31) // 32
+    fr = np.zeros(n_frames, FRAME_DTYPE)
+    fr["llr_offset"] = np.arange(n_frames, dtype=np.int64) * S * code.beta
+    fr["bit_offset"] = np.arange(n_frames, dtype=np.int64) * wpf * 32
+    fr["n_stages"] = S
+    fr["out_begin"] = 0
+    fr["n_out"] = n_info
+    fr["code"] = 0
+    fr["flags"] = MIVIT_START_KNOWN | (MIVIT_END_ZERO if terminated else 0)
+    return fr
+
+
+_plan_cache = {}
+
+
+def _cached_plan(key, make):
+    p = _plan_cache.get(key)
+    if p is None:
+        if len(_plan_cache) >= 8:
+            _plan_cache.pop(next(iter(_plan_cache))).close()
+        p = make()
+        _plan_cache[key] = p
+    return p
+
+
+def decode(llr, code, n_info: int, terminated: bool = True, radix: int = 0, stream=None):
+    """Equal-length frames.  llr: device tensor [F, S*beta] float32 or int8.
+
+    Returns (bit words int32 [F, ceil(N/32)], metric [F]).
+    """
+    torch = _torch()
+    code = _as_code(code)
+    F = llr.shape[0] if llr.dim() == 2 else 1
+    dt = "f32" if llr.dtype == torch.float32 else "i8"
+    key = ("u", code, F, n_info, terminated, dt, radix, llr.device.index)
+    plan = _cached_plan(key, lambda: Plan([code], uniform_frames(code, F, n_info, terminated),
+                                          dt, radix))
+    bits, metric, _ = plan.decode(llr.contiguous(), stream=stream)
+    wpf = (n_info + 31) // 32
+    return bits[: F * wpf].view(F, wpf), metric[:F]
+
+
+def decode_stream(llr, code, n_info: int, chunk: int = 2048, overlap: int = 64, radix: int = 0,
+                  stream=None):
+    """One unterminated stream starting in state 0, split into chunks of
+    ``chunk`` stages decoded on windows widened by ``overlap`` on each side.
+    Returns bit words int32 [ceil(N/32)]."""
+    torch = _torch()
+    code = _as_code(code)
+    dt = "f32" if llr.dtype == torch.float32 else "i8"
+    fr = np.zeros(1, FRAME_DTYPE)
+    fr[0] = (0, 0, n_info, 0, n_info, 0, MIVIT_START_KNOWN)
+    key = ("s", code, n_info, chunk, overlap, dt, radix, llr.device.index)
+    plan = _cached_plan(key, lambda: Plan([code], fr, dt, radix, chunk, overlap))
+    bits, metric, end = plan.decode(llr.contiguous(), stream=stream)
+    return bits[: (n_info + 31) // 32]
+
+
+def quantize_i8(llr, scale: float, out=None, stream=None):
+    """int8 soft values: saturate_127(round_half_even(fl32(llr * scale)))."""
+    torch = _torch()
+    if llr.dtype != torch.float32 or not llr.is_cuda:
+        raise ValueError("llr must be a float32 device tensor")
+    llr = llr.contiguous()
+    if out is None:
+        out = torch.empty(llr.shape, dtype=torch.int8, device=llr.device)
+    st = _capi.load().mivit_quantize_i8(_dptr(llr), _dptr(out), llr.numel(), float(scale),
+                                        _stream_handle(stream))
+    _capi.check(st, "mivit_quantize_i8")
+    return out
+
+
+def unpack_bits(words: np.ndarray, n: int) -> np.ndarray:
+    """Host helper: packed LSB-first words [..., W] -> uint8 bits [..., n]."""
+    w = np.ascontiguousarray(words).view(np.uint32)
+    b = ((w[..., :, None] >> np.arange(32, dtype=np.uint32)) & 1).astype(np.uint8)
+    return b.reshape(w.shape[:-1] + (w.shape[-1] * 32,))[..., :n]
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class ViterbiDecode(torch.autograd.Function):
+        """(bits, metric) = decode(llr); d(metric)/d(llr) from the HIP backward
+        kernel (the decoded codeword in +-1 form times the incoming gradient).
+        Bits are not differentiable."""
+
+        @staticmethod
+        def forward(ctx, llr, code, n_info, terminated=True):
+            code = _as_code(code)
+            F = llr.shape[0]
+            key = ("u", code, F, n_info, terminated, "f32", 2, llr.device.index)
+            plan = _cached_plan(key, lambda: Plan([code], uniform_frames(code, F, n_info, terminated),
+                                                  "f32", 2))
+            bits, metric, _ = plan.decode(llr.contiguous())
+            ctx.plan = plan
+            ctx.save_for_backward(bits)
+            ctx.shape = llr.shape
+            wpf = (n_info + 31) // 32
+            out_bits = bits[: F * wpf].view(F, wpf)
+            ctx.mark_non_differentiable(out_bits)
+            return out_bits, metric[:F].clone()
+
+        @staticmethod
+        def backward(ctx, g_bits, g_metric):
+            (bits,) = ctx.saved_tensors
+            grad = torch.empty(ctx.shape, dtype=torch.float32, device=bits.device)
+            ctx.plan.decode_grad(bits, g_metric.contiguous().float(), grad)
+            return grad, None, None, None
+
+    return ViterbiDecode
+
+
+class _LazyAutograd:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _LazyAutograd._cls is None:
+            _LazyAutograd._cls = _make_autograd()
+        return getattr(_LazyAutograd._cls, name)
+
+
+ViterbiDecode = _LazyAutograd()

@@ -1,0 +1,354 @@
+// C ABI of the Viterbi decoder library: argument validation, plan building
+// (chunking of long frames into overlapping windows, §III), work ordering,
+// device memory ownership and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/mivit.h"
+#include "mivit_device.h"
+
+namespace mivit {
+hipError_t launch_fwd(int radix, int nsl, bool is_int, const DevCode* codes, const Item* items,
+                      int n_items, const void* llr, uint64_t* surv, void* metric,
+                      int32_t* end_out, int32_t* item_end, hipStream_t st);
+hipError_t launch_tb(int radix, const DevCode* codes, const Item* items, int n_items,
+                     const uint64_t* surv, const int32_t* item_end, uint32_t* bits,
+                     hipStream_t st);
+hipError_t launch_grad(const DevCode* codes, const GradFrame* frames, int n_frames,
+                       int max_stages, const uint32_t* bits, const float* gm, float* grad,
+                       hipStream_t st);
+hipError_t launch_quant(const float* x, int8_t* q, int64_t n, float scale, hipStream_t st);
+}  // namespace mivit
+
+using namespace mivit;
+
+struct PlanGroup {
+  int nsl;    // states per lane of the forward kernel
+  int first;  // first item of the group
+  int count;
+};
+
+struct mivit_plan {
+  int device = 0;
+  int dtype = MIVIT_F32;
+  int radix = 2;
+  int n_frames = 0;
+  bool grad_ok = false;
+  int grad_max_stages = 0;
+  int64_t total_stages = 0;
+  int64_t surv_words = 0;
+  std::vector<Item> items;
+  std::vector<PlanGroup> groups;
+  DevCode* d_codes = nullptr;
+  Item* d_items = nullptr;
+  int32_t* d_item_end = nullptr;
+  uint64_t* d_surv = nullptr;
+  GradFrame* d_gframes = nullptr;
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+mivit_status check_code(const mivit_code& c) {
+  if (c.K < 3 || c.K > kMaxK || c.beta < 2 || c.beta > 4) return MIVIT_EINVAL;
+  for (int b = 0; b < c.beta; ++b) {
+    if (c.gen[b] == 0 || c.gen[b] >= (1u << c.K)) return MIVIT_EINVAL;
+    // premise of the branch-output corollary (§IV): MSB and LSB taps set
+    if (!((c.gen[b] >> (c.K - 1)) & 1u) || !(c.gen[b] & 1u)) return MIVIT_EUNSUPPORTED;
+  }
+  return MIVIT_OK;
+}
+
+int nsl_of(int K) { return K <= 7 ? 1 : (1 << (K - 1)) / 64; }
+
+void free_plan(mivit_plan* p) {
+  if (!p) return;
+  (void)hipFree(p->d_codes);
+  (void)hipFree(p->d_items);
+  (void)hipFree(p->d_item_end);
+  (void)hipFree(p->d_surv);
+  (void)hipFree(p->d_gframes);
+  delete p;
+}
+
+template <typename T>
+hipError_t upload(T** dst, const T* src, size_t n) {
+  *dst = nullptr;
+  if (n == 0) return hipSuccess;
+  hipError_t e = hipMalloc((void**)dst, n * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mivit_strerror(mivit_status s) {
+  switch (s) {
+    case MIVIT_OK: return "ok";
+    case MIVIT_EINVAL: return "invalid argument";
+    case MIVIT_ENOMEM: return "out of memory";
+    case MIVIT_EHIP: return "HIP runtime error";
+    case MIVIT_EUNSUPPORTED: return "unsupported request";
+  }
+  return "unknown status";
+}
+
+const char* mivit_version(void) { return "mivit 0.1 (gfx950)"; }
+
+mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_t n_codes,
+                               const mivit_frame* frames, int32_t n_frames,
+                               const mivit_opts* opts) {
+  if (!out) return MIVIT_EINVAL;
+  *out = nullptr;
+  if (!codes || n_codes <= 0 || n_codes > 32767 || n_frames < 0 || (n_frames > 0 && !frames))
+    return MIVIT_EINVAL;
+  mivit_opts o;
+  std::memset(&o, 0, sizeof o);
+  if (opts) o = *opts;
+  if (o.dtype != MIVIT_F32 && o.dtype != MIVIT_I8) return MIVIT_EINVAL;
+  if (o.radix != 0 && o.radix != 2 && o.radix != 4) return MIVIT_EINVAL;
+  if (o.radix == 4 && o.dtype != MIVIT_I8) return MIVIT_EINVAL;
+  if (o.chunk < 0 || o.overlap < 0 || (o.chunk > 0 && o.chunk % 32 != 0)) return MIVIT_EINVAL;
+  for (int c = 0; c < n_codes; ++c) {
+    mivit_status s = check_code(codes[c]);
+    if (s != MIVIT_OK) return s;
+  }
+  // frames: ranges and non-overlapping outputs
+  std::vector<std::pair<int64_t, int64_t>> words;
+  words.reserve(n_frames);
+  for (int f = 0; f < n_frames; ++f) {
+    const mivit_frame& fr = frames[f];
+    if (fr.code < 0 || fr.code >= n_codes) return MIVIT_EINVAL;
+    if (fr.n_stages < 0 || fr.out_begin < 0 || fr.n_out < 0) return MIVIT_EINVAL;
+    if ((int64_t)fr.out_begin + fr.n_out > fr.n_stages) return MIVIT_EINVAL;
+    if (fr.llr_offset < 0 || fr.bit_offset < 0 || (fr.bit_offset & 31)) return MIVIT_EINVAL;
+    if (fr.flags & ~(MIVIT_START_KNOWN | MIVIT_END_ZERO)) return MIVIT_EINVAL;
+    if (o.chunk > 0 && fr.n_stages > o.chunk && fr.out_begin != 0) return MIVIT_EUNSUPPORTED;
+    if (fr.n_out > 0) words.push_back({fr.bit_offset >> 5, (fr.bit_offset + fr.n_out + 31) >> 5});
+  }
+  std::sort(words.begin(), words.end());
+  for (size_t k = 1; k < words.size(); ++k)
+    if (words[k].first < words[k - 1].second) return MIVIT_EINVAL;
+
+  mivit_plan* p = nullptr;
+  try {
+    p = new mivit_plan();
+    if (hipGetDevice(&p->device) != hipSuccess) {
+      delete p;
+      return MIVIT_EHIP;
+    }
+    p->dtype = o.dtype;
+    p->radix = o.radix == 0 ? 2 : o.radix;
+    p->n_frames = n_frames;
+    // expand frames into work items
+    std::vector<Item> items;
+    bool chunked_any = false;
+    bool tail_ok = true;
+    for (int f = 0; f < n_frames; ++f) {
+      const mivit_frame& fr = frames[f];
+      const mivit_code& c = codes[fr.code];
+      const int S = fr.n_stages;
+      if (fr.out_begin != 0) tail_ok = false;
+      if (o.chunk > 0 && S > o.chunk) {
+        chunked_any = true;
+        for (int c0 = 0; c0 < S; c0 += o.chunk) {
+          const int c1 = std::min(S, c0 + o.chunk);
+          const int w0 = std::max(0, c0 - o.overlap);
+          const int w1 = std::min(S, c1 + o.overlap);
+          const bool last = c1 == S;
+          const int e1 = std::min(c1, fr.n_out);
+          const int nout = e1 > c0 ? e1 - c0 : 0;
+          if (nout == 0 && !last) continue;
+          Item it;
+          std::memset(&it, 0, sizeof it);
+          it.llr_off = fr.llr_offset + (int64_t)w0 * c.beta;
+          it.bit_off = fr.bit_offset + c0;
+          it.n_stages = w1 - w0;
+          it.out_begin = c0 - w0;
+          it.n_out = nout;
+          it.code = fr.code;
+          it.start_known = (w0 == 0) && (fr.flags & MIVIT_START_KNOWN);
+          it.end_state = (last && (fr.flags & MIVIT_END_ZERO)) ? 0 : -1;
+          it.frame = last ? f : -1;
+          items.push_back(it);
+        }
+      } else {
+        Item it;
+        std::memset(&it, 0, sizeof it);
+        it.llr_off = fr.llr_offset;
+        it.bit_off = fr.bit_offset;
+        it.n_stages = S;
+        it.out_begin = fr.out_begin;
+        it.n_out = fr.n_out;
+        it.code = fr.code;
+        it.start_known = (fr.flags & MIVIT_START_KNOWN) ? 1 : 0;
+        it.end_state = (fr.flags & MIVIT_END_ZERO) ? 0 : -1;
+        it.frame = f;
+        items.push_back(it);
+      }
+    }
+    // group by forward-kernel shape, longest first inside a group
+    std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) {
+      const int na = nsl_of(codes[a.code].K), nb = nsl_of(codes[b.code].K);
+      if (na != nb) return na > nb;
+      return a.n_stages > b.n_stages;
+    });
+    int64_t words_total = 0;
+    for (size_t k = 0; k < items.size(); ++k) {
+      Item& it = items[k];
+      it.slot = (int32_t)k;
+      it.surv_off = words_total;
+      words_total += (int64_t)it.n_stages * words_per_stage(codes[it.code].K);
+      p->total_stages += it.n_stages;
+      const int nsl = nsl_of(codes[it.code].K);
+      if (p->groups.empty() || p->groups.back().nsl != nsl)
+        p->groups.push_back({nsl, (int)k, 0});
+      p->groups.back().count++;
+    }
+    p->surv_words = words_total;
+    p->items = items;
+
+    std::vector<DevCode> dc(n_codes);
+    for (int c = 0; c < n_codes; ++c) {
+      dc[c].K = codes[c].K;
+      dc[c].beta = codes[c].beta;
+      for (int b = 0; b < 4; ++b) dc[c].gen[b] = b < codes[c].beta ? codes[c].gen[b] : 0;
+    }
+    hipError_t e = upload(&p->d_codes, dc.data(), dc.size());
+    if (e == hipSuccess) e = upload(&p->d_items, items.data(), items.size());
+    if (e == hipSuccess && !items.empty())
+      e = hipMalloc((void**)&p->d_item_end, items.size() * sizeof(int32_t));
+    if (e == hipSuccess && words_total > 0)
+      e = hipMalloc((void**)&p->d_surv, (size_t)words_total * sizeof(uint64_t));
+    // gradient support: whole frames whose bits cover every stage but a zero tail
+    if (e == hipSuccess && !chunked_any && tail_ok) {
+      std::vector<GradFrame> gf(n_frames);
+      bool ok = true;
+      for (int f = 0; f < n_frames && ok; ++f) {
+        const mivit_frame& fr = frames[f];
+        const int K = codes[fr.code].K;
+        const bool term = (fr.flags & MIVIT_END_ZERO) && (fr.flags & MIVIT_START_KNOWN);
+        if (!(fr.n_out == fr.n_stages || (term && fr.n_out + K - 1 == fr.n_stages))) ok = false;
+        gf[f].llr_off = fr.llr_offset;
+        gf[f].bit_off = fr.bit_offset;
+        gf[f].n_stages = fr.n_stages;
+        gf[f].n_out = fr.n_out;
+        gf[f].code = fr.code;
+        gf[f].pad = 0;
+        p->grad_max_stages = std::max(p->grad_max_stages, fr.n_stages);
+      }
+      if (ok) {
+        e = upload(&p->d_gframes, gf.data(), gf.size());
+        p->grad_ok = (e == hipSuccess);
+      }
+    }
+    if (e != hipSuccess) {
+      mivit_status s = (e == hipErrorOutOfMemory) ? MIVIT_ENOMEM : MIVIT_EHIP;
+      free_plan(p);
+      return s;
+    }
+  } catch (const std::bad_alloc&) {
+    free_plan(p);
+    return MIVIT_ENOMEM;
+  } catch (...) {
+    free_plan(p);
+    return MIVIT_EHIP;
+  }
+  *out = p;
+  return MIVIT_OK;
+}
+
+mivit_status mivit_forward(mivit_plan* p, const void* llr, void* metric, int32_t* end_state,
+                           void* stream) {
+  if (!p) return MIVIT_EINVAL;
+  if (p->items.empty()) return MIVIT_OK;
+  if (!llr) return MIVIT_EINVAL;
+  DeviceGuard guard(p->device);
+  hipStream_t st = (hipStream_t)stream;
+  const bool is_int = p->dtype == MIVIT_I8;
+  for (const PlanGroup& g : p->groups) {
+    hipError_t e = launch_fwd(p->radix, g.nsl, is_int, p->d_codes, p->d_items + g.first, g.count,
+                              llr, p->d_surv, metric, end_state, p->d_item_end, st);
+    if (e != hipSuccess) return MIVIT_EHIP;
+  }
+  return MIVIT_OK;
+}
+
+mivit_status mivit_traceback(mivit_plan* p, uint32_t* bits, void* stream) {
+  if (!p) return MIVIT_EINVAL;
+  if (p->items.empty()) return MIVIT_OK;
+  if (!bits) return MIVIT_EINVAL;
+  DeviceGuard guard(p->device);
+  hipError_t e = launch_tb(p->radix, p->d_codes, p->d_items, (int)p->items.size(), p->d_surv,
+                           p->d_item_end, bits, (hipStream_t)stream);
+  return e == hipSuccess ? MIVIT_OK : MIVIT_EHIP;
+}
+
+mivit_status mivit_decode(mivit_plan* p, const void* llr, uint32_t* bits, void* metric,
+                          int32_t* end_state, void* stream) {
+  if (!p) return MIVIT_EINVAL;
+  if (p->items.empty()) return MIVIT_OK;
+  if (!llr || !bits) return MIVIT_EINVAL;
+  mivit_status s = mivit_forward(p, llr, metric, end_state, stream);
+  if (s != MIVIT_OK) return s;
+  return mivit_traceback(p, bits, stream);
+}
+
+mivit_status mivit_decode_grad(mivit_plan* p, const uint32_t* bits, const float* grad_metric,
+                               float* grad_llr, void* stream) {
+  if (!p) return MIVIT_EINVAL;
+  if (!p->grad_ok) return MIVIT_EUNSUPPORTED;
+  if (p->n_frames == 0) return MIVIT_OK;
+  if (!bits || !grad_metric || !grad_llr) return MIVIT_EINVAL;
+  DeviceGuard guard(p->device);
+  hipError_t e = launch_grad(p->d_codes, p->d_gframes, p->n_frames, p->grad_max_stages, bits,
+                             grad_metric, grad_llr, (hipStream_t)stream);
+  return e == hipSuccess ? MIVIT_OK : MIVIT_EHIP;
+}
+
+mivit_status mivit_plan_destroy(mivit_plan* p) {
+  if (!p) return MIVIT_EINVAL;
+  {
+    DeviceGuard guard(p->device);
+    (void)hipDeviceSynchronize();
+  }
+  free_plan(p);
+  return MIVIT_OK;
+}
+
+mivit_status mivit_plan_get_info(const mivit_plan* p, mivit_plan_info* info) {
+  if (!p || !info) return MIVIT_EINVAL;
+  info->n_items = (int64_t)p->items.size();
+  info->survivor_bytes = p->surv_words * 8;
+  info->total_stages = p->total_stages;
+  info->radix = p->radix;
+  info->dtype = p->dtype;
+  return MIVIT_OK;
+}
+
+mivit_status mivit_quantize_i8(const float* llr, int8_t* q, int64_t n, float scale,
+                               void* stream) {
+  if (n < 0 || (n > 0 && (!llr || !q))) return MIVIT_EINVAL;
+  if (!(scale > 0.0f) || scale > 3.0e38f) return MIVIT_EINVAL;
+  hipError_t e = launch_quant(llr, q, n, scale, (hipStream_t)stream);
+  return e == hipSuccess ? MIVIT_OK : MIVIT_EHIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,491 @@
+// Kernels of the soft-decision Viterbi decoder for gfx950 (wave64).
+//
+// Paper: arXiv 2011.13579.  The forward procedure evaluates Eq. (BM) and
+// Eq. (PM)/(SP0) of §II-B stage by stage (Algorithm 1); the traceback walks
+// the stored decisions backwards (Algorithm 2).  The radix-4 forward kernel
+// evaluates Eqs. (radix4:BM)/(radix4:PM)/(radix4:SP0) of §VIII-A, two stages
+// per iteration, with the left/right state maps of Eq. (radix4:S).
+//
+// Mapping (one wavefront per trellis): lane l holds states l + 64*s for the
+// slots s < NSL (NSL = 2^(K-1)/64 for K > 7, else 1).  The branch metrics of
+// a block of 64 stages are tabulated in LDS, one stage per lane, for every
+// beta-bit branch output pattern.  Path metrics are exchanged through LDS.
+// Decisions of 64 states are packed by a wave ballot into one 64-bit word
+// per stage and slot (bit j = 1 when state j kept its higher-index previous
+// state), collected 64 stages at a time across the lanes and written with one
+// coalesced store.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mivit_device.h"
+
+namespace mivit {
+
+__device__ __forceinline__ int parity32(uint32_t x) { return __popc(x) & 1; }
+
+// beta-bit output of the branch leaving state i on input u (encoder, §II-A):
+// register = (u << (K-1)) | i, output bit b = parity(gen[b] & register).
+__device__ __forceinline__ int branch_out(const DevCode& c, int i, int u) {
+  uint32_t reg = ((uint32_t)u << (c.K - 1)) | (uint32_t)i;
+  int w = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+    if (b < c.beta) w |= parity32(c.gen[b] & reg) << b;
+  return w;
+}
+
+template <bool INT>
+struct Arith;
+template <>
+struct Arith<false> {
+  using T = float;
+  using In = float;
+  __device__ static T unreachable() { return -__builtin_inff(); }
+};
+template <>
+struct Arith<true> {
+  using T = int;
+  using In = int8_t;
+  // Finite stand-in for minus infinity: every reachable metric stays above
+  // -2^28 and the gap never closes within the K-1 stages before all states
+  // become reachable.
+  __device__ static T unreachable() { return -(1 << 29); }
+};
+
+constexpr int kBlk = 64;  // stages per staged block
+
+// Eq. (BM) for every beta-bit output pattern p of stage t0+lane:
+// bmt[lane][p] = sum_b (-1)^{p_b} l[b], summed in increasing b from zero.
+template <bool INT>
+__device__ __forceinline__ void fill_bm_table(const DevCode& c, const typename Arith<INT>::In* llr,
+                                              int64_t off, int t0, int nst,
+                                              typename Arith<INT>::T (*bmt)[16]) {
+  using T = typename Arith<INT>::T;
+  const int lane = threadIdx.x;
+  if (lane < nst) {
+    T l[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      l[b] = b < c.beta ? (T)llr[off + (int64_t)(t0 + lane) * c.beta + b] : (T)0;
+    for (int p = 0; p < (1 << c.beta); ++p) {
+      T v = (T)0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (b < c.beta) v += ((p >> b) & 1) ? -l[b] : l[b];
+      bmt[lane][p] = v;
+    }
+  }
+}
+
+// Final state and metric of an item (shared by both forward kernels).
+template <bool INT, int NSL>
+__device__ __forceinline__ void finish_item(const Item& it, int NS, const typename Arith<INT>::T* pm,
+                                            const bool* act, typename Arith<INT>::T* xpm,
+                                            int64_t offset, void* metric, int32_t* end_out,
+                                            int32_t* item_end) {
+  const int lane = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < NSL; ++s)
+    if (act[s]) xpm[lane + 64 * s] = pm[s];
+  __syncthreads();
+  if (lane == 0) {
+    int js = it.end_state;
+    if (js < 0) {
+      js = 0;
+      for (int j = 1; j < NS; ++j)
+        if (xpm[j] > xpm[js]) js = j;
+    }
+    item_end[it.slot] = js;
+    if (it.frame >= 0) {
+      if (end_out) end_out[it.frame] = js;
+      if (metric) {
+        if constexpr (INT)
+          ((int64_t*)metric)[it.frame] = (int64_t)xpm[js] + offset;
+        else
+          ((float*)metric)[it.frame] = (float)xpm[js];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Radix-2 forward procedure.
+// ---------------------------------------------------------------------------
+template <int NSL, bool INT>
+__global__ __launch_bounds__(64) void k_fwd_r2(const DevCode* __restrict__ codes,
+                                               const Item* __restrict__ items,
+                                               const void* __restrict__ llr_v,
+                                               uint64_t* __restrict__ surv, void* metric,
+                                               int32_t* end_out, int32_t* item_end) {
+  using T = typename Arith<INT>::T;
+  using In = typename Arith<INT>::In;
+  const In* llr = (const In*)llr_v;
+  const Item it = items[blockIdx.x];
+  const DevCode c = codes[it.code];
+  const int K = c.K, NS = 1 << (K - 1), half = NS >> 1;
+  const int lane = threadIdx.x;
+  __shared__ T xpm[kMaxStates];
+  __shared__ T bmt[kBlk][16];
+
+  int iLo[NSL], pLo[NSL], pHi[NSL];
+  bool act[NSL];
+  T pm[NSL];
+  uint32_t svlo[NSL], svhi[NSL];
+#pragma unroll
+  for (int s = 0; s < NSL; ++s) {
+    const int j = lane + 64 * s;
+    act[s] = j < NS;
+    const int jj = act[s] ? j : 0;
+    const int u = jj >> (K - 2), f = jj & (half - 1);
+    // previous states of j (Eq. (radix2:S)): 2f and 2f+1, both on input u
+    iLo[s] = 2 * f;
+    pLo[s] = branch_out(c, 2 * f, u);
+    pHi[s] = branch_out(c, 2 * f + 1, u);
+    pm[s] = (it.start_known && j != 0) ? Arith<INT>::unreachable() : (T)0;
+    svlo[s] = svhi[s] = 0;
+  }
+  int64_t offset = 0;  // integer metrics: total subtracted by renormalisation
+  const int S = it.n_stages;
+  for (int t0 = 0; t0 < S; t0 += kBlk) {
+    const int nst = min(kBlk, S - t0);
+    fill_bm_table<INT>(c, llr, it.llr_off, t0, nst, bmt);
+    if constexpr (INT) {
+      if (t0 > 0) {
+        // subtract the metric of state 0 (held by lane 0, slot 0) from all
+        const T ref = __builtin_amdgcn_readfirstlane(pm[0]);
+#pragma unroll
+        for (int s = 0; s < NSL; ++s) pm[s] -= ref;
+        offset += ref;
+      }
+    }
+    __syncthreads();
+    for (int tt = 0; tt < nst; ++tt) {
+#pragma unroll
+      for (int s = 0; s < NSL; ++s)
+        if (act[s]) xpm[lane + 64 * s] = pm[s];
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < NSL; ++s) {
+        const T a = xpm[iLo[s]], b = xpm[iLo[s] + 1];
+        const T cLo = a + bmt[tt][pLo[s]];
+        const T cHi = b + bmt[tt][pHi[s]];
+        const bool d = act[s] && (cHi > cLo);  // strict: a tie keeps 2f
+        pm[s] = d ? cHi : cLo;
+        const uint64_t m = __ballot(d);
+        if (lane == tt) {
+          svlo[s] = (uint32_t)m;
+          svhi[s] = (uint32_t)(m >> 32);
+        }
+      }
+      __syncthreads();
+    }
+    if (lane < nst) {
+      uint64_t* dst = surv + it.surv_off + (int64_t)(t0 + lane) * NSL;
+#pragma unroll
+      for (int s = 0; s < NSL; ++s) dst[s] = ((uint64_t)svhi[s] << 32) | svlo[s];
+    }
+  }
+  finish_item<INT, NSL>(it, NS, pm, act, xpm, offset, metric, end_out, item_end);
+}
+
+// ---------------------------------------------------------------------------
+// Radix-4 forward procedure (exact integers).  Right state j of dragonfly
+// f = j mod 2^(K-3) takes the best of the four left states 4f+y (smallest y
+// on ties); the super-branch i -> m -> j has middle state
+// m = (bit K-3 of j) << (K-2) | (i >> 1).  A frame with an odd number of
+// stages starts with one radix-2 stage.  Decision words: for the pair of
+// stages (t, t+1), word t holds bit 0 of y and word t+1 holds bit 1.
+// ---------------------------------------------------------------------------
+template <int NSL>
+__global__ __launch_bounds__(64) void k_fwd_r4(const DevCode* __restrict__ codes,
+                                               const Item* __restrict__ items,
+                                               const void* __restrict__ llr_v,
+                                               uint64_t* __restrict__ surv, void* metric,
+                                               int32_t* end_out, int32_t* item_end) {
+  using T = int;
+  const int8_t* llr = (const int8_t*)llr_v;
+  const Item it = items[blockIdx.x];
+  const DevCode c = codes[it.code];
+  const int K = c.K, NS = 1 << (K - 1), half = NS >> 1, quarter = NS >> 2;
+  const int lane = threadIdx.x;
+  __shared__ T xpm[kMaxStates];
+  __shared__ T bmt[kBlk][16];
+
+  int iLo[NSL], pLo[NSL], pHi[NSL], base[NSL];
+  uint8_t q1[NSL][4], q2[NSL][4];
+  bool act[NSL];
+  T pm[NSL];
+  uint32_t svlo[NSL], svhi[NSL];
+#pragma unroll
+  for (int s = 0; s < NSL; ++s) {
+    const int j = lane + 64 * s;
+    act[s] = j < NS;
+    const int jj = act[s] ? j : 0;
+    const int u = jj >> (K - 2), f2 = jj & (half - 1);
+    iLo[s] = 2 * f2;
+    pLo[s] = branch_out(c, 2 * f2, u);
+    pHi[s] = branch_out(c, 2 * f2 + 1, u);
+    const int f = jj & (quarter - 1);
+    const int u2 = jj >> (K - 2), u1 = (jj >> (K - 3)) & 1;
+    base[s] = 4 * f;
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int i = 4 * f + y;
+      const int m = (u1 << (K - 2)) | (i >> 1);
+      q1[s][y] = (uint8_t)branch_out(c, i, u1);
+      q2[s][y] = (uint8_t)branch_out(c, m, u2);
+    }
+    pm[s] = (it.start_known && j != 0) ? Arith<true>::unreachable() : 0;
+    svlo[s] = svhi[s] = 0;
+  }
+  int64_t offset = 0;
+  const int S = it.n_stages;
+  const int lead = S & 1;
+  if (lead) {
+    // one radix-2 stage at t = 0
+    fill_bm_table<true>(c, llr, it.llr_off, 0, 1, bmt);
+#pragma unroll
+    for (int s = 0; s < NSL; ++s)
+      if (act[s]) xpm[lane + 64 * s] = pm[s];
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NSL; ++s) {
+      const T a = xpm[iLo[s]], b = xpm[iLo[s] + 1];
+      const T cLo = a + bmt[0][pLo[s]];
+      const T cHi = b + bmt[0][pHi[s]];
+      const bool d = act[s] && (cHi > cLo);
+      pm[s] = d ? cHi : cLo;
+      const uint64_t m = __ballot(d);
+      if (lane == 0) surv[it.surv_off + s] = m;
+    }
+    __syncthreads();
+  }
+  for (int t0 = lead; t0 < S; t0 += kBlk) {
+    const int nst = min(kBlk, S - t0);  // even
+    fill_bm_table<true>(c, llr, it.llr_off, t0, nst, bmt);
+    if (t0 > lead) {
+      const T ref = __builtin_amdgcn_readfirstlane(pm[0]);
+#pragma unroll
+      for (int s = 0; s < NSL; ++s) pm[s] -= ref;
+      offset += ref;
+    }
+    __syncthreads();
+    for (int tt = 0; tt < nst; tt += 2) {
+#pragma unroll
+      for (int s = 0; s < NSL; ++s)
+        if (act[s]) xpm[lane + 64 * s] = pm[s];
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < NSL; ++s) {
+        T best = 0;
+        int yb = 0;
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          // Eq. (radix4:BM): the 2*beta soft values of the two stages
+          const T cand = xpm[base[s] + y] + bmt[tt][q1[s][y]] + bmt[tt + 1][q2[s][y]];
+          if (y == 0 || cand > best) {
+            best = cand;
+            yb = y;
+          }
+        }
+        pm[s] = best;
+        const uint64_t m0 = __ballot(act[s] && (yb & 1));
+        const uint64_t m1 = __ballot(act[s] && (yb >> 1));
+        if (lane == tt) {
+          svlo[s] = (uint32_t)m0;
+          svhi[s] = (uint32_t)(m0 >> 32);
+        }
+        if (lane == tt + 1) {
+          svlo[s] = (uint32_t)m1;
+          svhi[s] = (uint32_t)(m1 >> 32);
+        }
+      }
+      __syncthreads();
+    }
+    if (lane < nst) {
+      uint64_t* dst = surv + it.surv_off + (int64_t)(t0 + lane) * NSL;
+#pragma unroll
+      for (int s = 0; s < NSL; ++s) dst[s] = ((uint64_t)svhi[s] << 32) | svlo[s];
+    }
+  }
+  finish_item<true, NSL>(it, NS, pm, act, xpm, offset, metric, end_out, item_end);
+}
+
+// ---------------------------------------------------------------------------
+// Traceback (Algorithm 2), one lane per item.
+// ---------------------------------------------------------------------------
+struct BitSink {
+  uint32_t word = 0;
+  // Emit the decoded bit of stage t (called with t decreasing).
+  __device__ __forceinline__ void put(const Item& it, int t, int u, uint32_t* bits) {
+    const int k = t - it.out_begin;
+    if (k >= 0 && k < it.n_out) {
+      word |= (uint32_t)u << (k & 31);
+      if ((k & 31) == 0) {
+        bits[(it.bit_off + k) >> 5] = word;
+        word = 0;
+      }
+    }
+  }
+};
+
+__global__ __launch_bounds__(64) void k_tb_r2(const DevCode* __restrict__ codes,
+                                              const Item* __restrict__ items, int n_items,
+                                              const uint64_t* __restrict__ surv,
+                                              const int32_t* __restrict__ item_end,
+                                              uint32_t* __restrict__ bits) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n_items) return;
+  const Item it = items[idx];
+  const DevCode c = codes[it.code];
+  const int K = c.K, NS = 1 << (K - 1), W = words_per_stage(K);
+  const uint64_t* sv = surv + it.surv_off;
+  int j = item_end[it.slot];
+  BitSink sink;
+  for (int t = it.n_stages - 1; t >= 0; --t) {
+    const uint64_t w = sv[(int64_t)t * W + (j >> 6)];
+    const int d = (int)((w >> (j & 63)) & 1);
+    sink.put(it, t, j >> (K - 2), bits);  // alpha_in of the branch into j
+    j = ((j << 1) | d) & (NS - 1);
+  }
+}
+
+__global__ __launch_bounds__(64) void k_tb_r4(const DevCode* __restrict__ codes,
+                                              const Item* __restrict__ items, int n_items,
+                                              const uint64_t* __restrict__ surv,
+                                              const int32_t* __restrict__ item_end,
+                                              uint32_t* __restrict__ bits) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n_items) return;
+  const Item it = items[idx];
+  const DevCode c = codes[it.code];
+  const int K = c.K, NS = 1 << (K - 1), W = words_per_stage(K);
+  const uint64_t* sv = surv + it.surv_off;
+  const int S = it.n_stages, lead = S & 1;
+  int j = item_end[it.slot];
+  BitSink sink;
+  for (int t = S - 2; t >= lead; t -= 2) {
+    const int wi = j >> 6, sh = j & 63;
+    const int y = (int)((sv[(int64_t)t * W + wi] >> sh) & 1) |
+                  ((int)((sv[(int64_t)(t + 1) * W + wi] >> sh) & 1) << 1);
+    sink.put(it, t + 1, j >> (K - 2), bits);
+    sink.put(it, t, (j >> (K - 3)) & 1, bits);
+    j = 4 * (j & ((NS >> 2) - 1)) + y;
+  }
+  if (lead) {
+    const int d = (int)((sv[j >> 6] >> (j & 63)) & 1);
+    sink.put(it, 0, j >> (K - 2), bits);
+    j = ((j << 1) | d) & (NS - 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Backward of the best path metric: grad = g * (-1)^{coded bit of the
+// decoded path}, the decoded bits re-encoded with the encoder of §II-A.
+// grid: x over stages (256 per block), y over frames.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_grad(const DevCode* __restrict__ codes,
+                                              const GradFrame* __restrict__ frames,
+                                              const uint32_t* __restrict__ bits,
+                                              const float* __restrict__ gm,
+                                              float* __restrict__ grad) {
+  const GradFrame fr = frames[blockIdx.y];
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= fr.n_stages) return;
+  const DevCode c = codes[fr.code];
+  const int K = c.K;
+  uint32_t reg = 0;
+  for (int k = 0; k < K; ++k) {
+    const int tt = t - (K - 1 - k);  // register bit k holds the input K-1-k stages back
+    int u = 0;
+    if (tt >= 0 && tt < fr.n_out) {
+      const int64_t bi = fr.bit_off + tt;
+      u = (int)((bits[bi >> 5] >> (bi & 31)) & 1);
+    }
+    reg |= (uint32_t)u << k;
+  }
+  const float g = gm[blockIdx.y];
+  float* dst = grad + fr.llr_off + (int64_t)t * c.beta;
+  for (int b = 0; b < c.beta; ++b) dst[b] = parity32(c.gen[b] & reg) ? -g : g;
+}
+
+// ---------------------------------------------------------------------------
+// int8 quantiser: saturate_127(round_half_even(fl32(x * scale))), NaN -> 0.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_quant_i8(const float* __restrict__ x,
+                                                  int8_t* __restrict__ q, int64_t n,
+                                                  float scale) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+    float r = __builtin_rintf(x[k] * scale);
+    r = r > 127.0f ? 127.0f : r;
+    r = r < -127.0f ? -127.0f : r;
+    if (r != r) r = 0.0f;
+    q[k] = (int8_t)(int)r;
+  }
+}
+
+// Host-side launch helpers (called by the C ABI layer).
+hipError_t launch_fwd(int radix, int nsl, bool is_int, const DevCode* codes, const Item* items,
+                      int n_items, const void* llr, uint64_t* surv, void* metric,
+                      int32_t* end_out, int32_t* item_end, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  dim3 g(n_items), b(64);
+#define MV_FWD2(N, I) hipLaunchKernelGGL((k_fwd_r2<N, I>), g, b, 0, st, codes, items, llr, surv, metric, end_out, item_end)
+#define MV_FWD4(N) hipLaunchKernelGGL((k_fwd_r4<N>), g, b, 0, st, codes, items, llr, surv, metric, end_out, item_end)
+  if (radix == 4) {
+    switch (nsl) {
+      case 1: MV_FWD4(1); break;
+      case 2: MV_FWD4(2); break;
+      case 4: MV_FWD4(4); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (nsl * 2 + (is_int ? 1 : 0)) {
+      case 2: MV_FWD2(1, false); break;
+      case 3: MV_FWD2(1, true); break;
+      case 4: MV_FWD2(2, false); break;
+      case 5: MV_FWD2(2, true); break;
+      case 8: MV_FWD2(4, false); break;
+      case 9: MV_FWD2(4, true); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+#undef MV_FWD2
+#undef MV_FWD4
+  return hipGetLastError();
+}
+
+hipError_t launch_tb(int radix, const DevCode* codes, const Item* items, int n_items,
+                     const uint64_t* surv, const int32_t* item_end, uint32_t* bits,
+                     hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  dim3 g((n_items + 63) / 64), b(64);
+  if (radix == 4)
+    hipLaunchKernelGGL(k_tb_r4, g, b, 0, st, codes, items, n_items, surv, item_end, bits);
+  else
+    hipLaunchKernelGGL(k_tb_r2, g, b, 0, st, codes, items, n_items, surv, item_end, bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad(const DevCode* codes, const GradFrame* frames, int n_frames,
+                       int max_stages, const uint32_t* bits, const float* gm, float* grad,
+                       hipStream_t st) {
+  if (n_frames <= 0 || max_stages <= 0) return hipSuccess;
+  for (int f0 = 0; f0 < n_frames; f0 += 65535) {
+    const int nf = n_frames - f0 < 65535 ? n_frames - f0 : 65535;
+    dim3 g((max_stages + 255) / 256, nf), b(256);
+    hipLaunchKernelGGL(k_grad, g, b, 0, st, codes, frames + f0, bits, gm + f0, grad);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_quant(const float* x, int8_t* q, int64_t n, float scale, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_quant_i8, dim3((unsigned)blocks), dim3(256), 0, st, x, q, n, scale);
+  return hipGetLastError();
+}
+
+}  // namespace mivit

@@ -1,0 +1,124 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects invalid arguments before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2011_13579_amd import _capi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mivit.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(_capi.LIB_PATH),
+                                reason="libmivit.so not built")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(mivit_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_matches_binding():
+    assert sorted(_capi.EXPORTS) == declared_symbols()
+
+
+def test_exports_every_symbol():
+    lib = ctypes.CDLL(_capi.LIB_PATH)
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts():
+    assert ctypes.sizeof(_capi.Code) == 24
+    assert ctypes.sizeof(_capi.Frame) == 32
+    assert ctypes.sizeof(_capi.Opts) == 32
+    text = open(HEADER).read()
+    assert "int64_t llr_offset" in text and "uint16_t flags" in text
+
+
+def test_strerror_and_version():
+    lib = _capi.load()
+    assert lib.mivit_strerror(0) == b"ok"
+    assert lib.mivit_strerror(-1) == b"invalid argument"
+    assert b"gfx950" in lib.mivit_version()
+
+
+def _plan_status(codes, frames, **opts):
+    lib = _capi.load()
+    arr = (_capi.Code * len(codes))(*codes)
+    o = _capi.Opts()
+    for k, v in opts.items():
+        setattr(o, k, v)
+    h = ctypes.c_void_p()
+    fr = np.ascontiguousarray(frames, dtype=_capi.FRAME_DTYPE)
+    st = lib.mivit_plan_create(ctypes.byref(h), arr, len(codes),
+                               fr.ctypes.data if len(fr) else None, len(fr), ctypes.byref(o))
+    assert not h.value  # nothing allocated on rejection
+    return st
+
+
+def _code(K, gens):
+    c = _capi.Code()
+    c.K, c.beta = K, len(gens)
+    for b, g in enumerate(gens):
+        c.gen[b] = g
+    return c
+
+
+def _frame(**kw):
+    f = np.zeros(1, _capi.FRAME_DTYPE)
+    f[0] = (0, 0, 10, 0, 4, 0, 3)
+    for k, v in kw.items():
+        f[k] = v
+    return f
+
+
+K7 = _code(7, [0o133, 0o171])
+
+
+@pytest.mark.parametrize("code,status", [
+    (_code(2, [3, 3]), _capi.MIVIT_EINVAL),           # K too small
+    (_code(10, [0o1001, 0o1001]), _capi.MIVIT_EINVAL),  # K too large
+    (_code(7, [0o133]), _capi.MIVIT_EINVAL),            # beta = 1
+    (_code(7, [0o333, 0o171]), _capi.MIVIT_EINVAL),     # generator >= 2^K
+    (_code(7, [0o132, 0o171]), _capi.MIVIT_EUNSUPPORTED),  # LSB tap missing
+    (_code(7, [0o033, 0o171]), _capi.MIVIT_EUNSUPPORTED),  # MSB tap missing
+])
+def test_bad_codes(code, status):
+    assert _plan_status([code], _frame()) == status
+
+
+@pytest.mark.parametrize("kw", [
+    dict(code=1), dict(code=-1), dict(n_stages=-1), dict(n_out=11), dict(out_begin=8),
+    dict(bit_offset=5), dict(llr_offset=-2), dict(flags=8),
+])
+def test_bad_frames(kw):
+    assert _plan_status([K7], _frame(**kw)) == _capi.MIVIT_EINVAL
+
+
+def test_overlapping_outputs():
+    fr = np.concatenate([_frame(), _frame(bit_offset=0)])
+    assert _plan_status([K7], fr) == _capi.MIVIT_EINVAL
+
+
+@pytest.mark.parametrize("opts", [
+    dict(dtype=2), dict(radix=3), dict(radix=4, dtype=0), dict(chunk=-1), dict(chunk=100),
+    dict(overlap=-1),
+])
+def test_bad_opts(opts):
+    assert _plan_status([K7], _frame(), **opts) == _capi.MIVIT_EINVAL
+
+
+def test_null_and_misc():
+    lib = _capi.load()
+    assert lib.mivit_plan_create(None, None, 0, None, 0, None) == _capi.MIVIT_EINVAL
+    assert lib.mivit_decode(None, None, None, None, None, None) == _capi.MIVIT_EINVAL
+    assert lib.mivit_decode_grad(None, None, None, None, None) == _capi.MIVIT_EINVAL
+    assert lib.mivit_plan_destroy(None) == _capi.MIVIT_EINVAL
+    assert lib.mivit_plan_get_info(None, None) == _capi.MIVIT_EINVAL
+    assert lib.mivit_quantize_i8(None, None, -1, 1.0, None) == _capi.MIVIT_EINVAL
+    assert lib.mivit_quantize_i8(None, None, 10, 1.0, None) == _capi.MIVIT_EINVAL
+    assert lib.mivit_quantize_i8(None, None, 0, 0.0, None) == _capi.MIVIT_EINVAL

@@ -1,0 +1,281 @@
+"""GPU parity: the HIP decoder against the CPU oracle on the same seeded inputs.
+
+float32 frames: decoded bits and metrics identical to the single-precision
+oracle (the decisions are taken in the same precision); bits equal to the
+double-precision oracle on every frame whose runner-up gap exceeds the float32
+error bound; metric within 1e-5 relative of double precision.
+int8 frames: bits and metrics identical to the exact-integer oracle, radix 2
+and radix 4, including tie-heavy inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2011_13579_amd as mv
+from workload import CODE_K5, CODE_K7, CODE_K9, Code, make_uniform_batch, make_stream
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+DEV = "cuda:0"
+
+
+def gpu_decode(llr_np, code, n_info, terminated=True, radix=0):
+    t = torch.from_numpy(np.ascontiguousarray(llr_np)).to(DEV)
+    words, metric = mv.decode(t, code, n_info, terminated, radix)
+    torch.cuda.synchronize()
+    bits = mv.unpack_bits(words.cpu().numpy(), n_info)
+    return bits, metric.cpu().numpy()
+
+
+def f32_error_bound(S, max_abs_pm):
+    # each stage adds one rounding of the branch metric and one of the sum
+    return 2.0 * S * 2.0 ** -24 * max(1.0, max_abs_pm) * 2
+
+
+def check_float_batch(code, batch, radix=0):
+    n = batch.n_info
+    S = batch.n_stages
+    bits, metric = gpu_decode(batch.llr, code, n, batch.terminated, radix)
+    ob32, om32, _ = oracle.decode_uniform(code, batch.llr, n, batch.terminated, oracle.F32)
+    np.testing.assert_array_equal(bits, ob32)
+    np.testing.assert_array_equal(metric, om32)
+    ob64, om64, gap = oracle.decode_uniform(code, batch.llr, n, batch.terminated, oracle.F64,
+                                            want_gap=True)
+    bound = f32_error_bound(S, float(np.abs(om64).max()) if om64.size else 1.0)
+    clear = gap > bound
+    np.testing.assert_array_equal(bits[clear], ob64[clear])
+    np.testing.assert_allclose(metric.astype(np.float64), om64, rtol=1e-5, atol=1e-5)
+    return bits, metric
+
+
+def test_single_frame_k7_3db():
+    """One frame of 1024 info bits + 6 tail bits, K=7 (133,171), 3 dB, seed 1."""
+    b = make_uniform_batch(CODE_K7, 1, 1024, 3.0, seed=1)
+    bits, metric = check_float_batch(CODE_K7, b)
+    assert (bits != b.msg).sum() < 20
+
+
+CODES = [
+    Code.from_octal(3, ["7", "5"]),
+    Code.from_octal(4, ["17", "13"]),
+    CODE_K5,
+    Code.from_octal(6, ["65", "57"]),
+    CODE_K7,
+    Code.from_octal(8, ["247", "371"]),
+    CODE_K9,
+    Code.from_octal(5, ["25", "33", "37"]),
+    Code.from_octal(7, ["133", "171", "165"]),
+    Code.from_octal(7, ["133", "171", "165", "117"]),
+]
+cid = lambda c: "K%d_" % c.K + "_".join("%o" % g for g in c.gens)
+
+
+@pytest.mark.parametrize("code", CODES, ids=cid)
+def test_float_ragged(code):
+    for n, F, eb in [(0, 3, 2.0), (1, 5, 2.0), (57, 7, 1.0), (64 - code.K + 1, 4, 3.0),
+                     (200, 9, 0.0), (1000, 3, 2.5)]:
+        b = make_uniform_batch(code, F, n, eb, seed=1000 + n + code.K)
+        print("float", cid(code), n, F, flush=True)
+        check_float_batch(code, b)
+
+
+def int8_batch(code, F, n, eb, seed, ties=False):
+    b = make_uniform_batch(code, F, n, eb, seed=seed)
+    if ties:
+        rng = np.random.default_rng(seed)
+        q = rng.integers(-2, 3, size=b.llr.shape).astype(np.int8)
+    else:
+        from workload import int8_scale_for
+        q = oracle.quantize_i8(b.llr, int8_scale_for(eb, code.beta))
+    return b, q
+
+
+@pytest.mark.parametrize("radix", [2, 4])
+@pytest.mark.parametrize("code", CODES, ids=cid)
+def test_int8_exact(code, radix):
+    for n, F, eb, ties in [(0, 2, 2.0, False), (1, 3, 2.0, True), (2, 3, 1.0, True),
+                           (61, 5, 1.0, False), (130, 4, 2.0, True), (777, 3, 0.0, False)]:
+        b, q = int8_batch(code, F, n, eb, 2000 + n + code.K, ties)
+        print("int8", cid(code), radix, n, F, ties, flush=True)
+        bits, metric = gpu_decode(q, code, n, True, radix)
+        ob, om, _ = oracle.decode_uniform(code, q, n, True, oracle.I64)
+        np.testing.assert_array_equal(bits, ob)
+        np.testing.assert_array_equal(metric, om)
+
+
+def _plan_decode(code, frames, llr_np, dtype, radix=0, chunk=0, overlap=0):
+    plan = mv.Plan([code], frames, dtype, radix, chunk, overlap)
+    t = torch.from_numpy(np.ascontiguousarray(llr_np)).to(DEV)
+    words, metric, end = plan.decode(t)
+    torch.cuda.synchronize()
+    n_words = plan.n_bit_words
+    out = words.cpu().numpy()[:n_words]
+    return plan, mv.unpack_bits(out, n_words * 32), metric.cpu().numpy(), end.cpu().numpy()
+
+
+@pytest.mark.parametrize("code", [CODE_K5, CODE_K7, CODE_K9], ids=cid)
+@pytest.mark.parametrize("dtype", ["f32", "i8"])
+def test_free_end_and_unknown_start(code, dtype):
+    """Frames with a best-state end and with an unknown start (all-zero
+    initial metrics), mixed lengths in one plan."""
+    rng = np.random.default_rng(5 + code.K)
+    lens = [1, 2, 5, 63, 64, 65, 300, 1000]
+    fr = np.zeros(len(lens) * 2, mv.FRAME_DTYPE)
+    ofr = np.zeros(len(lens) * 2, oracle.FRAME_DTYPE)
+    off = 0
+    boff = 0
+    for k, (S, sk) in enumerate([(s, sk) for s in lens for sk in (0, 1)]):
+        fr[k] = (off, boff, S, 0, S, 0, mv.MIVIT_START_KNOWN if sk else 0)
+        ofr[k] = (off, boff, S, 0, S, sk, -1, 0)
+        off += S * code.beta
+        boff += ((S + 31) // 32) * 32
+    if dtype == "f32":
+        llr = rng.normal(0, 3, off).astype(np.float32)
+        mode = oracle.F32
+    else:
+        llr = rng.integers(-3, 4, off).astype(np.int8)
+        mode = oracle.I64
+    _, bits, metric, end = _plan_decode(code, fr, llr, dtype)
+    ob, om, oend, _ = oracle.decode_frames([code], ofr, llr, mode, boff)
+    np.testing.assert_array_equal(end, oend)
+    np.testing.assert_array_equal(metric, om)
+    for k in range(len(fr)):
+        a, S = int(ofr[k]["bit_offset"]), int(ofr[k]["n_stages"])
+        np.testing.assert_array_equal(bits[a:a + S], ob[a:a + S])
+
+
+@pytest.mark.parametrize("dtype", ["i8", "f32"])
+def test_chunked_stream(dtype):
+    """A continuous stream split into 2048-stage chunks with 64 stages of
+    overlap on each side; identical to the oracle using the same chunking."""
+    n = 50000
+    msg, llr = make_stream(CODE_K7, n, 4.0, seed=3)
+    if dtype == "i8":
+        from workload import int8_scale_for
+        llr = oracle.quantize_i8(llr, int8_scale_for(4.0, 2))
+        mode = oracle.I64
+    else:
+        mode = oracle.F32
+    t = torch.from_numpy(llr).to(DEV)
+    for radix in ((2, 4) if dtype == "i8" else (2,)):
+        words = mv.decode_stream(t, CODE_K7, n, 2048, 64, radix)
+        torch.cuda.synchronize()
+        bits = mv.unpack_bits(words.cpu().numpy(), n)
+        ob, _, _ = oracle.decode_chunked(CODE_K7, llr, n, 2048, 64, mode)
+        np.testing.assert_array_equal(bits, ob)
+        assert (bits != msg).sum() < 50
+
+
+def test_quantizer_exact():
+    rng = np.random.default_rng(9)
+    x = np.concatenate([
+        rng.normal(0, 8, 100000).astype(np.float32),
+        np.array([0.5, 1.5, 2.5, -0.5, -1.5, 126.5, 127.5, -127.5, 1e30, -1e30, np.inf,
+                  -np.inf, np.nan, 0.0, -0.0, 3.4e38], np.float32),
+    ])
+    for scale in (1.0, 0.37, 16 * 0.5011872336272722, 3.0):
+        q_gpu = mv.quantize_i8(torch.from_numpy(x).to(DEV), scale).cpu().numpy()
+        np.testing.assert_array_equal(q_gpu, oracle.quantize_i8(x, scale))
+
+
+def test_determinism():
+    b = make_uniform_batch(CODE_K7, 64, 2000, 1.0, seed=12)
+    a1 = gpu_decode(b.llr, CODE_K7, 2000)
+    a2 = gpu_decode(b.llr, CODE_K7, 2000)
+    np.testing.assert_array_equal(a1[0], a2[0])
+    np.testing.assert_array_equal(a1[1], a2[1])
+
+
+@pytest.mark.parametrize("dtype", ["f32", "i8"])
+def test_full_batch_4096x8192_sampled(dtype):
+    """4096 terminated frames of 8192 bits (K=7, 2 dB): every frame's metric
+    is the correlation of its decoded codeword and no smaller than the
+    transmitted one; 48 sampled frames match the oracle exactly."""
+    from workload import int8_scale_for
+    F, n, eb = 4096, 8192, 2.0
+    b = make_uniform_batch(CODE_K7, F, n, eb, seed=2002)
+    if dtype == "i8":
+        llr = oracle.quantize_i8(b.llr, int8_scale_for(eb, 2))
+        radixes = (2, 4)
+    else:
+        llr = b.llr
+        radixes = (2,)
+    for radix in radixes:
+        print("full", dtype, radix, flush=True)
+        bits, metric = gpu_decode(llr, CODE_K7, n, True, radix)
+        rng = np.random.default_rng(0)
+        idx = np.sort(rng.choice(F, 48, replace=False))
+        mode = oracle.F32 if dtype == "f32" else oracle.I64
+        ob, om, _ = oracle.decode_uniform(CODE_K7, llr[idx], n, True, mode)
+        np.testing.assert_array_equal(bits[idx], ob)
+        np.testing.assert_array_equal(metric[idx], om)
+        for f in range(0, F, 97):
+            if dtype == "i8":
+                assert oracle.path_correlation(CODE_K7, bits[f], llr[f], exact_int=True) == metric[f]
+                assert metric[f] >= oracle.path_correlation(CODE_K7, b.msg[f], llr[f], exact_int=True)
+            else:
+                c = oracle.path_correlation(CODE_K7, bits[f], llr[f])
+                assert abs(c - metric[f]) <= 1e-5 * abs(c)
+        ber = (bits != b.msg).mean()
+        assert ber < 2e-2  # about 5e-3 at 2 dB for this code
+
+
+def test_gradient_matches_oracle_and_fd():
+    """Backward of the best metric: (-1)^{c(u_hat)} * g for 2048 frames of 1024
+    bits at 2 dB; FD check on frames whose runner-up gap exceeds 1e-2."""
+    F, n = 2048, 1024
+    b = make_uniform_batch(CODE_K7, F, n, 2.0, seed=5)
+    llr = torch.from_numpy(b.llr).to(DEV).requires_grad_(True)
+    words, metric = mv.ViterbiDecode.apply(llr, CODE_K7, n, True)
+    g = torch.linspace(0.5, 1.5, F, device=DEV)
+    (metric * g).sum().backward()
+    grad = llr.grad.cpu().numpy()
+    bits = mv.unpack_bits(words.cpu().numpy(), n)
+    ob, om, _ = oracle.decode_uniform(CODE_K7, b.llr, n, True, oracle.F32)
+    np.testing.assert_array_equal(bits, ob)
+    gn = g.cpu().numpy()
+    for f in range(0, F, 37):
+        ref = oracle.metric_grad(CODE_K7, bits[f], gn[f])
+        np.testing.assert_array_equal(grad[f], ref.astype(np.float32))
+    # finite differences in fp64 on untied frames
+    sub = np.arange(0, F, 256)
+    _, _, gap = oracle.decode_uniform(CODE_K7, b.llr[sub], n, True, oracle.F64, want_gap=True)
+    rng = np.random.default_rng(2)
+    checked = 0
+    for k, f in enumerate(sub):
+        if gap[k] <= 1e-2:
+            continue
+        for pos in rng.choice(b.llr.shape[1], 8, replace=False):
+            lp = b.llr[f].copy()
+            lm = b.llr[f].copy()
+            lp[pos] = np.float32(np.float64(lp[pos]) + 1e-4)
+            lm[pos] = np.float32(np.float64(lm[pos]) - 1e-4)
+            _, mp, _ = oracle.decode_uniform(CODE_K7, lp[None], n, True, oracle.F64)
+            _, mm, _ = oracle.decode_uniform(CODE_K7, lm[None], n, True, oracle.F64)
+            fd = (mp[0] - mm[0]) / (np.float64(lp[pos]) - np.float64(lm[pos]))
+            assert abs(fd * gn[f] - grad[f, pos]) < 1e-5 * abs(gn[f]) + 1e-6
+            checked += 1
+    assert checked > 0
+
+
+def test_plan_reuse_and_empty():
+    code = CODE_K7
+    fr = mv.uniform_frames(code, 0, 10)
+    plan = mv.Plan([code], fr, "f32")
+    assert plan.n_items == 0
+    t = torch.zeros(1, device=DEV)
+    plan.decode(t)
+    b = make_uniform_batch(code, 3, 100, 2.0, seed=1)
+    for _ in range(3):
+        bits, m = gpu_decode(b.llr, code, 100)
+        ob, om, _ = oracle.decode_uniform(code, b.llr, 100, True, oracle.F32)
+        np.testing.assert_array_equal(bits, ob)
