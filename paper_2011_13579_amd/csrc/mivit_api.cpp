@@ -22,14 +22,30 @@ hipError_t launch_grad(const DevCode* codes, const GradFrame* frames, int n_fram
                        int max_stages, const uint32_t* bits, const float* gm, float* grad,
                        hipStream_t st);
 hipError_t launch_quant(const float* x, int8_t* q, int64_t n, float scale, hipStream_t st);
+hipError_t launch_fwd_rot(int K, int beta, bool is_int, const DevCode* codes, const Item* items,
+                          const int2* waves, int n_waves, const void* llr, uint64_t* surv,
+                          void* metric, int32_t* end_out, int32_t* item_end, hipStream_t st);
+hipError_t launch_tb_seg(int layout, const DevCode* codes, const Item* items, int n_items,
+                         const uint64_t* surv, const int32_t* item_end, uint32_t* bits,
+                         int warm, hipStream_t st);
 }  // namespace mivit
 
 using namespace mivit;
 
+// forward kernels and the survivor layouts they write
+enum : int { kKernGeneric2 = 0, kKernGeneric4 = 1, kKernRot2 = 2 };
+enum : int { kLayoutNatR2 = 0, kLayoutNatR4 = 1, kLayoutRotR2 = 2 };
+constexpr int kWarmStages = 64;  // speculative traceback warm-up
+
 struct PlanGroup {
-  int nsl;    // states per lane of the forward kernel
+  int kern;   // forward kernel
+  int layout; // survivor layout (selects the traceback)
+  int nsl;    // generic kernels: states per lane
+  int K, beta;
   int first;  // first item of the group
   int count;
+  int wave_off;  // rotating kernel: first entry of the group in the wave table
+  int n_waves;
 };
 
 struct mivit_plan {
@@ -43,11 +59,13 @@ struct mivit_plan {
   int64_t surv_words = 0;
   std::vector<Item> items;
   std::vector<PlanGroup> groups;
+  std::vector<int> group_keys;
   DevCode* d_codes = nullptr;
   Item* d_items = nullptr;
   int32_t* d_item_end = nullptr;
   uint64_t* d_surv = nullptr;
   GradFrame* d_gframes = nullptr;
+  int2* d_waves = nullptr;  // rotating kernel: (first item, count) per wavefront
 };
 
 namespace {
@@ -83,6 +101,7 @@ void free_plan(mivit_plan* p) {
   (void)hipFree(p->d_item_end);
   (void)hipFree(p->d_surv);
   (void)hipFree(p->d_gframes);
+  (void)hipFree(p->d_waves);
   delete p;
 }
 
@@ -204,24 +223,75 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
         items.push_back(it);
       }
     }
-    // group by forward-kernel shape, longest first inside a group
+    // choose the forward kernel of every item and group them
+    const int radix = p->radix;
+    auto kern_of = [&](const Item& it) {
+      const mivit_code& c = codes[it.code];
+      if (radix == 4) return (int)kKernGeneric4;
+      if (c.K <= 7) return (int)kKernRot2;
+      return (int)kKernGeneric2;
+    };
+    auto key_of = [&](const Item& it) {
+      const mivit_code& c = codes[it.code];
+      const int kern = kern_of(it);
+      // generic kernels group by states per lane; the rotating one by (K, beta)
+      return kern == kKernRot2 ? (kern << 16) | (c.K << 8) | c.beta
+                               : (kern << 16) | nsl_of(c.K);
+    };
     std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) {
-      const int na = nsl_of(codes[a.code].K), nb = nsl_of(codes[b.code].K);
-      if (na != nb) return na > nb;
+      const int ka = key_of(a), kb = key_of(b);
+      if (ka != kb) return ka > kb;
       return a.n_stages > b.n_stages;
     });
     int64_t words_total = 0;
     for (size_t k = 0; k < items.size(); ++k) {
       Item& it = items[k];
+      const mivit_code& c = codes[it.code];
+      const int kern = kern_of(it);
       it.slot = (int32_t)k;
       it.surv_off = words_total;
-      words_total += (int64_t)it.n_stages * words_per_stage(codes[it.code].K);
+      int64_t words;
+      if (kern == kKernRot2)
+        words = (int64_t)((it.n_stages + 31) / 32) * (1 << (c.K - 1)) / 2;
+      else
+        words = (int64_t)it.n_stages * words_per_stage(c.K);
+      words_total += (words + 1) & ~(int64_t)1;  // 16-byte aligned blocks
       p->total_stages += it.n_stages;
-      const int nsl = nsl_of(codes[it.code].K);
-      if (p->groups.empty() || p->groups.back().nsl != nsl)
-        p->groups.push_back({nsl, (int)k, 0});
+      const int key = key_of(it);
+      if (p->groups.empty() || p->group_keys.back() != key) {
+        PlanGroup g;
+        g.kern = kern;
+        g.layout = kern == kKernRot2 ? kLayoutRotR2 : kern == kKernGeneric4 ? kLayoutNatR4 : kLayoutNatR2;
+        g.nsl = nsl_of(c.K);
+        g.K = c.K;
+        g.beta = c.beta;
+        g.first = (int)k;
+        g.count = 0;
+        p->groups.push_back(g);
+        p->group_keys.push_back(key);
+      }
       p->groups.back().count++;
     }
+    // rotating kernel: waves of up to 64/2^(K-1) frames of equal length
+    std::vector<int2> waves;
+    for (PlanGroup& g : p->groups) {
+      g.wave_off = (int)waves.size();
+      g.n_waves = 0;
+      if (g.kern != kKernRot2) continue;
+      const int fpw = 64 >> (g.K - 1);
+      for (int k = g.first; k < g.first + g.count; ++k) {
+        if (g.n_waves > 0) {
+          int2& w = waves.back();
+          if (w.y < fpw && items[w.x].n_stages == items[k].n_stages) {
+            w.y++;
+            continue;
+          }
+        }
+        waves.push_back(make_int2(k, 1));
+        g.n_waves++;
+      }
+    }
+    words_total += 32;  // the traceback reads whole blocks past an item's end
     p->surv_words = words_total;
     p->items = items;
 
@@ -232,6 +302,7 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
       for (int b = 0; b < 4; ++b) dc[c].gen[b] = b < codes[c].beta ? codes[c].gen[b] : 0;
     }
     hipError_t e = upload(&p->d_codes, dc.data(), dc.size());
+    if (e == hipSuccess) e = upload(&p->d_waves, waves.data(), waves.size());
     if (e == hipSuccess) e = upload(&p->d_items, items.data(), items.size());
     if (e == hipSuccess && !items.empty())
       e = hipMalloc((void**)&p->d_item_end, items.size() * sizeof(int32_t));
@@ -284,8 +355,14 @@ mivit_status mivit_forward(mivit_plan* p, const void* llr, void* metric, int32_t
   hipStream_t st = (hipStream_t)stream;
   const bool is_int = p->dtype == MIVIT_I8;
   for (const PlanGroup& g : p->groups) {
-    hipError_t e = launch_fwd(p->radix, g.nsl, is_int, p->d_codes, p->d_items + g.first, g.count,
-                              llr, p->d_surv, metric, end_state, p->d_item_end, st);
+    hipError_t e;
+    if (g.kern == kKernRot2)
+      e = launch_fwd_rot(g.K, g.beta, is_int, p->d_codes, p->d_items, p->d_waves + g.wave_off,
+                         g.n_waves, llr, p->d_surv, metric, end_state, p->d_item_end, st);
+    else
+      e = launch_fwd(g.kern == kKernGeneric4 ? 4 : 2, g.nsl, is_int, p->d_codes,
+                     p->d_items + g.first, g.count, llr, p->d_surv, metric, end_state,
+                     p->d_item_end, st);
     if (e != hipSuccess) return MIVIT_EHIP;
   }
   return MIVIT_OK;
@@ -296,9 +373,12 @@ mivit_status mivit_traceback(mivit_plan* p, uint32_t* bits, void* stream) {
   if (p->items.empty()) return MIVIT_OK;
   if (!bits) return MIVIT_EINVAL;
   DeviceGuard guard(p->device);
-  hipError_t e = launch_tb(p->radix, p->d_codes, p->d_items, (int)p->items.size(), p->d_surv,
-                           p->d_item_end, bits, (hipStream_t)stream);
-  return e == hipSuccess ? MIVIT_OK : MIVIT_EHIP;
+  for (const PlanGroup& g : p->groups) {
+    hipError_t e = launch_tb_seg(g.layout, p->d_codes, p->d_items + g.first, g.count, p->d_surv,
+                                 p->d_item_end, bits, kWarmStages, (hipStream_t)stream);
+    if (e != hipSuccess) return MIVIT_EHIP;
+  }
+  return MIVIT_OK;
 }
 
 mivit_status mivit_decode(mivit_plan* p, const void* llr, uint32_t* bits, void* metric,

@@ -1,0 +1,334 @@
+// Radix-2 forward procedure for K <= 7 with a rotating state-to-lane map.
+//
+// Eq. (radix2:S) pairs the previous states 2f and 2f+1 (differing in their
+// LSB) into the states f and f + 2^(K-2) (differing in their MSB).  With n =
+// K-1 state bits, let the state s live in lane rotl_n(s, t mod n) at time t.
+// Then at stage t both previous states of the state in lane l sit in lanes
+// l with bit (t mod n) cleared and set, and the new state stays in lane l: a
+// butterfly is an exchange between two lanes that differ in one lane bit, and
+// no data moves otherwise.  Lane bits 0 and 1 are exchanged with DPP
+// quad permutations fused into the adds, bits 2..4 with ds_swizzle, bit 5
+// with ds_bpermute.
+//
+// Branch metrics: by the corollary of §IV (MSB and LSB taps set) the two
+// branches into a state carry opposite metrics, delta(2f+1 -> j) =
+// -delta(2f -> j), so each lane reads one value per stage from a per-frame
+// LDS table of Eq. (BM) over the 2^beta output patterns.
+//
+// Decisions: d = 1 when the odd previous state wins (strict comparison, so a
+// tie keeps the even, lower-index one).  Each lane shifts its decision into a
+// 32-bit word (bit 31 - (t mod 32) holds stage t); every 32 stages the words
+// of a frame's lanes are stored together, word index = lane.
+//
+// One wavefront runs 64/2^(K-1) frames of equal length side by side.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mivit_device.h"
+
+namespace mivit {
+
+namespace rot {
+
+__device__ __forceinline__ int parity(uint32_t x) { return __popc(x) & 1; }
+
+__device__ __forceinline__ int branch_out(const DevCode& c, int i, int u) {
+  uint32_t reg = ((uint32_t)u << (c.K - 1)) | (uint32_t)i;
+  int w = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+    if (b < c.beta) w |= parity(c.gen[b] & reg) << b;
+  return w;
+}
+
+__device__ __forceinline__ int rotl(int x, int r, int n) {
+  return r == 0 ? x : (((x << r) | (x >> (n - r))) & ((1 << n) - 1));
+}
+__device__ __forceinline__ int rotr(int x, int r, int n) { return rotl(x, (n - r) % n, n); }
+
+template <bool INT>
+struct Ty;
+template <>
+struct Ty<false> {
+  using T = float;
+  using In = float;
+  __device__ static float neg_unreachable() { return -__builtin_inff(); }
+  __device__ static int bits(float x) { return __builtin_bit_cast(int, x); }
+  __device__ static float from(int x) { return __builtin_bit_cast(float, x); }
+};
+template <>
+struct Ty<true> {
+  using T = int;
+  using In = int8_t;
+  __device__ static int neg_unreachable() { return -(1 << 29); }
+  __device__ static int bits(int x) { return x; }
+  __device__ static int from(int x) { return x; }
+};
+
+// Fetch the metrics of the even and odd previous states for lane bit Q.
+template <int Q, bool INT>
+__device__ __forceinline__ void pair_fetch(typename Ty<INT>::T x, int addr_e, int addr_o,
+                                           typename Ty<INT>::T& e, typename Ty<INT>::T& o) {
+  const int xi = Ty<INT>::bits(x);
+  int ei, oi;
+  if constexpr (Q == 0) {
+    ei = __builtin_amdgcn_mov_dpp(xi, 0xA0, 0xF, 0xF, true);  // quad_perm [0,0,2,2]
+    oi = __builtin_amdgcn_mov_dpp(xi, 0xF5, 0xF, 0xF, true);  // quad_perm [1,1,3,3]
+  } else if constexpr (Q == 1) {
+    ei = __builtin_amdgcn_mov_dpp(xi, 0x44, 0xF, 0xF, true);  // quad_perm [0,1,0,1]
+    oi = __builtin_amdgcn_mov_dpp(xi, 0xEE, 0xF, 0xF, true);  // quad_perm [2,3,2,3]
+  } else if constexpr (Q <= 4) {
+    // ds_swizzle bit-mask mode within 32 lanes: lane' = (lane & and) | or
+    ei = __builtin_amdgcn_ds_swizzle(xi, 0x1F & ~(1 << Q));
+    oi = __builtin_amdgcn_ds_swizzle(xi, 0x1F | ((1 << Q) << 5));
+  } else {
+    ei = __builtin_amdgcn_ds_bpermute(addr_e, xi);
+    oi = __builtin_amdgcn_ds_bpermute(addr_o, xi);
+  }
+  e = Ty<INT>::from(ei);
+  o = Ty<INT>::from(oi);
+}
+
+template <int KM1, bool INT, int NP>
+struct Frame {
+  using T = typename Ty<INT>::T;
+  T pm;
+  uint32_t acc;
+  int pat_off[KM1];  // LDS word offset of this lane's pattern, per phase
+  int addr_e, addr_o;
+};
+
+// Shift a decision into a lane's word: acc = 2*acc + d in one add-with-carry,
+// the carry-in being the wave mask of the comparison.  The wait state covers
+// a VALU-written SGPR read as carry by the next VALU instruction.
+__device__ __forceinline__ uint32_t push_decision(uint32_t acc, uint64_t mask) {
+  uint32_t out;
+  uint64_t carry_out;
+  asm volatile("s_nop 1\n\tv_addc_co_u32_e64 %0, %1, %2, %2, %3"
+               : "=v"(out), "=s"(carry_out)
+               : "v"(acc), "s"(mask));
+  return out;
+}
+
+// One stage at phase Q: add, compare, select, record.
+template <int KM1, bool INT, int NP, int Q>
+__device__ __forceinline__ void stage(Frame<KM1, INT, NP>& F, typename Ty<INT>::T bm) {
+  using T = typename Ty<INT>::T;
+  T e, o;
+  pair_fetch<Q, INT>(F.pm, F.addr_e, F.addr_o, e, o);
+  const T ce = e + bm;  // even previous state, Eq. (PM) candidate
+  const T co = o - bm;  // odd previous state: opposite branch metric
+  const bool d = co > ce;
+  F.pm = d ? co : ce;
+  F.acc = push_decision(F.acc, __builtin_amdgcn_ballot_w64(d));
+}
+
+template <int KM1, bool INT, int NP, int P0, int K0>
+__device__ __forceinline__ void stages_full(Frame<KM1, INT, NP>& F,
+                                            const typename Ty<INT>::T* bmv) {
+  if constexpr (K0 < 32) {
+    stage<KM1, INT, NP, (P0 + K0) % KM1>(F, bmv[K0]);
+    stages_full<KM1, INT, NP, P0, K0 + 1>(F, bmv);
+  }
+}
+
+// A stage whose phase is only known at run time (the last, partial block).
+template <int KM1, bool INT, int NP, int Q>
+__device__ __forceinline__ void stage_dyn(Frame<KM1, INT, NP>& F, const typename Ty<INT>::T* bmrow,
+                                          int q) {
+  if constexpr (Q < KM1) {
+    if (q == Q)
+      stage<KM1, INT, NP, Q>(F, bmrow[F.pat_off[Q]]);
+    else
+      stage_dyn<KM1, INT, NP, Q + 1>(F, bmrow, q);
+  }
+}
+
+template <int KM1, bool INT, int NP, int P0>
+__device__ __forceinline__ void block(Frame<KM1, INT, NP>& F, const typename Ty<INT>::T* bmt,
+                                      int n) {
+  using T = typename Ty<INT>::T;
+  if (n == 32) {
+    // this lane's branch metric of every stage of the block, read up front
+    T bmv[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) bmv[k] = bmt[k * NP + F.pat_off[(P0 + k) % KM1]];
+    stages_full<KM1, INT, NP, P0, 0>(F, bmv);
+  } else {
+#pragma unroll 1
+    for (int k = 0; k < n; ++k) stage_dyn<KM1, INT, NP, 0>(F, bmt + k * NP, (P0 + k) % KM1);
+  }
+}
+
+// State shared by the blocks of one wavefront.
+template <int KM1, bool INT, int BETA>
+struct BlockCtx {
+  Frame<KM1, INT, (1 << BETA)>* F;
+  typename Ty<INT>::T* bmt;
+  const typename Ty<INT>::In* llr;
+  uint32_t* sv;
+  int64_t* offset;
+  int* blk;
+  int S, sl, lane;
+  bool valid;
+};
+
+// One block of up to 32 stages starting at tb, phase (32*BI) mod (K-1).
+template <int KM1, bool INT, int BETA, int BI>
+__device__ __forceinline__ void one_block(BlockCtx<KM1, INT, BETA>& bc, int tb) {
+  using T = typename Ty<INT>::T;
+  constexpr int NS = 1 << KM1, NP = 1 << BETA;
+  const int n = min(32, bc.S - tb);
+  // branch-metric table of this block: Eq. (BM) for every output pattern
+  for (int tt = bc.sl; tt < 32; tt += NS) {
+    if (tt < n && bc.valid) {
+      T l[BETA];
+#pragma unroll
+      for (int b = 0; b < BETA; ++b) l[b] = (T)bc.llr[(int64_t)(tb + tt) * BETA + b];
+#pragma unroll
+      for (int p = 0; p < NP / 2; ++p) {
+        T v = (T)0;
+#pragma unroll
+        for (int b = 0; b < BETA; ++b) v += ((p >> b) & 1) ? -l[b] : l[b];
+        bc.bmt[tt * NP + p] = v;
+        bc.bmt[tt * NP + (NP - 1 - p)] = -v;
+      }
+    }
+  }
+  if constexpr (INT) {
+    if (tb > 0) {
+      // renormalise by the metric of state 0 (always in the frame's lane 0)
+      const T ref = __builtin_amdgcn_ds_bpermute((bc.lane & ~(NS - 1)) << 2, bc.F->pm);
+      bc.F->pm -= ref;
+      *bc.offset += ref;
+    }
+  }
+  __syncthreads();
+  block<KM1, INT, NP, (32 * BI) % KM1>(*bc.F, bc.bmt, n);
+  if (bc.valid) bc.sv[(int64_t)(*bc.blk) * NS + bc.sl] = bc.F->acc << (32 - n);
+  bc.F->acc = 0;
+  ++*bc.blk;
+  __syncthreads();
+}
+
+template <int KM1, bool INT, int BETA, int BI, int NB>
+__device__ __forceinline__ void super_block(BlockCtx<KM1, INT, BETA>& bc, int t0) {
+  if constexpr (BI < NB) {
+    const int tb = t0 + 32 * BI;
+    if (tb < bc.S) {
+      one_block<KM1, INT, BETA, BI>(bc, tb);
+      super_block<KM1, INT, BETA, BI + 1, NB>(bc, t0);
+    }
+  }
+}
+
+constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
+
+}  // namespace rot
+
+template <int KM1, bool INT, int BETA>
+__global__ __launch_bounds__(64) void k_fwd_rot(const DevCode* __restrict__ codes,
+                                                const Item* __restrict__ items,
+                                                const int2* __restrict__ waves,
+                                                const void* __restrict__ llr_v,
+                                                uint64_t* __restrict__ surv, void* metric,
+                                                int32_t* end_out, int32_t* item_end) {
+  using namespace rot;
+  using T = typename Ty<INT>::T;
+  using In = typename Ty<INT>::In;
+  constexpr int NS = 1 << KM1;
+  constexpr int FPW = 64 / NS;
+  constexpr int NP = 1 << BETA;
+  constexpr int SUPER = 32 * KM1 / gcd_c(32, KM1);  // lcm(32, K-1)
+  __shared__ T bmt[FPW][32 * NP];
+  __shared__ T xpm[64];
+
+  const int lane = threadIdx.x;
+  const int fr = lane / NS, sl = lane % NS;
+  // this wave's frames: waves[w] = (first item, count), all of equal length
+  const int2 wv = waves[blockIdx.x];
+  const bool valid = fr < wv.y;
+  const Item it = items[wv.x + (valid ? fr : 0)];
+  const DevCode c = codes[it.code];
+  const int S = __builtin_amdgcn_readfirstlane(it.n_stages);  // equal within the wave
+  const In* llr = (const In*)llr_v + it.llr_off;
+  uint32_t* sv = (uint32_t*)(surv + it.surv_off);
+
+  Frame<KM1, INT, NP> F;
+#pragma unroll
+  for (int q = 0; q < KM1; ++q) {
+    const int j = rotr(sl, (q + 1) % KM1, KM1);  // state held after a phase-q stage
+    const int ie = (j << 1) & (NS - 1);
+    const int u = j >> (KM1 - 1);
+    F.pat_off[q] = branch_out(c, ie, u);
+  }
+  F.addr_e = (lane & ~32) << 2;
+  F.addr_o = (lane | 32) << 2;
+  F.pm = (it.start_known && sl != 0) ? Ty<INT>::neg_unreachable() : (T)0;
+  F.acc = 0;
+  int64_t offset = 0;
+  T* my_bmt = &bmt[fr][0];
+
+  int blk = 0;
+  BlockCtx<KM1, INT, BETA> bc{&F, my_bmt, llr, sv, &offset, &blk, S, sl, lane, valid};
+  for (int t0 = 0; t0 < S; t0 += SUPER) super_block<KM1, INT, BETA, 0, SUPER / 32>(bc, t0);
+  // final metrics: lane sl holds state rotr(sl, S mod (K-1))
+  const int st = rotr(sl, S % KM1, KM1);
+  xpm[fr * NS + st] = F.pm;
+  __syncthreads();
+  if (sl == 0 && valid) {
+    int js = it.end_state;
+    if (js < 0) {
+      js = 0;
+      for (int j = 1; j < NS; ++j)
+        if (xpm[fr * NS + j] > xpm[fr * NS + js]) js = j;
+    }
+    item_end[it.slot] = js;
+    if (it.frame >= 0) {
+      if (end_out) end_out[it.frame] = js;
+      if (metric) {
+        if constexpr (INT)
+          ((int64_t*)metric)[it.frame] = (int64_t)xpm[fr * NS + js] + offset;
+        else
+          ((float*)metric)[it.frame] = xpm[fr * NS + js];
+      }
+    }
+  }
+}
+
+hipError_t launch_fwd_rot(int K, int beta, bool is_int, const DevCode* codes, const Item* items,
+                          const int2* waves, int n_waves, const void* llr, uint64_t* surv,
+                          void* metric, int32_t* end_out, int32_t* item_end, hipStream_t st) {
+  if (n_waves <= 0) return hipSuccess;
+  dim3 grid(n_waves), block(64);
+#define MV_ROT(KM1, I, B)                                                                      \
+  hipLaunchKernelGGL((k_fwd_rot<KM1, I, B>), grid, block, 0, st, codes, items, waves, llr, \
+                     surv, metric, end_out, item_end)
+#define MV_ROT_B(KM1, I)         \
+  switch (beta) {                \
+    case 2: MV_ROT(KM1, I, 2); break; \
+    case 3: MV_ROT(KM1, I, 3); break; \
+    case 4: MV_ROT(KM1, I, 4); break; \
+    default: return hipErrorInvalidValue; \
+  }
+#define MV_ROT_K(I)                  \
+  switch (K) {                       \
+    case 3: MV_ROT_B(2, I); break;   \
+    case 4: MV_ROT_B(3, I); break;   \
+    case 5: MV_ROT_B(4, I); break;   \
+    case 6: MV_ROT_B(5, I); break;   \
+    case 7: MV_ROT_B(6, I); break;   \
+    default: return hipErrorInvalidValue; \
+  }
+  if (is_int) {
+    MV_ROT_K(true);
+  } else {
+    MV_ROT_K(false);
+  }
+#undef MV_ROT_K
+#undef MV_ROT_B
+#undef MV_ROT
+  return hipGetLastError();
+}
+
+}  // namespace mivit

@@ -192,9 +192,10 @@ __global__ __launch_bounds__(64) void k_fwd_r2(const DevCode* __restrict__ codes
 // Radix-4 forward procedure (exact integers).  Right state j of dragonfly
 // f = j mod 2^(K-3) takes the best of the four left states 4f+y (smallest y
 // on ties); the super-branch i -> m -> j has middle state
-// m = (bit K-3 of j) << (K-2) | (i >> 1).  A frame with an odd number of
-// stages starts with one radix-2 stage.  Decision words: for the pair of
-// stages (t, t+1), word t holds bit 0 of y and word t+1 holds bit 1.
+// m = (bit K-3 of j) << (K-2) | (i >> 1).  Stage pairs start at stage 0; a
+// frame with an odd number of stages ends with one radix-2 stage (equivalent
+// in exact arithmetic to any other placement).  Decision words: for the pair
+// of stages (t, t+1), word t holds bit 0 of y and word t+1 holds bit 1.
 // ---------------------------------------------------------------------------
 template <int NSL>
 __global__ __launch_bounds__(64) void k_fwd_r4(const DevCode* __restrict__ codes,
@@ -240,37 +241,18 @@ __global__ __launch_bounds__(64) void k_fwd_r4(const DevCode* __restrict__ codes
   }
   int64_t offset = 0;
   const int S = it.n_stages;
-  const int lead = S & 1;
-  if (lead) {
-    // one radix-2 stage at t = 0
-    fill_bm_table<true>(c, llr, it.llr_off, 0, 1, bmt);
-#pragma unroll
-    for (int s = 0; s < NSL; ++s)
-      if (act[s]) xpm[lane + 64 * s] = pm[s];
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < NSL; ++s) {
-      const T a = xpm[iLo[s]], b = xpm[iLo[s] + 1];
-      const T cLo = a + bmt[0][pLo[s]];
-      const T cHi = b + bmt[0][pHi[s]];
-      const bool d = act[s] && (cHi > cLo);
-      pm[s] = d ? cHi : cLo;
-      const uint64_t m = __ballot(d);
-      if (lane == 0) surv[it.surv_off + s] = m;
-    }
-    __syncthreads();
-  }
-  for (int t0 = lead; t0 < S; t0 += kBlk) {
-    const int nst = min(kBlk, S - t0);  // even
+  for (int t0 = 0; t0 < S; t0 += kBlk) {
+    const int nst = min(kBlk, S - t0);
     fill_bm_table<true>(c, llr, it.llr_off, t0, nst, bmt);
-    if (t0 > lead) {
+    if (t0 > 0) {
       const T ref = __builtin_amdgcn_readfirstlane(pm[0]);
 #pragma unroll
       for (int s = 0; s < NSL; ++s) pm[s] -= ref;
       offset += ref;
     }
     __syncthreads();
-    for (int tt = 0; tt < nst; tt += 2) {
+    const int npair = nst & ~1;
+    for (int tt = 0; tt < npair; tt += 2) {
 #pragma unroll
       for (int s = 0; s < NSL; ++s)
         if (act[s]) xpm[lane + 64 * s] = pm[s];
@@ -298,6 +280,28 @@ __global__ __launch_bounds__(64) void k_fwd_r4(const DevCode* __restrict__ codes
         if (lane == tt + 1) {
           svlo[s] = (uint32_t)m1;
           svhi[s] = (uint32_t)(m1 >> 32);
+        }
+      }
+      __syncthreads();
+    }
+    if (nst & 1) {
+      // the final stage of an odd-length frame: one radix-2 stage
+      const int tt = nst - 1;
+#pragma unroll
+      for (int s = 0; s < NSL; ++s)
+        if (act[s]) xpm[lane + 64 * s] = pm[s];
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < NSL; ++s) {
+        const T a = xpm[iLo[s]], b = xpm[iLo[s] + 1];
+        const T cLo = a + bmt[tt][pLo[s]];
+        const T cHi = b + bmt[tt][pHi[s]];
+        const bool d = act[s] && (cHi > cLo);
+        pm[s] = d ? cHi : cLo;
+        const uint64_t m = __ballot(d);
+        if (lane == tt) {
+          svlo[s] = (uint32_t)m;
+          svhi[s] = (uint32_t)(m >> 32);
         }
       }
       __syncthreads();
@@ -361,21 +365,22 @@ __global__ __launch_bounds__(64) void k_tb_r4(const DevCode* __restrict__ codes,
   const DevCode c = codes[it.code];
   const int K = c.K, NS = 1 << (K - 1), W = words_per_stage(K);
   const uint64_t* sv = surv + it.surv_off;
-  const int S = it.n_stages, lead = S & 1;
+  const int S = it.n_stages;
   int j = item_end[it.slot];
   BitSink sink;
-  for (int t = S - 2; t >= lead; t -= 2) {
+  if (S & 1) {
+    const int t = S - 1;
+    const int d = (int)((sv[(int64_t)t * W + (j >> 6)] >> (j & 63)) & 1);
+    sink.put(it, t, j >> (K - 2), bits);
+    j = ((j << 1) | d) & (NS - 1);
+  }
+  for (int t = (S & ~1) - 2; t >= 0; t -= 2) {
     const int wi = j >> 6, sh = j & 63;
     const int y = (int)((sv[(int64_t)t * W + wi] >> sh) & 1) |
                   ((int)((sv[(int64_t)(t + 1) * W + wi] >> sh) & 1) << 1);
     sink.put(it, t + 1, j >> (K - 2), bits);
     sink.put(it, t, (j >> (K - 3)) & 1, bits);
     j = 4 * (j & ((NS >> 2) - 1)) + y;
-  }
-  if (lead) {
-    const int d = (int)((sv[j >> 6] >> (j & 63)) & 1);
-    sink.put(it, 0, j >> (K - 2), bits);
-    j = ((j << 1) | d) & (NS - 1);
   }
 }
 

@@ -1,0 +1,229 @@
+// Parallel traceback (Algorithm 2) of one trellis per wavefront.
+//
+// The emitted stages of an item are cut into at most 64 segments of L stages
+// (L a multiple of 32, so every segment owns whole output words).  Lane g
+// traces segment g.  The lane whose chase reaches the item's last stage
+// starts from the true final state and is exact.  Every other lane starts
+// `warm` stages above its segment from a guessed state; survivor paths merge
+// quickly going backwards, so it usually meets the true path before reaching
+// its segment.  Exactness does not rest on that: lane g records the state y_g
+// it passes at its segment's upper boundary and its final state x_g at the
+// lower boundary.  When y_g equals x_{g+1} of the lane above (itself exact),
+// lane g followed the true path through its whole segment.  A ballot finds
+// the lanes where this fails; they trace again from x_{g+1} and the check
+// repeats, at most G times, until every boundary agrees.
+//
+// Survivor words are read one block (64 words) per lane at a time.  All lanes
+// advance block by block in lockstep rounds; the blocks of the next round are
+// streamed by the lanes straight into the other half of a double-buffered LDS
+// area (global_load_lds, no register staging) while the current round is
+// chased.  In buffer k, word w of lane l sits at ((k*16 + w/4)*64 + l)*4 +
+// w%4, the layout one 16-byte global_load_lds per lane and chunk produces.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mivit_device.h"
+
+namespace mivit {
+
+// survivor layouts
+enum : int {
+  kLayoutNatR2 = 0,  // per stage, ceil(NS/64) uint64 words, bit j = decision of state j
+  kLayoutNatR4 = 1,  // same words; stage pairs (t, t+1) from 0 hold bits 0 and 1 of y
+  kLayoutRotR2 = 2,  // per 32 stages, NS uint32 words; rotating state-to-word map
+};
+
+template <int LAYOUT>
+struct TbGeom {
+  int K, KM1, NS, W;  // W: uint64 words per stage (natural layouts)
+  int SB;             // stages per block
+  int WB;             // uint32 words per block
+  __device__ TbGeom(int K_) : K(K_), KM1(K_ - 1), NS(1 << (K_ - 1)) {
+    W = words_per_stage(K_);
+    if (LAYOUT == kLayoutRotR2) {
+      SB = 32;
+      WB = NS;
+    } else {
+      SB = 32 / W;
+      WB = 64;
+    }
+  }
+};
+
+__device__ __forceinline__ int rotl_bits(int x, int r, int n) {
+  // rotate the n-bit value x left by r (0 <= r < n)
+  return ((x << r) | (x >> (n - r))) & ((1 << n) - 1);
+}
+
+struct Emitter {
+  uint32_t word = 0;
+  __device__ __forceinline__ void put(int k, int u, uint32_t* bits, int64_t bit_off) {
+    word |= (uint32_t)u << (k & 31);
+    if ((k & 31) == 0) {
+      bits[(bit_off + k) >> 5] = word;
+      word = 0;
+    }
+  }
+};
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+// Stream this lane's 64-word block starting at src into LDS buffer buf_k
+// (for the lanes currently active).  Always 64 words: a block of fewer words
+// is followed by more survivor words or by the allocation's padding.
+__device__ __forceinline__ void fetch_block(const uint32_t* src, uint32_t* buf_k) {
+#pragma unroll
+  for (int c = 0; c < 16; ++c)
+    __builtin_amdgcn_global_load_lds((const void*)(src + 4 * c), (lds_ptr_t)(buf_k + c * 256),
+                                     16, 0, 0);
+}
+
+__device__ __forceinline__ uint32_t word_at(const uint32_t* buf_k, int w, int lane) {
+  return buf_k[((w >> 2) * 64 + lane) * 4 + (w & 3)];
+}
+
+// Per-lane chase state.
+struct Chase {
+  int top, a, b;  // from time top down to time a; bits of [a, b) are emitted
+  int j;          // current state
+  int y;          // state at time b
+};
+
+// All lanes with top > a chase their range; the others idle.  Returns with
+// c.j = state at time a and c.y = state at time b.
+template <int LAYOUT>
+__device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_t* __restrict__ sv,
+                                          uint32_t* lds, Chase& c, int ob, uint32_t* bits,
+                                          int64_t bit_off) {
+  const int lane = threadIdx.x;
+  const int SB = g.SB, WB = g.WB;
+  Emitter em;
+  if (c.top == c.b) c.y = c.j;
+  const bool go = c.top > c.a;
+  const int B0 = go ? (c.top - 1) / SB : 0;
+  const int nb = go ? B0 - c.a / SB + 1 : 0;
+  int t = c.top - 1;
+  if (nb > 0) fetch_block(sv + (int64_t)B0 * WB, lds);
+  for (int r = 0;; ++r) {
+    if (__ballot(r < nb) == 0) break;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    uint32_t* cur = lds + (r & 1) * 4096;
+    uint32_t* nxt = lds + ((r + 1) & 1) * 4096;
+    if (r + 1 < nb) fetch_block(sv + (int64_t)(B0 - r - 1) * WB, nxt);
+    if (r < nb) {
+      const int B = B0 - r;
+      const int lo = max(c.a, B * SB);
+      int j = c.j;
+      if (LAYOUT == kLayoutNatR4) {
+        if (t >= lo && !(t & 1)) {
+          // odd stage count: the last stage was a radix-2 stage
+          const int w = (t % SB) * 2 * g.W + (j >> 5);
+          const int d = (word_at(cur, w, lane) >> (j & 31)) & 1;
+          if (t < c.b) em.put(t - ob, j >> (g.KM1 - 1), bits, bit_off);
+          j = ((j << 1) | d) & (g.NS - 1);
+          if (t == c.b) c.y = j;
+          --t;
+        }
+        for (; t > lo; t -= 2) {
+          // the pair of stages (t-1, t): y = bit 0 from word t-1, bit 1 from word t
+          const int w0 = ((t - 1) % SB) * 2 * g.W + (j >> 5);
+          const int w1 = (t % SB) * 2 * g.W + (j >> 5);
+          const int yy = ((word_at(cur, w0, lane) >> (j & 31)) & 1) |
+                         (((word_at(cur, w1, lane) >> (j & 31)) & 1) << 1);
+          // b is even except for the last segment, whose b = out_begin + n_out
+          // may split a pair
+          if (t < c.b) em.put(t - ob, j >> (g.KM1 - 1), bits, bit_off);
+          if (t - 1 < c.b) em.put(t - 1 - ob, (j >> (g.KM1 - 2)) & 1, bits, bit_off);
+          j = 4 * (j & ((g.NS >> 2) - 1)) + yy;
+          if (t - 1 == c.b) c.y = j;
+        }
+      } else {
+        for (; t >= lo; --t) {
+          int d;
+          if (LAYOUT == kLayoutRotR2) {
+            const int w = rotl_bits(j, (t + 1) % g.KM1, g.KM1);
+            d = (word_at(cur, w, lane) >> (31 - (t & 31))) & 1;
+          } else {
+            const int w = (t % SB) * 2 * g.W + (j >> 5);
+            d = (word_at(cur, w, lane) >> (j & 31)) & 1;
+          }
+          if (t < c.b) em.put(t - ob, j >> (g.KM1 - 1), bits, bit_off);
+          j = ((j << 1) | d) & (g.NS - 1);
+          if (t == c.b) c.y = j;
+        }
+      }
+      c.j = j;
+    }
+  }
+}
+
+template <int LAYOUT>
+__global__ __launch_bounds__(64) void k_tb_seg(const DevCode* __restrict__ codes,
+                                               const Item* __restrict__ items,
+                                               const uint64_t* __restrict__ surv,
+                                               const int32_t* __restrict__ item_end,
+                                               uint32_t* __restrict__ bits, int warm) {
+  __shared__ uint32_t lds[2 * 4096];
+  const Item it = items[blockIdx.x];
+  if (it.n_out <= 0) return;
+  const DevCode code = codes[it.code];
+  const TbGeom<LAYOUT> g(code.K);
+  const int lane = threadIdx.x;
+  const uint32_t* sv = (const uint32_t*)(surv + it.surv_off);
+  const int S = it.n_stages, ob = it.out_begin, n = it.n_out;
+  // segment geometry: G segments of L stages, L a multiple of 32
+  int G = min(64, (n + 31) / 32);
+  const int L = (((n + G - 1) / G) + 31) & ~31;
+  G = (n + L - 1) / L;
+  const bool active = lane < G;
+  Chase c;
+  c.a = ob + lane * L;
+  c.b = min(ob + (lane + 1) * L, ob + n);
+  c.top = active ? ((lane == G - 1) ? S : min(S, c.b + warm)) : c.a;
+  const bool exact = active && c.top == S;
+  c.j = exact ? item_end[it.slot] : 0;
+  c.y = -1;
+  chase_all<LAYOUT>(g, sv, lds, c, ob, bits, it.bit_off);
+  // repair rounds: lane g is right when its state at b equals lane g+1's at a
+  bool checked = exact;
+  for (int round = 0; round <= G; ++round) {
+    const int x_up = __shfl_down(c.j, 1);
+    const bool bad = active && !checked && lane < G - 1 && c.y != x_up;
+    if (__ballot(bad) == 0) break;
+    // lanes that agree with their neighbour stay idle this round
+    Chase r = c;
+    r.top = bad ? c.b : c.a;
+    r.j = bad ? x_up : c.j;
+    chase_all<LAYOUT>(g, sv, lds, r, ob, bits, it.bit_off);
+    if (bad) {
+      c.j = r.j;
+      c.y = x_up;
+    }
+  }
+}
+
+hipError_t launch_tb_seg(int layout, const DevCode* codes, const Item* items, int n_items,
+                         const uint64_t* surv, const int32_t* item_end, uint32_t* bits,
+                         int warm, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  dim3 grid(n_items), block(64);
+  switch (layout) {
+    case kLayoutNatR2:
+      hipLaunchKernelGGL(k_tb_seg<kLayoutNatR2>, grid, block, 0, st, codes, items, surv,
+                         item_end, bits, warm);
+      break;
+    case kLayoutNatR4:
+      hipLaunchKernelGGL(k_tb_seg<kLayoutNatR4>, grid, block, 0, st, codes, items, surv,
+                         item_end, bits, warm);
+      break;
+    case kLayoutRotR2:
+      hipLaunchKernelGGL(k_tb_seg<kLayoutRotR2>, grid, block, 0, st, codes, items, surv,
+                         item_end, bits, warm);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mivit
