@@ -144,8 +144,9 @@ def main():
     plans = {}
     results = {}
     for v in args.variants.split(","):
-        dt, radix = ("i8", 4) if v == "i8r4" else ("f32", 2) if v == "f32r2" else ("i8", 2)
-        plans[v] = mv.Plan([code], frames, dt, radix)
+        base, _, kv = v.partition(":")
+        dt, radix = ("i8", 4) if base == "i8r4" else ("f32", 2) if base == "f32r2" else ("i8", 2)
+        plans[v] = mv.Plan([code], frames, dt, radix, variant=int(kv[1:]) if kv else 0)
         llr = llr_i8 if dt == "i8" else llr_f32
         ms, fwd, tb, bits, _ = time_variant(torch, mv, plans[v], llr, args.steps, args.warmup)
         dec = mv.unpack_bits(bits.cpu().numpy()[: N_FRAMES * (N_INFO // 32)].reshape(N_FRAMES, -1), N_INFO)

@@ -89,7 +89,15 @@ typedef struct {
                        windows of chunk core stages plus 'overlap' stages on
                        each side (§III); 0: decode whole frames */
   int32_t overlap;  /* stages of overlap on each side of a chunk, >= 0 */
-  int32_t reserved[4];
+  int32_t variant;  /* kernel variant for tuning and comparison; 0: default
+                       (butterfly exchanges through DPP and permlane swaps;
+                       radix 4 with K = 5 or 7, beta = 2: two frames per
+                       register in packed 16-bit metrics); 1 and 2: radix-2
+                       forward exchanging through LDS swizzles (1: both
+                       previous-state metrics fetched, 2: one partner metric
+                       per lane), radix 4 through LDS, one frame per lane
+                       group and 32-bit metrics */
+  int32_t reserved[3];
 } mivit_opts;
 
 typedef struct mivit_plan mivit_plan;

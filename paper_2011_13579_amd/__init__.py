@@ -84,7 +84,7 @@ class Plan:
     """
 
     def __init__(self, codes: Sequence, frames: np.ndarray, dtype: str = "f32", radix: int = 0,
-                 chunk: int = 0, overlap: int = 0):
+                 chunk: int = 0, overlap: int = 0, variant: int = 0):
         lib = _capi.load()
         self.codes = [_as_code(c) for c in codes]
         self.frames = np.ascontiguousarray(frames, dtype=FRAME_DTYPE)
@@ -92,6 +92,7 @@ class Plan:
         arr = (_capi.Code * len(self.codes))(*[c.c_struct() for c in self.codes])
         opts = _capi.Opts()
         opts.dtype, opts.radix, opts.chunk, opts.overlap = self.dtype, int(radix), int(chunk), int(overlap)
+        opts.variant = int(variant)
         h = ctypes.c_void_p()
         st = lib.mivit_plan_create(ctypes.byref(h), arr, len(self.codes),
                                    self.frames.ctypes.data if len(self.frames) else None,

@@ -44,7 +44,8 @@ assert FRAME_DTYPE.itemsize == ctypes.sizeof(Frame) == 32
 
 class Opts(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("radix", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("overlap", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("overlap", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class PlanInfo(ctypes.Structure):

@@ -22,20 +22,31 @@ hipError_t launch_grad(const DevCode* codes, const GradFrame* frames, int n_fram
                        int max_stages, const uint32_t* bits, const float* gm, float* grad,
                        hipStream_t st);
 hipError_t launch_quant(const float* x, int8_t* q, int64_t n, float scale, hipStream_t st);
-hipError_t launch_fwd_rot(int K, int beta, bool is_int, const DevCode* codes, const Item* items,
-                          const int2* waves, int n_waves, const void* llr, uint64_t* surv,
-                          void* metric, int32_t* end_out, int32_t* item_end, hipStream_t st);
+hipError_t launch_fwd_rot(int K, int beta, bool is_int, int mode, const DevCode* codes,
+                          const Item* items, const int2* waves, int n_waves, const void* llr,
+                          uint64_t* surv, void* metric, int32_t* end_out, int32_t* item_end,
+                          hipStream_t st);
 hipError_t launch_tb_seg(int layout, const DevCode* codes, const Item* items, int n_items,
                          const uint64_t* surv, const int32_t* item_end, uint32_t* bits,
                          int warm, hipStream_t st);
+hipError_t launch_fwd_r4p(int K, const DevCode* codes, const Item* items, const int2* waves,
+                          int n_waves, const int8_t* llr, uint64_t* surv, int64_t* metric,
+                          int32_t* end_out, int32_t* item_end, hipStream_t st);
+hipError_t launch_tb_r4p(int K, const Item* items, const int2* pairs, int n_pairs,
+                         const uint64_t* surv, const int32_t* item_end, uint32_t* bits, int warm,
+                         hipStream_t st);
 }  // namespace mivit
 
 using namespace mivit;
 
 // forward kernels and the survivor layouts they write
-enum : int { kKernGeneric2 = 0, kKernGeneric4 = 1, kKernRot2 = 2 };
-enum : int { kLayoutNatR2 = 0, kLayoutNatR4 = 1, kLayoutRotR2 = 2 };
+enum : int { kKernGeneric2 = 0, kKernGeneric4 = 1, kKernRot2 = 2, kKernRot4P = 3 };
+enum : int { kLayoutNatR2 = 0, kLayoutNatR4 = 1, kLayoutRotR2 = 2, kLayoutRot4P = 3 };
 constexpr int kWarmStages = 64;  // speculative traceback warm-up
+// rotating forward kernel exchange scheme per plan variant:
+// 0 all exchanges in the VALU (DPP, permlane swaps), 1 both previous-state
+// metrics via DPP/LDS swizzles, 2 one partner metric via DPP/LDS swizzles
+constexpr int kRotMode[3] = {2, 0, 1};
 
 struct PlanGroup {
   int kern;   // forward kernel
@@ -44,14 +55,17 @@ struct PlanGroup {
   int K, beta;
   int first;  // first item of the group
   int count;
-  int wave_off;  // rotating kernel: first entry of the group in the wave table
+  int wave_off;  // rotating kernels: first entry of the group in the wave table
   int n_waves;
+  int pair_off;  // packed radix-4 kernel: first entry in the traceback pair table
+  int n_pairs;
 };
 
 struct mivit_plan {
   int device = 0;
   int dtype = MIVIT_F32;
   int radix = 2;
+  int variant = 0;  // kernel variant (0: default)
   int n_frames = 0;
   bool grad_ok = false;
   int grad_max_stages = 0;
@@ -65,7 +79,8 @@ struct mivit_plan {
   int32_t* d_item_end = nullptr;
   uint64_t* d_surv = nullptr;
   GradFrame* d_gframes = nullptr;
-  int2* d_waves = nullptr;  // rotating kernel: (first item, count) per wavefront
+  int2* d_waves = nullptr;  // rotating kernels: (first item, count) per wavefront
+  int2* d_pairs = nullptr;  // packed radix-4 traceback: (first item, count) per frame pair
 };
 
 namespace {
@@ -102,6 +117,7 @@ void free_plan(mivit_plan* p) {
   (void)hipFree(p->d_surv);
   (void)hipFree(p->d_gframes);
   (void)hipFree(p->d_waves);
+  (void)hipFree(p->d_pairs);
   delete p;
 }
 
@@ -145,6 +161,7 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
   if (o.radix != 0 && o.radix != 2 && o.radix != 4) return MIVIT_EINVAL;
   if (o.radix == 4 && o.dtype != MIVIT_I8) return MIVIT_EINVAL;
   if (o.chunk < 0 || o.overlap < 0 || (o.chunk > 0 && o.chunk % 32 != 0)) return MIVIT_EINVAL;
+  if (o.variant < 0 || o.variant > 2) return MIVIT_EINVAL;
   for (int c = 0; c < n_codes; ++c) {
     mivit_status s = check_code(codes[c]);
     if (s != MIVIT_OK) return s;
@@ -175,6 +192,7 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
     }
     p->dtype = o.dtype;
     p->radix = o.radix == 0 ? 2 : o.radix;
+    p->variant = o.variant;
     p->n_frames = n_frames;
     // expand frames into work items
     std::vector<Item> items;
@@ -227,62 +245,72 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
     const int radix = p->radix;
     auto kern_of = [&](const Item& it) {
       const mivit_code& c = codes[it.code];
-      if (radix == 4) return (int)kKernGeneric4;
+      if (radix == 4)
+        return (o.variant == 0 && c.beta == 2 && (c.K == 5 || c.K == 7)) ? (int)kKernRot4P
+                                                                          : (int)kKernGeneric4;
       if (c.K <= 7) return (int)kKernRot2;
       return (int)kKernGeneric2;
     };
     auto key_of = [&](const Item& it) {
       const mivit_code& c = codes[it.code];
       const int kern = kern_of(it);
-      // generic kernels group by states per lane; the rotating one by (K, beta)
-      return kern == kKernRot2 ? (kern << 16) | (c.K << 8) | c.beta
-                               : (kern << 16) | nsl_of(c.K);
+      // generic kernels group by states per lane; the rotating ones by (K, beta)
+      return (kern == kKernRot2 || kern == kKernRot4P) ? (kern << 16) | (c.K << 8) | c.beta
+                                                       : (kern << 16) | nsl_of(c.K);
     };
     std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) {
       const int ka = key_of(a), kb = key_of(b);
       if (ka != kb) return ka > kb;
-      return a.n_stages > b.n_stages;
+      if (a.n_stages != b.n_stages) return a.n_stages > b.n_stages;
+      if (a.out_begin != b.out_begin) return a.out_begin < b.out_begin;
+      return a.n_out < b.n_out;
     });
-    int64_t words_total = 0;
     for (size_t k = 0; k < items.size(); ++k) {
       Item& it = items[k];
       const mivit_code& c = codes[it.code];
       const int kern = kern_of(it);
       it.slot = (int32_t)k;
-      it.surv_off = words_total;
-      int64_t words;
-      if (kern == kKernRot2)
-        words = (int64_t)((it.n_stages + 31) / 32) * (1 << (c.K - 1)) / 2;
-      else
-        words = (int64_t)it.n_stages * words_per_stage(c.K);
-      words_total += (words + 1) & ~(int64_t)1;  // 16-byte aligned blocks
       p->total_stages += it.n_stages;
       const int key = key_of(it);
       if (p->groups.empty() || p->group_keys.back() != key) {
         PlanGroup g;
         g.kern = kern;
-        g.layout = kern == kKernRot2 ? kLayoutRotR2 : kern == kKernGeneric4 ? kLayoutNatR4 : kLayoutNatR2;
+        g.layout = kern == kKernRot2    ? kLayoutRotR2
+                   : kern == kKernRot4P ? kLayoutRot4P
+                   : kern == kKernGeneric4 ? kLayoutNatR4
+                                           : kLayoutNatR2;
         g.nsl = nsl_of(c.K);
         g.K = c.K;
         g.beta = c.beta;
         g.first = (int)k;
         g.count = 0;
+        g.pair_off = 0;
+        g.n_pairs = 0;
         p->groups.push_back(g);
         p->group_keys.push_back(key);
       }
       p->groups.back().count++;
     }
-    // rotating kernel: waves of up to 64/2^(K-1) frames of equal length
-    std::vector<int2> waves;
+    // rotating kernels: wavefronts of frames of equal length (radix 2: up to
+    // 64/2^(K-1) frames; packed radix 4: up to 2*64/2^(K-1), where the two
+    // frames of a lane group must also emit the same stages)
+    std::vector<int2> waves, pairs;
+    std::vector<char> pair_hi(items.size(), 0);
     for (PlanGroup& g : p->groups) {
       g.wave_off = (int)waves.size();
       g.n_waves = 0;
-      if (g.kern != kKernRot2) continue;
-      const int fpw = 64 >> (g.K - 1);
+      if (g.kern != kKernRot2 && g.kern != kKernRot4P) continue;
+      const bool packed = g.kern == kKernRot4P;
+      const int fpw = (packed ? 2 : 1) * (64 >> (g.K - 1));
       for (int k = g.first; k < g.first + g.count; ++k) {
         if (g.n_waves > 0) {
           int2& w = waves.back();
-          if (w.y < fpw && items[w.x].n_stages == items[k].n_stages) {
+          const Item& prev = items[k - 1];
+          bool fits = w.y < fpw && items[w.x].n_stages == items[k].n_stages;
+          if (packed && (w.y & 1))
+            fits = fits && prev.out_begin == items[k].out_begin && prev.n_out == items[k].n_out;
+          if (fits) {
+            if (packed) pair_hi[k] = (char)(w.y & 1);
             w.y++;
             continue;
           }
@@ -290,6 +318,33 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
         waves.push_back(make_int2(k, 1));
         g.n_waves++;
       }
+      if (packed) {
+        g.pair_off = (int)pairs.size();
+        for (int w = g.wave_off; w < g.wave_off + g.n_waves; ++w)
+          for (int s = 0; s < waves[w].y; s += 2)
+            pairs.push_back(make_int2(waves[w].x + s, std::min(2, waves[w].y - s)));
+        g.n_pairs = (int)pairs.size() - g.pair_off;
+      }
+    }
+    // survivor memory, 16-byte aligned per item (per frame pair when packed)
+    int64_t words_total = 0;
+    for (size_t k = 0; k < items.size(); ++k) {
+      Item& it = items[k];
+      const mivit_code& c = codes[it.code];
+      const int kern = kern_of(it);
+      if (kern == kKernRot4P && pair_hi[k]) {
+        it.surv_off = items[k - 1].surv_off;
+        continue;
+      }
+      it.surv_off = words_total;
+      int64_t words;
+      if (kern == kKernRot2)
+        words = (int64_t)((it.n_stages + 31) / 32) * (1 << (c.K - 1)) / 2;
+      else if (kern == kKernRot4P)  // 2^(K-1) 32-bit words per 8 iterations
+        words = (int64_t)((it.n_stages / 2 + 7) / 8) * (1 << (c.K - 1)) / 2;
+      else
+        words = (int64_t)it.n_stages * words_per_stage(c.K);
+      words_total += (words + 1) & ~(int64_t)1;
     }
     words_total += 32;  // the traceback reads whole blocks past an item's end
     p->surv_words = words_total;
@@ -303,6 +358,7 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
     }
     hipError_t e = upload(&p->d_codes, dc.data(), dc.size());
     if (e == hipSuccess) e = upload(&p->d_waves, waves.data(), waves.size());
+    if (e == hipSuccess) e = upload(&p->d_pairs, pairs.data(), pairs.size());
     if (e == hipSuccess) e = upload(&p->d_items, items.data(), items.size());
     if (e == hipSuccess && !items.empty())
       e = hipMalloc((void**)&p->d_item_end, items.size() * sizeof(int32_t));
@@ -356,8 +412,13 @@ mivit_status mivit_forward(mivit_plan* p, const void* llr, void* metric, int32_t
   const bool is_int = p->dtype == MIVIT_I8;
   for (const PlanGroup& g : p->groups) {
     hipError_t e;
-    if (g.kern == kKernRot2)
-      e = launch_fwd_rot(g.K, g.beta, is_int, p->d_codes, p->d_items, p->d_waves + g.wave_off,
+    if (g.kern == kKernRot4P)
+      e = launch_fwd_r4p(g.K, p->d_codes, p->d_items, p->d_waves + g.wave_off, g.n_waves,
+                         (const int8_t*)llr, p->d_surv, (int64_t*)metric, end_state,
+                         p->d_item_end, st);
+    else if (g.kern == kKernRot2)
+      e = launch_fwd_rot(g.K, g.beta, is_int, kRotMode[p->variant], p->d_codes, p->d_items,
+                         p->d_waves + g.wave_off,
                          g.n_waves, llr, p->d_surv, metric, end_state, p->d_item_end, st);
     else
       e = launch_fwd(g.kern == kKernGeneric4 ? 4 : 2, g.nsl, is_int, p->d_codes,
@@ -374,8 +435,12 @@ mivit_status mivit_traceback(mivit_plan* p, uint32_t* bits, void* stream) {
   if (!bits) return MIVIT_EINVAL;
   DeviceGuard guard(p->device);
   for (const PlanGroup& g : p->groups) {
-    hipError_t e = launch_tb_seg(g.layout, p->d_codes, p->d_items + g.first, g.count, p->d_surv,
-                                 p->d_item_end, bits, kWarmStages, (hipStream_t)stream);
+    hipError_t e =
+        g.kern == kKernRot4P
+            ? launch_tb_r4p(g.K, p->d_items, p->d_pairs + g.pair_off, g.n_pairs, p->d_surv,
+                            p->d_item_end, bits, kWarmStages, (hipStream_t)stream)
+            : launch_tb_seg(g.layout, p->d_codes, p->d_items + g.first, g.count, p->d_surv,
+                            p->d_item_end, bits, kWarmStages, (hipStream_t)stream);
     if (e != hipSuccess) return MIVIT_EHIP;
   }
   return MIVIT_OK;

@@ -89,13 +89,34 @@ __device__ __forceinline__ void pair_fetch(typename Ty<INT>::T x, int addr_e, in
   o = Ty<INT>::from(oi);
 }
 
-template <int KM1, bool INT, int NP>
+// Fetch the metric of the partner lane (lane XOR 2^Q).  XOR 1, 2 and 8 are
+// single DPP patterns (fused by the compiler into the consuming subtract).
+template <int Q, bool INT>
+__device__ __forceinline__ typename Ty<INT>::T partner_fetch(typename Ty<INT>::T x, int addr_p) {
+  const int xi = Ty<INT>::bits(x);
+  int pi;
+  if constexpr (Q == 0) {
+    pi = __builtin_amdgcn_mov_dpp(xi, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
+  } else if constexpr (Q == 1) {
+    pi = __builtin_amdgcn_mov_dpp(xi, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
+  } else if constexpr (Q == 3) {
+    pi = __builtin_amdgcn_mov_dpp(xi, 0x128, 0xF, 0xF, true);  // row_ror:8
+  } else if constexpr (Q == 2 || Q == 4) {
+    pi = __builtin_amdgcn_ds_swizzle(xi, 0x1F | ((1 << Q) << 10));  // xor mode
+  } else {
+    pi = __builtin_amdgcn_ds_bpermute(addr_p, xi);
+  }
+  return Ty<INT>::from(pi);
+}
+
+template <int KM1, bool INT, int NP, int MODE>
 struct Frame {
   using T = typename Ty<INT>::T;
   T pm;
   uint32_t acc;
   int pat_off[KM1];  // LDS word offset of this lane's pattern, per phase
-  int addr_e, addr_o;
+  int addr_e, addr_o, addr_p;
+  uint64_t bmask[KM1];  // lanes whose bit q is set, per phase q
 };
 
 // Shift a decision into a lane's word: acc = 2*acc + d in one add-with-carry,
@@ -110,9 +131,83 @@ __device__ __forceinline__ uint32_t push_decision(uint32_t acc, uint64_t mask) {
   return out;
 }
 
+// Mode 2 picks, per lane bit, the cheapest exchange that stays in the VALU:
+//   bits 0, 1  both previous-state metrics by DPP quad permutations (fixed roles)
+//   bit 2      partner (lane ^ 4) = quad reverse of the row half-mirror (two DPPs)
+//   bit 3      partner (lane ^ 8) = DPP row rotate by 8
+//   bits 4, 5  v_permlane16_swap / v_permlane32_swap of the metric and a copy:
+//              one register receives the even rows (halves), the other the odd
+template <int Q>
+struct Mode2 {
+  static constexpr bool fixed_roles = (Q == 0 || Q == 1 || Q == 4 || Q == 5);
+};
+
+template <int Q, bool INT>
+__device__ __forceinline__ void pair_fetch_valu(typename Ty<INT>::T x, typename Ty<INT>::T& e,
+                                                typename Ty<INT>::T& o) {
+  const int xi = Ty<INT>::bits(x);
+  int ei, oi;
+  if constexpr (Q == 0) {
+    ei = __builtin_amdgcn_mov_dpp(xi, 0xA0, 0xF, 0xF, true);
+    oi = __builtin_amdgcn_mov_dpp(xi, 0xF5, 0xF, 0xF, true);
+  } else if constexpr (Q == 1) {
+    ei = __builtin_amdgcn_mov_dpp(xi, 0x44, 0xF, 0xF, true);
+    oi = __builtin_amdgcn_mov_dpp(xi, 0xEE, 0xF, 0xF, true);
+  } else if constexpr (Q == 4) {
+    auto r = __builtin_amdgcn_permlane16_swap(xi, xi, false, false);
+    ei = r[0];
+    oi = r[1];
+  } else {
+    auto r = __builtin_amdgcn_permlane32_swap(xi, xi, false, false);
+    ei = r[0];
+    oi = r[1];
+  }
+  e = Ty<INT>::from(ei);
+  o = Ty<INT>::from(oi);
+}
+
+template <int Q, bool INT>
+__device__ __forceinline__ typename Ty<INT>::T partner_fetch_valu(typename Ty<INT>::T x) {
+  const int xi = Ty<INT>::bits(x);
+  int pi;
+  if constexpr (Q == 2) {
+    const int hm = __builtin_amdgcn_mov_dpp(xi, 0x141, 0xF, 0xF, true);  // row_half_mirror: ^7
+    pi = __builtin_amdgcn_mov_dpp(hm, 0x1B, 0xF, 0xF, true);            // quad_perm [3,2,1,0]: ^3
+  } else {
+    pi = __builtin_amdgcn_mov_dpp(xi, 0x128, 0xF, 0xF, true);  // row_ror:8
+  }
+  return Ty<INT>::from(pi);
+}
+
+template <typename T>
+__device__ __forceinline__ T tmax(T a, T b) {
+  return a > b ? a : b;
+}
+
+// One stage at phase Q, own/partner form.  The lane keeps its own previous
+// state's metric and fetches its partner's.  With m0 the Eq. (BM) value of
+// the even previous state on input 0, the candidate through the lane's own
+// previous state is own + m0 and through the partner's is partner - m0, in
+// every lane (the corollary flips the sign once for the odd state and once
+// for input 1).  The new metric is the larger one; the decision "the odd
+// previous state won" is partner > own where the lane's bit Q is 0 (partner
+// odd) and own > partner where it is 1 (own odd), strict either way, so a tie
+// keeps the even state.
+template <int KM1, bool INT, int NP, int MODE, int Q>
+__device__ __forceinline__ void stage_op(Frame<KM1, INT, NP, MODE>& F, typename Ty<INT>::T m0) {
+  using T = typename Ty<INT>::T;
+  const T cp = partner_fetch<Q, INT>(F.pm, F.addr_p) - m0;
+  const T co = F.pm + m0;
+  F.pm = tmax(co, cp);
+  const uint64_t g1 = __builtin_amdgcn_ballot_w64(cp > co);
+  const uint64_t g2 = __builtin_amdgcn_ballot_w64(co > cp);
+  const uint64_t d = (g1 & ~F.bmask[Q]) | (g2 & F.bmask[Q]);
+  F.acc = push_decision(F.acc, d);
+}
+
 // One stage at phase Q: add, compare, select, record.
-template <int KM1, bool INT, int NP, int Q>
-__device__ __forceinline__ void stage(Frame<KM1, INT, NP>& F, typename Ty<INT>::T bm) {
+template <int KM1, bool INT, int NP, int MODE, int Q>
+__device__ __forceinline__ void stage(Frame<KM1, INT, NP, MODE>& F, typename Ty<INT>::T bm) {
   using T = typename Ty<INT>::T;
   T e, o;
   pair_fetch<Q, INT>(F.pm, F.addr_e, F.addr_o, e, o);
@@ -123,29 +218,63 @@ __device__ __forceinline__ void stage(Frame<KM1, INT, NP>& F, typename Ty<INT>::
   F.acc = push_decision(F.acc, __builtin_amdgcn_ballot_w64(d));
 }
 
-template <int KM1, bool INT, int NP, int P0, int K0>
-__device__ __forceinline__ void stages_full(Frame<KM1, INT, NP>& F,
+// Mode 2 stage: fixed roles (both metrics fetched) or own/partner.
+template <int KM1, bool INT, int NP, int MODE, int Q>
+__device__ __forceinline__ void stage_m2(Frame<KM1, INT, NP, MODE>& F, typename Ty<INT>::T bm) {
+  using T = typename Ty<INT>::T;
+  if constexpr (Mode2<Q>::fixed_roles) {
+    T e, o;
+    pair_fetch_valu<Q, INT>(F.pm, e, o);
+    const T ce = e + bm;
+    const T co = o - bm;
+    const bool d = co > ce;
+    F.pm = d ? co : ce;
+    F.acc = push_decision(F.acc, __builtin_amdgcn_ballot_w64(d));
+  } else {
+    const T cp = partner_fetch_valu<Q, INT>(F.pm) - bm;
+    const T co = F.pm + bm;
+    F.pm = tmax(co, cp);
+    const uint64_t g1 = __builtin_amdgcn_ballot_w64(cp > co);
+    const uint64_t g2 = __builtin_amdgcn_ballot_w64(co > cp);
+    const uint64_t d = (g1 & ~F.bmask[Q]) | (g2 & F.bmask[Q]);
+    F.acc = push_decision(F.acc, d);
+  }
+}
+
+template <int KM1, bool INT, int NP, int MODE, int Q>
+__device__ __forceinline__ void stage_any(Frame<KM1, INT, NP, MODE>& F, typename Ty<INT>::T bm) {
+  if constexpr (MODE == 2)
+    stage_m2<KM1, INT, NP, MODE, Q>(F, bm);
+  else if constexpr (MODE == 1)
+    stage_op<KM1, INT, NP, MODE, Q>(F, bm);
+  else
+    stage<KM1, INT, NP, MODE, Q>(F, bm);
+}
+
+template <int KM1, bool INT, int NP, int MODE, int P0, int K0>
+__device__ __forceinline__ void stages_full(Frame<KM1, INT, NP, MODE>& F,
                                             const typename Ty<INT>::T* bmv) {
   if constexpr (K0 < 32) {
-    stage<KM1, INT, NP, (P0 + K0) % KM1>(F, bmv[K0]);
-    stages_full<KM1, INT, NP, P0, K0 + 1>(F, bmv);
+    stage_any<KM1, INT, NP, MODE, (P0 + K0) % KM1>(F, bmv[K0]);
+    stages_full<KM1, INT, NP, MODE, P0, K0 + 1>(F, bmv);
   }
 }
 
 // A stage whose phase is only known at run time (the last, partial block).
-template <int KM1, bool INT, int NP, int Q>
-__device__ __forceinline__ void stage_dyn(Frame<KM1, INT, NP>& F, const typename Ty<INT>::T* bmrow,
+template <int KM1, bool INT, int NP, int MODE, int Q>
+__device__ __forceinline__ void stage_dyn(Frame<KM1, INT, NP, MODE>& F, const typename Ty<INT>::T* bmrow,
                                           int q) {
   if constexpr (Q < KM1) {
-    if (q == Q)
-      stage<KM1, INT, NP, Q>(F, bmrow[F.pat_off[Q]]);
-    else
-      stage_dyn<KM1, INT, NP, Q + 1>(F, bmrow, q);
+    if (q == Q) {
+      stage_any<KM1, INT, NP, MODE, Q>(F, bmrow[F.pat_off[Q]]);
+    } else {
+      stage_dyn<KM1, INT, NP, MODE, Q + 1>(F, bmrow, q);
+    }
   }
 }
 
-template <int KM1, bool INT, int NP, int P0>
-__device__ __forceinline__ void block(Frame<KM1, INT, NP>& F, const typename Ty<INT>::T* bmt,
+template <int KM1, bool INT, int NP, int MODE, int P0>
+__device__ __forceinline__ void block(Frame<KM1, INT, NP, MODE>& F, const typename Ty<INT>::T* bmt,
                                       int n) {
   using T = typename Ty<INT>::T;
   if (n == 32) {
@@ -153,17 +282,47 @@ __device__ __forceinline__ void block(Frame<KM1, INT, NP>& F, const typename Ty<
     T bmv[32];
 #pragma unroll
     for (int k = 0; k < 32; ++k) bmv[k] = bmt[k * NP + F.pat_off[(P0 + k) % KM1]];
-    stages_full<KM1, INT, NP, P0, 0>(F, bmv);
+    stages_full<KM1, INT, NP, MODE, P0, 0>(F, bmv);
   } else {
 #pragma unroll 1
-    for (int k = 0; k < n; ++k) stage_dyn<KM1, INT, NP, 0>(F, bmt + k * NP, (P0 + k) % KM1);
+    for (int k = 0; k < n; ++k) stage_dyn<KM1, INT, NP, MODE, 0>(F, bmt + k * NP, (P0 + k) % KM1);
   }
 }
 
-// State shared by the blocks of one wavefront.
+// Order LDS traffic between the lanes of one wavefront.  LDS instructions of
+// a wavefront execute in order, so a compiler-level fence at wavefront scope
+// is enough; unlike a workgroup barrier it does not wait for the outstanding
+// global loads that prefetch the next block.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Soft values of the stages a lane tabulates in one block: stages
+// sl + k*2^(K-1) for k < max(1, 32/2^(K-1)).
 template <int KM1, bool INT, int BETA>
+struct LlrRegs {
+  static constexpr int NS = 1 << KM1;
+  static constexpr int NSTG = NS >= 32 ? 1 : 32 / NS;
+  typename Ty<INT>::T v[NSTG][BETA];
+  __device__ __forceinline__ void load(const typename Ty<INT>::In* llr, int tb, int S, int sl,
+                                       bool valid) {
+#pragma unroll
+    for (int k = 0; k < NSTG; ++k) {
+      const int t = tb + sl + k * NS;
+      const bool ok = valid && sl + k * NS < 32 && t < S;
+#pragma unroll
+      for (int b = 0; b < BETA; ++b)
+        v[k][b] = ok ? (typename Ty<INT>::T)llr[(int64_t)t * BETA + b] : (typename Ty<INT>::T)0;
+    }
+  }
+};
+
+// State shared by the blocks of one wavefront.
+template <int KM1, bool INT, int BETA, int MODE>
 struct BlockCtx {
-  Frame<KM1, INT, (1 << BETA)>* F;
+  Frame<KM1, INT, (1 << BETA), MODE>* F;
   typename Ty<INT>::T* bmt;
   const typename Ty<INT>::In* llr;
   uint32_t* sv;
@@ -171,30 +330,33 @@ struct BlockCtx {
   int* blk;
   int S, sl, lane;
   bool valid;
+  LlrRegs<KM1, INT, BETA> lr;  // soft values of the current block, loaded a block ahead
 };
 
 // One block of up to 32 stages starting at tb, phase (32*BI) mod (K-1).
-template <int KM1, bool INT, int BETA, int BI>
-__device__ __forceinline__ void one_block(BlockCtx<KM1, INT, BETA>& bc, int tb) {
+template <int KM1, bool INT, int BETA, int MODE, int BI>
+__device__ __forceinline__ void one_block(BlockCtx<KM1, INT, BETA, MODE>& bc, int tb) {
   using T = typename Ty<INT>::T;
   constexpr int NS = 1 << KM1, NP = 1 << BETA;
+  constexpr int NSTG = LlrRegs<KM1, INT, BETA>::NSTG;
   const int n = min(32, bc.S - tb);
   // branch-metric table of this block: Eq. (BM) for every output pattern
-  for (int tt = bc.sl; tt < 32; tt += NS) {
-    if (tt < n && bc.valid) {
-      T l[BETA];
 #pragma unroll
-      for (int b = 0; b < BETA; ++b) l[b] = (T)bc.llr[(int64_t)(tb + tt) * BETA + b];
+  for (int k = 0; k < NSTG; ++k) {
+    const int tt = bc.sl + k * NS;
+    if (tt < 32) {
 #pragma unroll
       for (int p = 0; p < NP / 2; ++p) {
         T v = (T)0;
 #pragma unroll
-        for (int b = 0; b < BETA; ++b) v += ((p >> b) & 1) ? -l[b] : l[b];
+        for (int b = 0; b < BETA; ++b) v += ((p >> b) & 1) ? -bc.lr.v[k][b] : bc.lr.v[k][b];
         bc.bmt[tt * NP + p] = v;
         bc.bmt[tt * NP + (NP - 1 - p)] = -v;
       }
     }
   }
+  // the next block's soft values are read while this block runs
+  bc.lr.load(bc.llr, tb + 32, bc.S, bc.sl, bc.valid);
   if constexpr (INT) {
     if (tb > 0) {
       // renormalise by the metric of state 0 (always in the frame's lane 0)
@@ -203,21 +365,21 @@ __device__ __forceinline__ void one_block(BlockCtx<KM1, INT, BETA>& bc, int tb) 
       *bc.offset += ref;
     }
   }
-  __syncthreads();
-  block<KM1, INT, NP, (32 * BI) % KM1>(*bc.F, bc.bmt, n);
+  wave_sync();
+  block<KM1, INT, NP, MODE, (32 * BI) % KM1>(*bc.F, bc.bmt, n);
   if (bc.valid) bc.sv[(int64_t)(*bc.blk) * NS + bc.sl] = bc.F->acc << (32 - n);
   bc.F->acc = 0;
   ++*bc.blk;
-  __syncthreads();
+  wave_sync();
 }
 
-template <int KM1, bool INT, int BETA, int BI, int NB>
-__device__ __forceinline__ void super_block(BlockCtx<KM1, INT, BETA>& bc, int t0) {
+template <int KM1, bool INT, int BETA, int MODE, int BI, int NB>
+__device__ __forceinline__ void super_block(BlockCtx<KM1, INT, BETA, MODE>& bc, int t0) {
   if constexpr (BI < NB) {
     const int tb = t0 + 32 * BI;
     if (tb < bc.S) {
-      one_block<KM1, INT, BETA, BI>(bc, tb);
-      super_block<KM1, INT, BETA, BI + 1, NB>(bc, t0);
+      one_block<KM1, INT, BETA, MODE, BI>(bc, tb);
+      super_block<KM1, INT, BETA, MODE, BI + 1, NB>(bc, t0);
     }
   }
 }
@@ -226,10 +388,14 @@ constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
 
 }  // namespace rot
 
-template <int KM1, bool INT, int BETA>
-__global__ __launch_bounds__(64) void k_fwd_rot(const DevCode* __restrict__ codes,
+// Wavefronts per workgroup: four, one per SIMD, so that every SIMD of a CU
+// receives the same number of frames (the wavefronts share nothing).
+constexpr int kRotWaves = 4;
+
+template <int KM1, bool INT, int BETA, int MODE>
+__global__ __launch_bounds__(64 * kRotWaves) void k_fwd_rot(const DevCode* __restrict__ codes,
                                                 const Item* __restrict__ items,
-                                                const int2* __restrict__ waves,
+                                                const int2* __restrict__ waves, int n_waves,
                                                 const void* __restrict__ llr_v,
                                                 uint64_t* __restrict__ surv, void* metric,
                                                 int32_t* end_out, int32_t* item_end) {
@@ -240,13 +406,18 @@ __global__ __launch_bounds__(64) void k_fwd_rot(const DevCode* __restrict__ code
   constexpr int FPW = 64 / NS;
   constexpr int NP = 1 << BETA;
   constexpr int SUPER = 32 * KM1 / gcd_c(32, KM1);  // lcm(32, K-1)
-  __shared__ T bmt[FPW][32 * NP];
-  __shared__ T xpm[64];
+  __shared__ T bmt_all[kRotWaves][FPW][32 * NP];
+  __shared__ T xpm_all[kRotWaves][64];
 
-  const int lane = threadIdx.x;
+  const int wid = threadIdx.x >> 6;
+  const int wave = blockIdx.x * kRotWaves + wid;
+  if (wave >= n_waves) return;  // no workgroup barriers below: safe to leave
+  T(*bmt)[32 * NP] = bmt_all[wid];
+  T* xpm = xpm_all[wid];
+  const int lane = threadIdx.x & 63;
   const int fr = lane / NS, sl = lane % NS;
   // this wave's frames: waves[w] = (first item, count), all of equal length
-  const int2 wv = waves[blockIdx.x];
+  const int2 wv = waves[wave];
   const bool valid = fr < wv.y;
   const Item it = items[wv.x + (valid ? fr : 0)];
   const DevCode c = codes[it.code];
@@ -254,28 +425,37 @@ __global__ __launch_bounds__(64) void k_fwd_rot(const DevCode* __restrict__ code
   const In* llr = (const In*)llr_v + it.llr_off;
   uint32_t* sv = (uint32_t*)(surv + it.surv_off);
 
-  Frame<KM1, INT, NP> F;
+  Frame<KM1, INT, NP, MODE> F;
 #pragma unroll
   for (int q = 0; q < KM1; ++q) {
     const int j = rotr(sl, (q + 1) % KM1, KM1);  // state held after a phase-q stage
     const int ie = (j << 1) & (NS - 1);
     const int u = j >> (KM1 - 1);
-    F.pat_off[q] = branch_out(c, ie, u);
+    // fixed roles: the even previous state's branch into j; own/partner
+    // stages: its branch on input 0
+    const bool fixed = MODE == 0 || (MODE == 2 && (q == 0 || q == 1 || q == 4 || q == 5));
+    F.pat_off[q] = branch_out(c, ie, fixed ? u : 0);
+    uint64_t bm = 0;
+    for (int l = 0; l < 64; ++l)
+      if ((l >> q) & 1) bm |= 1ull << l;
+    F.bmask[q] = bm;
   }
   F.addr_e = (lane & ~32) << 2;
   F.addr_o = (lane | 32) << 2;
+  F.addr_p = (lane ^ 32) << 2;
   F.pm = (it.start_known && sl != 0) ? Ty<INT>::neg_unreachable() : (T)0;
   F.acc = 0;
   int64_t offset = 0;
   T* my_bmt = &bmt[fr][0];
 
   int blk = 0;
-  BlockCtx<KM1, INT, BETA> bc{&F, my_bmt, llr, sv, &offset, &blk, S, sl, lane, valid};
-  for (int t0 = 0; t0 < S; t0 += SUPER) super_block<KM1, INT, BETA, 0, SUPER / 32>(bc, t0);
+  BlockCtx<KM1, INT, BETA, MODE> bc{&F, my_bmt, llr, sv, &offset, &blk, S, sl, lane, valid, {}};
+  bc.lr.load(llr, 0, S, sl, valid);
+  for (int t0 = 0; t0 < S; t0 += SUPER) super_block<KM1, INT, BETA, MODE, 0, SUPER / 32>(bc, t0);
   // final metrics: lane sl holds state rotr(sl, S mod (K-1))
   const int st = rotr(sl, S % KM1, KM1);
   xpm[fr * NS + st] = F.pm;
-  __syncthreads();
+  wave_sync();
   if (sl == 0 && valid) {
     int js = it.end_state;
     if (js < 0) {
@@ -296,14 +476,22 @@ __global__ __launch_bounds__(64) void k_fwd_rot(const DevCode* __restrict__ code
   }
 }
 
-hipError_t launch_fwd_rot(int K, int beta, bool is_int, const DevCode* codes, const Item* items,
-                          const int2* waves, int n_waves, const void* llr, uint64_t* surv,
-                          void* metric, int32_t* end_out, int32_t* item_end, hipStream_t st) {
+hipError_t launch_fwd_rot(int K, int beta, bool is_int, int mode, const DevCode* codes,
+                          const Item* items, const int2* waves, int n_waves, const void* llr,
+                          uint64_t* surv, void* metric, int32_t* end_out, int32_t* item_end,
+                          hipStream_t st) {
   if (n_waves <= 0) return hipSuccess;
-  dim3 grid(n_waves), block(64);
-#define MV_ROT(KM1, I, B)                                                                      \
-  hipLaunchKernelGGL((k_fwd_rot<KM1, I, B>), grid, block, 0, st, codes, items, waves, llr, \
-                     surv, metric, end_out, item_end)
+  dim3 grid((n_waves + kRotWaves - 1) / kRotWaves), block(64 * kRotWaves);
+#define MV_ROT(KM1, I, B)                                                                     \
+  if (mode == 2)                                                                              \
+    hipLaunchKernelGGL((k_fwd_rot<KM1, I, B, 2>), grid, block, 0, st, codes, items, waves, n_waves, llr, \
+                       surv, metric, end_out, item_end);                                      \
+  else if (mode == 1)                                                                         \
+    hipLaunchKernelGGL((k_fwd_rot<KM1, I, B, 1>), grid, block, 0, st, codes, items, waves, n_waves, llr, \
+                       surv, metric, end_out, item_end);                                      \
+  else                                                                                        \
+    hipLaunchKernelGGL((k_fwd_rot<KM1, I, B, 0>), grid, block, 0, st, codes, items, waves, n_waves, llr, \
+                       surv, metric, end_out, item_end)
 #define MV_ROT_B(KM1, I)         \
   switch (beta) {                \
     case 2: MV_ROT(KM1, I, 2); break; \

@@ -1,0 +1,622 @@
+// Radix-4 forward procedure and traceback for int8 soft values, rate 1/2,
+// K = 5 or 7, with two frames packed in the 16-bit halves of every register.
+//
+// Trellis (§VIII-A, Eq. (radix4:S)).  Write a state of n = K-1 bits as n/2
+// base-4 digits.  One radix-4 iteration (two stages) maps the left state
+// i = 4f + y to the right state j = f + 2^(n-2) u, u = 2 u2 + u1 the two new
+// input bits: the lowest digit y of i is consumed, the others move down one
+// place and u enters on top.  A dragonfly group is the four left states that
+// differ in y and the four right states that differ in u.
+//
+// Rotating digit map.  At iteration it (phase ph = it mod n/2) the left state
+// i lives in lane rotl_n(i, 2 ph): its lowest digit sits in lane-digit slot
+// ph.  The right state j then lives in lane rotl_n(j, 2 (ph + 1)), which puts
+// its new top digit u in slot ph as well and leaves every other digit where
+// it was.  A dragonfly group is therefore the four lanes that differ only in
+// slot ph, and the right states stay in place: slot 0 (lane bits 0-1) is a
+// DPP quad broadcast, slot 1 (bits 2-3) a DPP row rotation by 4, 8, 12, and
+// slot 2 (bits 4-5) three v_permlane32/16_swap operations.
+//
+// Packed metrics.  Path metrics are unsigned 16-bit numbers, frame A in the
+// low and frame B in the high half of a VGPR.  A metric is stored as
+// 4 * (PM + offset) with offsets chosen so that every value stays in
+// [0, 65535]; adding two such words with one 32-bit add then never carries
+// between the halves, and v_pk_max_u16 compares both frames at once.  The
+// two low bits carry the tie tag 3 - y of the left state a candidate came
+// from: among equal metrics the larger tag, i.e. the smaller y, wins, which
+// is the lowest-index previous state of the paper's strict comparison, and
+// the winner's tag is the 2-bit decision.
+//
+// Branch metrics (Eq. (radix4:BM)).  For each iteration the 16 super-branch
+// metrics of a frame are the dot products of its four int8 soft values with
+// the +-1 sign rows of the 16 output patterns (v_dot4_i32_i8, signs scaled by
+// 4, bias 2048 so entries are >= 0); both frames share one LDS word per
+// pattern.  Every lane reads the four entries its candidates need.
+//
+// Range control.  Every 8 iterations the metric of state 0 (always lane 0 of
+// its lane group) is brought back to 16384 by a subtraction common to all
+// states of the frame; the subtracted amounts are accumulated exactly in
+// 64 bits and added back to the final metric.  With |l| <= 128 the spread of
+// reachable metrics is at most 2 (K-1) 2 128 (any state reaches any other in
+// K-1 stages), so values stay within [4093, 61443].
+//
+// Odd stage counts: stage 0 is a radix-2 stage evaluated in closed form
+// (the start metrics are either all zero or zero at state 0 only).  Its
+// decisions are never needed: the traceback emits stage 0's bit from the
+// state at time 1.
+//
+// Survivor layout of a frame pair (lane group of NS lanes): for each group
+// of 8 iterations, NS words; word G*NS + R holds, for the state in lane R
+// after iterations 8G..8G+7, the tags of frame A in bits 15..0 (iteration
+// 8G+k in bits 15-2k..14-2k) and of frame B in bits 31..16.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mivit_device.h"
+
+namespace mivit {
+
+namespace r4p {
+
+constexpr uint32_t kBase = 16384;
+constexpr uint32_t kBase2 = kBase | (kBase << 16);
+constexpr uint32_t kStrip = 0xFFFCFFFCu;
+constexpr uint32_t kTags = 0x00030003u;
+constexpr int kBias = 2048;   // 4 * max |super-branch metric| for |l| <= 128
+constexpr int kLeadOff = 256;  // max |branch metric| of one stage
+
+typedef unsigned short us2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pk_max(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(us2, a),
+                                                                __builtin_bit_cast(us2, b)));
+}
+
+__device__ __forceinline__ uint32_t pk_shl(uint32_t a, int s) {
+  const us2 sh = {(unsigned short)s, (unsigned short)s};
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(us2, a) << sh);
+}
+
+__device__ __forceinline__ int parity(uint32_t x) { return __popc(x) & 1; }
+
+// beta = 2 output bits of the branch leaving state i on input u (§II-A).
+__device__ __forceinline__ int branch_out2(const DevCode& c, int i, int u) {
+  const uint32_t reg = ((uint32_t)u << (c.K - 1)) | (uint32_t)i;
+  return parity(c.gen[0] & reg) | (parity(c.gen[1] & reg) << 1);
+}
+
+__device__ __forceinline__ int rotl_n(int x, int r, int n) {
+  return r == 0 ? x : (((x << r) | (x >> (n - r))) & ((1 << n) - 1));
+}
+__device__ __forceinline__ int rotr_n(int x, int r, int n) { return rotl_n(x, (n - r) % n, n); }
+
+// The four metrics a lane combines at phase PH, from the lanes that differ
+// from it in lane-digit slot PH.  Applied to lane ids it names those lanes.
+template <int PH>
+__device__ __forceinline__ void fetch4(uint32_t x, uint32_t (&o)[4]) {
+  if constexpr (PH == 0) {
+    o[0] = __builtin_amdgcn_mov_dpp((int)x, 0x00, 0xF, 0xF, true);  // quad_perm [0,0,0,0]
+    o[1] = __builtin_amdgcn_mov_dpp((int)x, 0x55, 0xF, 0xF, true);  // quad_perm [1,1,1,1]
+    o[2] = __builtin_amdgcn_mov_dpp((int)x, 0xAA, 0xF, 0xF, true);  // quad_perm [2,2,2,2]
+    o[3] = __builtin_amdgcn_mov_dpp((int)x, 0xFF, 0xF, 0xF, true);  // quad_perm [3,3,3,3]
+  } else if constexpr (PH == 1) {
+    o[0] = x;
+    o[1] = __builtin_amdgcn_mov_dpp((int)x, 0x124, 0xF, 0xF, true);  // row_ror:4
+    o[2] = __builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, true);  // row_ror:8
+    o[3] = __builtin_amdgcn_mov_dpp((int)x, 0x12C, 0xF, 0xF, true);  // row_ror:12
+  } else {
+    // rows (r0 r1 r2 r3) -> (r0 r1 r0 r1), (r2 r3 r2 r3) -> each row everywhere
+    const auto h = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    const auto a = __builtin_amdgcn_permlane16_swap(h[0], h[0], false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(h[1], h[1], false, false);
+    o[0] = a[0];
+    o[1] = a[1];
+    o[2] = b[0];
+    o[3] = b[1];
+  }
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Four int8 soft values of one iteration; any alignment.
+__device__ __forceinline__ uint32_t load_llr4(const int8_t* p) {
+  uint32_t w;
+  __builtin_memcpy(&w, p, 4);
+  return w;
+}
+
+template <int ND>
+struct Fwd {
+  static constexpr int KM1 = 2 * ND;
+  static constexpr int NS = 1 << KM1;
+  static constexpr int PPL = 256 / NS;  // table entries a lane fills per block
+
+  const uint32_t* tp[ND][4];  // LDS table entry of candidate k at phase ph (block row 0)
+  uint32_t tag[ND];           // tie tag of the state a lane holds entering phase ph
+  int32_t sgn[PPL];           // sign rows (+-4 per soft value) of this lane's patterns
+  uint32_t* tbl;              // this lane group's table: 16 rows x 16 patterns
+  int ib;                     // table row this lane fills
+  const int8_t* l0;           // soft values of iteration 0, frame A / B
+  const int8_t* l1;
+  uint32_t w0, w1;            // soft values of this lane's row, current block
+  uint32_t V;                 // packed metrics, tagged for the next iteration
+  uint32_t acc;               // decisions of the current group of 8 iterations
+  uint32_t* sv;               // survivor words of the lane group
+  int r, n_it;
+  bool store;
+  uint64_t off0, off1;        // accumulated renormalisation amounts
+};
+
+template <int ND, int PH>
+__device__ __forceinline__ void iterate(Fwd<ND>& F, int row) {
+  uint32_t o[4];
+  fetch4<PH>(F.V, o);
+  const uint32_t c0 = o[0] + F.tp[PH][0][row * 16];
+  const uint32_t c1 = o[1] + F.tp[PH][1][row * 16];
+  const uint32_t c2 = o[2] + F.tp[PH][2][row * 16];
+  const uint32_t c3 = o[3] + F.tp[PH][3][row * 16];
+  const uint32_t v = pk_max(pk_max(c0, c1), pk_max(c2, c3));
+  F.acc = (F.acc << 2) | (v & kTags);
+  F.V = (v & kStrip) | F.tag[(PH + 1) % ND];
+}
+
+template <int ND>
+__device__ __forceinline__ void iterate_dyn(Fwd<ND>& F, int row, int ph) {
+  if (ph == 0) {
+    iterate<ND, 0>(F, row);
+  } else if (ph == 1) {
+    iterate<ND, 1 % ND>(F, row);
+  } else {
+    iterate<ND, 2 % ND>(F, row);
+  }
+}
+
+// End of a group of iterations ending at iteration `last`.
+template <int ND>
+__device__ __forceinline__ void group_end(Fwd<ND>& F, int last) {
+  constexpr int NS = Fwd<ND>::NS;
+  const int n = (last & 7) + 1;
+  if (F.store) F.sv[(last >> 3) * NS + F.r] = n == 8 ? F.acc : pk_shl(F.acc, 2 * (8 - n));
+  F.acc = 0;
+  if (n == 8) {
+    // bring state 0 (lane 0 of the group) back to kBase in both halves
+    if constexpr (NS == 64) {
+      const uint32_t ref = __builtin_amdgcn_readfirstlane(F.V);  // lane 0
+      const uint32_t d = (ref & kStrip) - kBase2;
+      F.V -= d;
+      F.off0 += d & 0xFFFFu;
+      F.off1 += d >> 16;
+    } else {
+      const int src = (int)((threadIdx.x & 63) & ~(NS - 1)) << 2;
+      const uint32_t ref = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)F.V);
+      const uint32_t d = (ref & kStrip) - kBase2;
+      F.V -= d;
+      F.off0 += d & 0xFFFFu;
+      F.off1 += d >> 16;
+    }
+  }
+}
+
+// Iterations Q..15 of a full block (straight-line code, static phases).
+template <int ND, int P0, int Q>
+__device__ __forceinline__ void iterate_full(Fwd<ND>& F, int it0) {
+  if constexpr (Q < 16) {
+    iterate<ND, (P0 + Q) % ND>(F, Q);
+    if constexpr ((Q & 7) == 7) group_end<ND>(F, it0 + Q);
+    iterate_full<ND, P0, Q + 1>(F, it0);
+  }
+}
+
+// One block of up to 16 iterations from it0; P0 = phase of it0.
+template <int ND, int P0>
+__device__ __forceinline__ void block(Fwd<ND>& F, int it0) {
+  constexpr int PPL = Fwd<ND>::PPL;
+  // super-branch metric table of the block
+  {
+    uint32_t t[PPL];
+#pragma unroll
+    for (int e = 0; e < PPL; ++e) {
+      const uint32_t a = (uint32_t)__builtin_amdgcn_sdot4((int)F.w0, F.sgn[e], kBias, false);
+      const uint32_t b = (uint32_t)__builtin_amdgcn_sdot4((int)F.w1, F.sgn[e], kBias, false);
+      t[e] = a | (b << 16);
+    }
+    uint4* dst = (uint4*)(F.tbl + F.ib * 16 + (F.r >> 4) * PPL);
+#pragma unroll
+    for (int e = 0; e < PPL / 4; ++e) dst[e] = make_uint4(t[4 * e], t[4 * e + 1], t[4 * e + 2], t[4 * e + 3]);
+  }
+  // soft values of the next block
+  {
+    const int itn = it0 + 16 + F.ib;
+    const bool ok = itn < F.n_it;
+    F.w0 = ok ? load_llr4(F.l0 + 4 * (int64_t)itn) : 0u;
+    F.w1 = ok ? load_llr4(F.l1 + 4 * (int64_t)itn) : 0u;
+  }
+  wave_sync();
+  const int n = min(16, F.n_it - it0);
+  if (n == 16) {
+    iterate_full<ND, P0, 0>(F, it0);
+  } else {
+#pragma unroll 1
+    for (int q = 0; q < n; ++q) {
+      iterate_dyn<ND>(F, q, (P0 + q) % ND);
+      if ((q & 7) == 7 || q == n - 1) group_end<ND>(F, it0 + q);
+    }
+  }
+  wave_sync();
+}
+
+template <int ND, int B, int NB>
+__device__ __forceinline__ void super_block(Fwd<ND>& F, int it0) {
+  if constexpr (B < NB) {
+    const int itb = it0 + 16 * B;
+    if (itb < F.n_it) {
+      block<ND, (16 * B) % ND>(F, itb);
+      super_block<ND, B + 1, NB>(F, it0);
+    }
+  }
+}
+
+template <int ND, int PH>
+__device__ __forceinline__ void lane_consts(Fwd<ND>& F, const DevCode& c, int lane, int r) {
+  constexpr int KM1 = Fwd<ND>::KM1, NS = Fwd<ND>::NS;
+  if constexpr (PH < ND) {
+    uint32_t src[4];
+    fetch4<PH>((uint32_t)lane, src);
+    const int j = rotr_n(r, (2 * (PH + 1)) % KM1, KM1);  // right state held after the iteration
+    const int u = j >> (KM1 - 2);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = rotr_n((int)src[k] & (NS - 1), (2 * PH) % KM1, KM1);  // left state in that lane
+      const int mid = ((u & 1) << (KM1 - 1)) | (i >> 1);
+      const int p = branch_out2(c, i, u & 1) | (branch_out2(c, mid, u >> 1) << 2);
+      F.tp[PH][k] = F.tbl + p;
+    }
+    const int s = rotr_n(r, (2 * PH) % KM1, KM1);  // left state held entering the iteration
+    F.tag[PH] = (uint32_t)(3 - (s & 3)) * 0x10001u;
+    lane_consts<ND, PH + 1>(F, c, lane, r);
+  }
+}
+
+constexpr int kR4Waves = 4;
+
+}  // namespace r4p
+
+// One wavefront decodes up to 2 * 64 / 2^(K-1) frames of equal length:
+// lane group m (2^(K-1) lanes) holds frames 2m (low halves) and 2m+1 (high).
+template <int ND>
+__global__ __launch_bounds__(64 * r4p::kR4Waves) void k_fwd_r4p(
+    const DevCode* __restrict__ codes, const Item* __restrict__ items,
+    const int2* __restrict__ waves, int n_waves, const int8_t* __restrict__ llr,
+    uint64_t* __restrict__ surv, int64_t* metric, int32_t* end_out, int32_t* item_end) {
+  using namespace r4p;
+  constexpr int KM1 = 2 * ND, NS = 1 << KM1, FPG = 64 / NS, PPL = 256 / NS;
+  __shared__ uint32_t tbl_all[kR4Waves][FPG][16 * 16];
+
+  const int wid = threadIdx.x >> 6;
+  const int wave = blockIdx.x * kR4Waves + wid;
+  if (wave >= n_waves) return;  // no workgroup barriers below
+  const int lane = threadIdx.x & 63;
+  const int m = lane / NS, r = lane % NS;
+  const int2 wv = waves[wave];
+  const bool va = 2 * m < wv.y, vb = 2 * m + 1 < wv.y;
+  const int ia = wv.x + (va ? 2 * m : 0);
+  const int ib_ = vb ? ia + 1 : ia;  // a missing frame B repeats frame A
+  const Item ita = items[ia], itb = items[ib_];
+  const DevCode c = codes[ita.code];
+  const int S = __builtin_amdgcn_readfirstlane(ita.n_stages);  // equal within the wave
+  const int lead = S & 1, n_it = S >> 1;
+
+  Fwd<ND> F;
+  F.tbl = &tbl_all[wid][m][0];
+  F.r = r;
+  F.n_it = n_it;
+  F.ib = r & 15;
+  F.store = va;
+  F.sv = (uint32_t*)(surv + ita.surv_off);
+  F.l0 = llr + ita.llr_off + 2 * lead;
+  F.l1 = llr + itb.llr_off + 2 * lead;
+  F.off0 = F.off1 = 0;
+  F.acc = 0;
+#pragma unroll
+  for (int e = 0; e < PPL; ++e) {
+    const int p = (r >> 4) * PPL + e;
+    uint32_t s = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) s |= (((p >> b) & 1) ? 0xFCu : 0x04u) << (8 * b);
+    F.sgn[e] = (int32_t)s;
+  }
+  lane_consts<ND, 0>(F, c, lane, r);
+
+  // metrics entering iteration 0 (lane r holds state r)
+  {
+    const int j = r;
+    uint32_t v[2];
+    const Item* its[2] = {&ita, &itb};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const bool known = its[h]->start_known != 0;
+      if (lead) {
+        const int8_t* p = llr + its[h]->llr_off;
+        const int i0 = (j << 1) & (NS - 1);
+        const int w = branch_out2(c, i0, j >> (KM1 - 1));
+        const int bm = ((w & 1) ? -(int)p[0] : (int)p[0]) + ((w & 2) ? -(int)p[1] : (int)p[1]);
+        int pm;
+        bool reach = true;
+        if (known) {
+          reach = i0 == 0;
+          pm = bm;
+        } else {
+          pm = bm < 0 ? -bm : bm;  // max(bm, -bm): the two branches into j
+        }
+        v[h] = reach ? kBase + 4u * (uint32_t)(pm + kLeadOff) : 0u;
+      } else {
+        v[h] = (!known || j == 0) ? kBase : 0u;
+      }
+    }
+    F.V = v[0] | (v[1] << 16) | F.tag[0];
+  }
+  {
+    const bool ok = F.ib < n_it;
+    F.w0 = ok ? load_llr4(F.l0 + 4 * F.ib) : 0u;
+    F.w1 = ok ? load_llr4(F.l1 + 4 * F.ib) : 0u;
+  }
+  constexpr int SUPER = (ND == 3) ? 3 : 1;  // blocks per period of the phase pattern
+  for (int it0 = 0; it0 < n_it; it0 += 16 * SUPER) super_block<ND, 0, SUPER>(F, it0);
+
+  // final metrics: lane r holds state rotr(r, 2 (n_it mod ND))
+  const int js_lane = rotr_n(r, (2 * (n_it % ND)) % KM1, KM1);
+  const uint32_t vs = F.V & kStrip;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const Item& it = h ? itb : ita;
+    const bool valid = h ? vb : va;
+    const uint32_t val = (vs >> (16 * h)) & 0xFFFFu;
+    uint32_t key = (val << 8) | (uint32_t)(255 - js_lane);
+#pragma unroll
+    for (int o = 1; o < NS; o <<= 1) {
+      const uint32_t other = (uint32_t)__shfl_xor((int)key, o);
+      key = other > key ? other : key;
+    }
+    const bool fixed = it.end_state >= 0;
+    const int js = fixed ? it.end_state : 255 - (int)(key & 255);
+    const int src = m * NS + rotl_n(js & (NS - 1), (2 * (n_it % ND)) % KM1, KM1);
+    const uint32_t vfix = (uint32_t)__shfl((int)val, src);
+    const uint32_t vbest = fixed ? vfix : key >> 8;
+    if (r == 0 && valid) {
+      item_end[it.slot] = js;
+      if (it.frame >= 0) {
+        if (end_out) end_out[it.frame] = js;
+        if (metric) {
+          const int64_t o = (int64_t)(h ? F.off1 : F.off0);
+          metric[it.frame] = ((int64_t)vbest - (int64_t)kBase + o) / 4 -
+                             (int64_t)(kBias / 4) * n_it - (int64_t)kLeadOff * lead;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Traceback of a frame pair (Algorithm 2), 32 segments per frame.
+//
+// Lanes g and g+32 trace segment g of frames A and B; both frames of a pair
+// share their survivor words, so the two lanes share each staged block of 64
+// words: lane g streams its 16-byte chunks 0, 2, .., 14 and lane g+32 chunks
+// 1, 3, .., 15 into LDS (global_load_lds).  Word w of the block then sits at
+// byte ((w & 3) << 2) | ((w & ~3) << 7) + 16 g of the buffer.  The chase
+// keeps its state as that byte offset (for the word of its lane in the
+// current group), so taking a step only replaces one 2-bit field: the digit
+// slot the iteration consumed.  Segment boundaries, speculation and repair as
+// in the radix-2 traceback: lane g starts `warm` stages above its segment
+// from state 0, and a lane whose state at its upper boundary disagrees with
+// the (exact) lane above traces again from that lane's state.
+// ---------------------------------------------------------------------------
+namespace r4p {
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+template <int ND>
+struct Tb {
+  static constexpr int KM1 = 2 * ND, NS = 1 << KM1;
+  static constexpr int IPB = 512 / NS;  // iterations per staged block
+};
+
+__device__ __forceinline__ uint32_t addr_of(int R) {
+  return (uint32_t)(((R & 3) << 2) | ((R & ~3) << 7));
+}
+__device__ __forceinline__ int lane_of(uint32_t A) {
+  return (int)(((A >> 2) & 3) | ((A >> 7) & ~3));
+}
+// byte position of lane-digit slot s in the offset form
+__device__ __forceinline__ int slot_pos(int s) { return s == 0 ? 2 : (s == 1 ? 9 : 11); }
+
+struct Emit {
+  uint32_t word = 0;
+  __device__ __forceinline__ void put(int k, uint32_t bit, uint32_t* bits, int64_t bit_off) {
+    word |= bit << (k & 31);
+    if ((k & 31) == 0) {
+      bits[(bit_off + k) >> 5] = word;
+      word = 0;
+    }
+  }
+};
+
+struct Chase {
+  int hi, lo;       // iterations hi-1 down to lo are traced (lo >= 0)
+  int a, b;         // stages [a, b) are emitted
+  int PX, PY;       // iteration tops (time lead + 2P) where X and Y are taken
+  uint32_t A;       // current state (offset form) at time lead + 2*(current top)
+  uint32_t X, Y;
+  bool emit;
+};
+
+template <int ND>
+__device__ __forceinline__ void fetch_half(const uint32_t* blk, uint32_t* buf, int hb) {
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+    __builtin_amdgcn_global_load_lds((const void*)(blk + 4 * (2 * c + hb)), (lds_ptr_t)(buf + c * 256),
+                                     16, 0, 0);
+}
+
+// All lanes whose pair has work chase their range in lockstep rounds; lanes
+// with go set update c and emit.  The stage-0 bit of an odd stage count is
+// the top bit of the state at time 1, where the chase of iteration 0 ends.
+template <int ND>
+__device__ __forceinline__ void chase_all(Chase& c, bool go, bool pair_go, const uint32_t* sv,
+                                          uint32_t* lds, int lead, int h, int g, int ob,
+                                          uint32_t* bits, int64_t bit_off) {
+  constexpr int KM1 = Tb<ND>::KM1, NS = Tb<ND>::NS, IPB = Tb<ND>::IPB;
+  const int lane = threadIdx.x & 63;
+  Emit em;
+  const int B0 = pair_go ? (c.hi - 1) / IPB : 0;
+  const int nb = pair_go ? B0 - c.lo / IPB + 1 : 0;
+  int P = c.hi;
+  uint32_t A = go ? c.A : 0u;
+  if (go && P == c.PY) c.Y = A;
+  if (go && P == c.PX) c.X = A;
+  const int hb = lane >> 5;
+  if (nb > 0) fetch_half<ND>(sv + (int64_t)B0 * 64, lds, hb);
+  for (int rd = 0;; ++rd) {
+    if (__ballot(rd < nb) == 0) break;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    wave_sync();
+    const uint32_t base = (uint32_t)((rd & 1) * 8192 + g * 16);
+    uint32_t* nxt = lds + ((rd + 1) & 1) * 2048;
+    if (rd + 1 < nb) fetch_half<ND>(sv + (int64_t)(B0 - rd - 1) * 64, nxt, hb);
+    if (rd < nb) {
+      const int B = B0 - rd;
+      const int lo = max(c.lo, B * IPB);
+      for (; P > lo; --P) {
+        const int it = P - 1;
+        const int pos = slot_pos(it % ND);
+        const uint32_t goff = (uint32_t)(((it >> 3) & (64 / NS - 1)) << 11);
+        const uint32_t word = *(const uint32_t*)((const char*)lds + base + goff + A);
+        const uint32_t tag = (word >> (16 * h + 2 * (7 - (it & 7)))) & 3u;
+        const uint32_t u = (A >> pos) & 3u;
+        A = (A | (3u << pos)) - (tag << pos);
+        if (go && c.emit) {
+          const int s1 = lead + 2 * it + 1, s0 = s1 - 1;
+          if (s1 >= c.a && s1 < c.b) em.put(s1 - ob, u >> 1, bits, bit_off);
+          if (s0 >= c.a && s0 < c.b) em.put(s0 - ob, u & 1u, bits, bit_off);
+        }
+        if (go && it == c.PY) c.Y = A;
+        if (go && it == c.PX) c.X = A;
+      }
+    }
+    wave_sync();
+  }
+  if (go) {
+    c.A = A;
+    // time 1 holds state lane_of(A) (the phase-0 map is the identity)
+    if (c.emit && lead && c.lo == 0 && c.a <= 0 && c.b > 0)
+      em.put(-ob, (uint32_t)(lane_of(A) >> (KM1 - 1)), bits, bit_off);
+  }
+}
+
+}  // namespace r4p
+
+template <int ND>
+__global__ __launch_bounds__(64) void k_tb_r4p(const Item* __restrict__ items,
+                                               const int2* __restrict__ pairs,
+                                               const uint64_t* __restrict__ surv,
+                                               const int32_t* __restrict__ item_end,
+                                               uint32_t* __restrict__ bits, int warm) {
+  using namespace r4p;
+  constexpr int KM1 = 2 * ND;
+  __shared__ uint32_t lds[2 * 2048];
+  const int lane = threadIdx.x;
+  const int h = lane >> 5, g = lane & 31;
+  const int2 pr = pairs[blockIdx.x];
+  const bool have = h < pr.y;
+  const Item it = items[pr.x + (have ? h : 0)];
+  const int S = it.n_stages, ob = it.out_begin, n = it.n_out;
+  if (n <= 0) return;  // equal within the pair: the whole wavefront leaves
+  const int lead = S & 1, n_it = S >> 1;
+  const uint32_t* sv = (const uint32_t*)(surv + it.surv_off);
+  // segments of L stages (L a multiple of 32), at most 32 per frame
+  int G = min(32, (n + 31) / 32);
+  const int L = (((n + G - 1) / G) + 31) & ~31;
+  G = (n + L - 1) / L;
+  const bool active = g < G;
+  const int a = ob + g * L;
+  const int b = min(ob + (g + 1) * L, ob + n);
+  // pair-aligned times at or above a time t: lead + 2P
+  auto top_of = [&](int t) { return (t - lead + 1) >> 1; };  // smallest P with lead + 2P >= t
+  const bool exact = active && (g == G - 1);
+  int P_top = exact ? n_it : min(n_it, top_of(b + warm));
+  Chase c;
+  c.hi = active ? P_top : 0;
+  c.lo = max(0, (a - lead) >> 1);  // the iteration holding stage a (0: stage 0 of odd S)
+  c.a = a;
+  c.b = b;
+  c.PX = top_of(a);
+  c.PY = top_of(b);
+  c.emit = have;
+  c.X = c.Y = 0xFFFFFFFFu;
+  if (exact) {
+    const int js = item_end[it.slot];
+    c.A = addr_of(rotl_n(js, (2 * (n_it % ND)) % KM1, KM1));
+  } else {
+    c.A = 0;
+  }
+  bool go = active && c.hi > c.lo;
+  bool pair_go = go || __shfl_xor((int)go, 32);
+  chase_all<ND>(c, go, pair_go, sv, lds, lead, h, g, ob, bits, it.bit_off);
+  // repair: lane g is right when its state at its upper boundary equals the
+  // state lane g+1 reached at its lower boundary (the same time)
+  bool checked = exact;
+  constexpr uint32_t kStateBits = (uint32_t)((3 << 2) | (((1 << (2 * ND)) - 4) << 7));
+  for (int round = 0; round <= G; ++round) {
+    const uint32_t x_up = (uint32_t)__shfl_down((int)c.X, 1) & kStateBits;
+    const bool bad = active && !checked && g < G - 1 && c.Y != x_up;
+    if (__ballot(bad) == 0) break;
+    const bool pbad = bad || __shfl_xor((int)bad, 32);
+    Chase rc = c;
+    rc.hi = c.PY;
+    rc.A = x_up;
+    rc.Y = c.Y;
+    chase_all<ND>(rc, bad, pbad, sv, lds, lead, h, g, ob, bits, it.bit_off);
+    if (bad) {
+      c.A = rc.A;
+      c.X = rc.X;
+      c.Y = x_up;
+    }
+  }
+}
+
+hipError_t launch_fwd_r4p(int K, const DevCode* codes, const Item* items, const int2* waves,
+                          int n_waves, const int8_t* llr, uint64_t* surv, int64_t* metric,
+                          int32_t* end_out, int32_t* item_end, hipStream_t st) {
+  if (n_waves <= 0) return hipSuccess;
+  dim3 grid((n_waves + r4p::kR4Waves - 1) / r4p::kR4Waves), block(64 * r4p::kR4Waves);
+  if (K == 7)
+    hipLaunchKernelGGL(k_fwd_r4p<3>, grid, block, 0, st, codes, items, waves, n_waves, llr, surv,
+                       metric, end_out, item_end);
+  else if (K == 5)
+    hipLaunchKernelGGL(k_fwd_r4p<2>, grid, block, 0, st, codes, items, waves, n_waves, llr, surv,
+                       metric, end_out, item_end);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_tb_r4p(int K, const Item* items, const int2* pairs, int n_pairs,
+                         const uint64_t* surv, const int32_t* item_end, uint32_t* bits, int warm,
+                         hipStream_t st) {
+  if (n_pairs <= 0) return hipSuccess;
+  if (K == 7)
+    hipLaunchKernelGGL(k_tb_r4p<3>, dim3(n_pairs), dim3(64), 0, st, items, pairs, surv, item_end,
+                       bits, warm);
+  else if (K == 5)
+    hipLaunchKernelGGL(k_tb_r4p<2>, dim3(n_pairs), dim3(64), 0, st, items, pairs, surv, item_end,
+                       bits, warm);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace mivit

@@ -123,8 +123,8 @@ def _plan_decode(code, frames, llr_np, dtype, radix=0, chunk=0, overlap=0):
 
 
 @pytest.mark.parametrize("code", [CODE_K5, CODE_K7, CODE_K9], ids=cid)
-@pytest.mark.parametrize("dtype", ["f32", "i8"])
-def test_free_end_and_unknown_start(code, dtype):
+@pytest.mark.parametrize("dtype,radix", [("f32", 2), ("i8", 2), ("i8", 4)])
+def test_free_end_and_unknown_start(code, dtype, radix):
     """Frames with a best-state end and with an unknown start (all-zero
     initial metrics), mixed lengths in one plan."""
     rng = np.random.default_rng(5 + code.K)
@@ -144,7 +144,8 @@ def test_free_end_and_unknown_start(code, dtype):
     else:
         llr = rng.integers(-3, 4, off).astype(np.int8)
         mode = oracle.I64
-    _, bits, metric, end = _plan_decode(code, fr, llr, dtype)
+    print("free-end", cid(code), dtype, radix, flush=True)
+    _, bits, metric, end = _plan_decode(code, fr, llr, dtype, radix)
     ob, om, oend, _ = oracle.decode_frames([code], ofr, llr, mode, boff)
     np.testing.assert_array_equal(end, oend)
     np.testing.assert_array_equal(metric, om)
@@ -175,6 +176,52 @@ def test_chunked_stream(dtype):
         assert (bits != msg).sum() < 50
 
 
+@pytest.mark.parametrize("code", [CODE_K5, CODE_K7], ids=cid)
+def test_int8_radix4_extremes(code):
+    """Saturated soft values (+-127, -128 and runs of equal signs) over long
+    frames: the widest metric spread and many range-control steps."""
+    rng = np.random.default_rng(77 + code.K)
+    for n, F in [(5000, 3), (4093, 6), (255, 9)]:
+        S = n + code.K - 1
+        pick = rng.integers(0, 4, size=(F, S * code.beta))
+        vals = np.array([127, -127, -128, 0], np.int16)[pick]
+        runs = rng.integers(0, 2, size=(F, 1)) * rng.integers(-128, 128, size=(F, S * code.beta))
+        q = np.where(rng.random((F, S * code.beta)) < 0.3, runs, vals).astype(np.int8)
+        for variant in (0, 1):
+            print("extremes", cid(code), n, F, variant, flush=True)
+            fr = mv.uniform_frames(code, F, n, True)
+            plan = mv.Plan([code], fr, "i8", 4, variant=variant)
+            words, metric, _ = plan.decode(torch.from_numpy(q).to(DEV))
+            torch.cuda.synchronize()
+            nw = (n + 31) // 32
+            bits = mv.unpack_bits(words.cpu().numpy()[: F * nw].reshape(F, nw), n)
+            ob, om, _ = oracle.decode_uniform(code, q, n, True, oracle.I64)
+            np.testing.assert_array_equal(bits, ob)
+            np.testing.assert_array_equal(metric.cpu().numpy()[:F], om)
+
+
+@pytest.mark.parametrize("code", [CODE_K5, CODE_K7], ids=cid)
+def test_radix4_packed_vs_generic_windows(code):
+    """Chunked windows (unknown start, best end, emitted cores that differ
+    between equal-length windows) through the packed and the generic
+    radix-4 kernels, odd stage counts included; both equal the oracle."""
+    from workload import int8_scale_for
+    for n, chunk, ov in [(9001, 512, 64), (3001, 256, 33), (777, 2048, 64)]:
+        msg, llr = make_stream(code, n, 2.0, seed=31 + n)
+        q = oracle.quantize_i8(llr, int8_scale_for(2.0, 2))
+        t = torch.from_numpy(q).to(DEV)
+        ob, _, _ = oracle.decode_chunked(code, q, n, chunk, ov, oracle.I64)
+        for variant in (0, 1):
+            print("windows", cid(code), n, chunk, ov, variant, flush=True)
+            fr = np.zeros(1, mv.FRAME_DTYPE)
+            fr[0] = (0, 0, n, 0, n, 0, mv.MIVIT_START_KNOWN)
+            plan = mv.Plan([code], fr, "i8", 4, chunk, ov, variant=variant)
+            words, _, _ = plan.decode(t)
+            torch.cuda.synchronize()
+            bits = mv.unpack_bits(words.cpu().numpy(), n)
+            np.testing.assert_array_equal(bits, ob)
+
+
 def test_quantizer_exact():
     rng = np.random.default_rng(9)
     x = np.concatenate([
@@ -185,6 +232,25 @@ def test_quantizer_exact():
     for scale in (1.0, 0.37, 16 * 0.5011872336272722, 3.0):
         q_gpu = mv.quantize_i8(torch.from_numpy(x).to(DEV), scale).cpu().numpy()
         np.testing.assert_array_equal(q_gpu, oracle.quantize_i8(x, scale))
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("dtype", ["f32", "i8"])
+def test_kernel_variants_agree(dtype, variant):
+    """Every radix-2 forward variant gives the oracle's result (K=3..7)."""
+    from workload import int8_scale_for
+    for code in (Code.from_octal(3, ["7", "5"]), Code.from_octal(4, ["17", "13"]), CODE_K5,
+                 Code.from_octal(6, ["65", "57"]), CODE_K7):
+        b = make_uniform_batch(code, 16, 700, 1.0, seed=44)
+        llr = b.llr if dtype == "f32" else oracle.quantize_i8(b.llr, int8_scale_for(1.0, 2))
+        fr = mv.uniform_frames(code, 16, 700, True)
+        plan = mv.Plan([code], fr, dtype, 2, variant=variant)
+        words, metric, _ = plan.decode(torch.from_numpy(llr).to(DEV))
+        torch.cuda.synchronize()
+        bits = mv.unpack_bits(words.cpu().numpy()[: 16 * 22].reshape(16, 22), 700)
+        ob, om, _ = oracle.decode_uniform(code, llr, 700, True, oracle.F32 if dtype == "f32" else oracle.I64)
+        np.testing.assert_array_equal(bits, ob)
+        np.testing.assert_array_equal(metric.cpu().numpy()[:16], om)
 
 
 def test_determinism():
