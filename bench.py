@@ -9,7 +9,10 @@ add-compare-select, packed survivor decisions) plus traceback.
   value      int8 soft values, radix-4 forward (decoded info Gbit/s)
   variants   the same for float32 radix-2 and int8 radix-2
   roofline   the forward kernel of the headline variant against the vector
-             ALU peak: 3 ops per state per stage (add, add, compare-select)
+             ALU peak at the kernel's data width (packed 16-bit for the int8
+             radix-4 kernel): 3 ops per state per stage (add, add,
+             compare-select); traffic = HBM bytes per launch from the
+             committed counter summary when its kernel source is unchanged
   cpu_baseline  the CPU oracle (exact integers) on the host cores
 
 Prints one JSON line.  --ber adds the equal-BER sweep (0..6 dB).
@@ -17,9 +20,11 @@ Prints one JSON line.  --ber adds the equal-BER sweep (0..6 dB).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -32,6 +37,15 @@ METRIC = "decoded info Gbit/s on 1 MI355X (K=7 r1/2), int8 radix-4 vs fp32 radix
 N_FRAMES, N_INFO = 4096, 8192
 CUS, LANES, CLOCK_HZ = 256, 64, 2.4e9
 VALU32_PEAK_TOPS = CUS * LANES * CLOCK_HZ / 1e12  # 39.32 T lane-ops/s
+VALU16_PEAK_TOPS = 2 * VALU32_PEAK_TOPS           # packed 16-bit: 78.64 T ops/s
+COPY_BYTES = 512 << 20
+# forward kernels whose HBM traffic was counted: profile summary and sources
+TRAFFIC_PROFILES = {
+    "i8r4": ("fwd_r4p_k7_4096x8192_traffic.md", ["mivit_r4p.hip", "mivit_device.h"]),
+    "f32r2": ("fwd_rot_k7_4096x8192_traffic.md", ["mivit_fwd_rot.hip", "mivit_device.h"]),
+}
+# data width of the add-compare-select of each variant's forward kernel
+PACKED16 = {"i8r4"}
 
 
 def parse():
@@ -43,7 +57,40 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--ber", action="store_true", help="run the equal-BER sweep")
     ap.add_argument("--variants", default="i8r4,f32r2,i8r2")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one device copy of %d MiB (scale for HBM counters)" % (COPY_BYTES >> 20))
     return ap.parse_args()
+
+
+def source_digest(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2011_13579_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(variant):
+    """HBM bytes per forward launch from the committed counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    prof, files = TRAFFIC_PROFILES.get(variant, (None, None))
+    if prof is None:
+        return None
+    path = os.path.join(ROOT, "profiles", prof)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for ln in fh:
+            m = re.match(r"^- (\w+): (\S+)", ln.strip())
+            if m:
+                fields[m.group(1)] = m.group(2)
+    if fields.get("source_sha256") != source_digest(files):
+        return None
+    try:
+        return int(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def time_variant(torch, mv, plan, llr, steps, warmup):
@@ -141,6 +188,13 @@ def main():
     S = N_INFO + code.K - 1
     ops_per_launch = 3 * (1 << (code.K - 1)) * S * N_FRAMES
 
+    if args.copy_probe:
+        src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     plans = {}
     results = {}
     for v in args.variants.split(","):
@@ -150,16 +204,19 @@ def main():
         llr = llr_i8 if dt == "i8" else llr_f32
         ms, fwd, tb, bits, _ = time_variant(torch, mv, plans[v], llr, args.steps, args.warmup)
         dec = mv.unpack_bits(bits.cpu().numpy()[: N_FRAMES * (N_INFO // 32)].reshape(N_FRAMES, -1), N_INFO)
+        peak = VALU16_PEAK_TOPS if base in PACKED16 and not kv else VALU32_PEAK_TOPS
         results[v] = {
             "gbit_s": round(N_FRAMES * N_INFO / (ms * 1e-3) / 1e9, 3),
             "ms_per_step": round(ms, 4), "forward_ms": round(fwd, 4), "traceback_ms": round(tb, 4),
             "forward_tops": round(ops_per_launch / (fwd * 1e-3) / 1e12, 3),
-            "forward_frac_valu32": round(ops_per_launch / (fwd * 1e-3) / 1e12 / VALU32_PEAK_TOPS, 4),
+            "forward_peak_tops": round(peak, 2),
+            "forward_frac": round(ops_per_launch / (fwd * 1e-3) / 1e12 / peak, 4),
             "bit_errors": int((dec != b.msg).sum()),
         }
     head = results.get("i8r4") or next(iter(results.values()))
     hv = "i8r4" if "i8r4" in results else next(iter(results))
     achieved = ops_per_launch / (head["forward_ms"] * 1e-3) / 1e12
+    peak = head["forward_peak_tops"]
     line = {
         "metric": METRIC,
         "value": head["gbit_s"],
@@ -177,9 +234,10 @@ def main():
                    (N_FRAMES, N_INFO, hv), "frames": N_FRAMES, "info_bits": N_INFO,
                    "ebn0_db": args.ebn0, "variant": hv},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
-                     "peak": round(VALU32_PEAK_TOPS, 2), "unit": "Tops/s",
-                     "frac": round(achieved / VALU32_PEAK_TOPS, 4), "traffic": None,
+                     "peak": peak, "unit": "Tops/s",
+                     "frac": round(achieved / peak, 4), "traffic": measured_traffic(hv),
                      "kernel": "forward (%s)" % hv,
+                     "peak_basis": "packed 16-bit VALU" if peak > VALU32_PEAK_TOPS else "32-bit VALU",
                      "work": "3 ops x 64 states x %d stages x %d frames per launch" % (S, N_FRAMES)},
         "variants": results,
     }

@@ -472,8 +472,9 @@ __device__ __forceinline__ void chase_all(Chase& c, bool go, bool pair_go, const
   constexpr int KM1 = Tb<ND>::KM1, NS = Tb<ND>::NS, IPB = Tb<ND>::IPB;
   const int lane = threadIdx.x & 63;
   Emit em;
-  const int B0 = pair_go ? (c.hi - 1) / IPB : 0;
-  const int nb = pair_go ? B0 - c.lo / IPB + 1 : 0;
+  const bool any = pair_go && c.hi > c.lo;
+  const int B0 = any ? (c.hi - 1) / IPB : 0;
+  const int nb = any ? B0 - c.lo / IPB + 1 : 0;
   int P = c.hi;
   uint32_t A = go ? c.A : 0u;
   if (go && P == c.PY) c.Y = A;
@@ -546,8 +547,9 @@ __global__ __launch_bounds__(64) void k_tb_r4p(const Item* __restrict__ items,
   const int b = min(ob + (g + 1) * L, ob + n);
   // pair-aligned times at or above a time t: lead + 2P
   auto top_of = [&](int t) { return (t - lead + 1) >> 1; };  // smallest P with lead + 2P >= t
-  const bool exact = active && (g == G - 1);
-  int P_top = exact ? n_it : min(n_it, top_of(b + warm));
+  // lanes whose warm-up reaches the frame end start from the known end state
+  const int P_top = (g == G - 1) ? n_it : min(n_it, top_of(b + warm));
+  const bool exact = active && P_top == n_it;
   Chase c;
   c.hi = active ? P_top : 0;
   c.lo = max(0, (a - lead) >> 1);  // the iteration holding stage a (0: stage 0 of odd S)
@@ -563,8 +565,12 @@ __global__ __launch_bounds__(64) void k_tb_r4p(const Item* __restrict__ items,
   } else {
     c.A = 0;
   }
-  bool go = active && c.hi > c.lo;
-  bool pair_go = go || __shfl_xor((int)go, 32);
+  // a frame of one stage has no iteration: only stage 0's bit is emitted
+  const bool go = active && (c.hi > c.lo || (lead && c.lo == 0 && a <= 0));
+  // the shuffle runs on every lane: inside a short-circuit it would run only
+  // where the left side is false and read nothing from the other lanes
+  const int go_partner = __shfl_xor((int)go, 32);
+  const bool pair_go = go | (go_partner != 0);
   chase_all<ND>(c, go, pair_go, sv, lds, lead, h, g, ob, bits, it.bit_off);
   // repair: lane g is right when its state at its upper boundary equals the
   // state lane g+1 reached at its lower boundary (the same time)
@@ -574,7 +580,8 @@ __global__ __launch_bounds__(64) void k_tb_r4p(const Item* __restrict__ items,
     const uint32_t x_up = (uint32_t)__shfl_down((int)c.X, 1) & kStateBits;
     const bool bad = active && !checked && g < G - 1 && c.Y != x_up;
     if (__ballot(bad) == 0) break;
-    const bool pbad = bad || __shfl_xor((int)bad, 32);
+    const int bad_partner = __shfl_xor((int)bad, 32);
+    const bool pbad = bad | (bad_partner != 0);
     Chase rc = c;
     rc.hi = c.PY;
     rc.A = x_up;

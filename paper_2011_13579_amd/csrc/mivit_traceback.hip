@@ -82,27 +82,31 @@ __device__ __forceinline__ uint32_t word_at(const uint32_t* buf_k, int w, int la
   return buf_k[((w >> 2) * 64 + lane) * 4 + (w & 3)];
 }
 
-// Per-lane chase state.
+// Per-lane chase state.  Times are stage boundaries: time t is the state
+// entering stage t.  In the natural radix-4 layout the decisions of a stage
+// pair (2k, 2k+1) only name the state two stages back, so states are known
+// (and compared between segments) at pair-aligned times: even times and S.
 struct Chase {
   int top, a, b;  // from time top down to time a; bits of [a, b) are emitted
   int j;          // current state
-  int y;          // state at time b
+  int xa, yb;     // pair-aligned times at or above a and b
+  int x, y;       // states at times xa and yb
 };
 
-// All lanes with top > a chase their range; the others idle.  Returns with
-// c.j = state at time a and c.y = state at time b.
+// All lanes with go set chase their range; the others idle.  Returns with
+// c.j = state where the chase ended, c.x and c.y set.
 template <int LAYOUT>
 __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_t* __restrict__ sv,
-                                          uint32_t* lds, Chase& c, int ob, uint32_t* bits,
-                                          int64_t bit_off) {
+                                          uint32_t* lds, Chase& c, bool go, int ob, int S,
+                                          uint32_t* bits, int64_t bit_off) {
   const int lane = threadIdx.x;
   const int SB = g.SB, WB = g.WB;
   Emitter em;
-  if (c.top == c.b) c.y = c.j;
-  const bool go = c.top > c.a;
+  if (go && c.top == c.yb) c.y = c.j;
+  if (go && c.top == c.xa) c.x = c.j;
   const int B0 = go ? (c.top - 1) / SB : 0;
   const int nb = go ? B0 - c.a / SB + 1 : 0;
-  int t = c.top - 1;
+  int t = c.top - 1;  // next stage to step over
   if (nb > 0) fetch_block(sv + (int64_t)B0 * WB, lds);
   for (int r = 0;; ++r) {
     if (__ballot(r < nb) == 0) break;
@@ -112,32 +116,33 @@ __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_
     if (r + 1 < nb) fetch_block(sv + (int64_t)(B0 - r - 1) * WB, nxt);
     if (r < nb) {
       const int B = B0 - r;
-      const int lo = max(c.a, B * SB);
       int j = c.j;
       if (LAYOUT == kLayoutNatR4) {
-        if (t >= lo && !(t & 1)) {
+        if ((S & 1) && t == S - 1 && t >= B * SB) {
           // odd stage count: the last stage was a radix-2 stage
           const int w = (t % SB) * 2 * g.W + (j >> 5);
           const int d = (word_at(cur, w, lane) >> (j & 31)) & 1;
-          if (t < c.b) em.put(t - ob, j >> (g.KM1 - 1), bits, bit_off);
+          if (t >= c.a && t < c.b) em.put(t - ob, j >> (g.KM1 - 1), bits, bit_off);
           j = ((j << 1) | d) & (g.NS - 1);
-          if (t == c.b) c.y = j;
+          if (t == c.yb) c.y = j;
+          if (t == c.xa) c.x = j;
           --t;
         }
-        for (; t > lo; t -= 2) {
-          // the pair of stages (t-1, t): y = bit 0 from word t-1, bit 1 from word t
+        // pairs (t-1, t), t odd; pairs never straddle a block
+        for (; t > B * SB && t >= c.a; t -= 2) {
           const int w0 = ((t - 1) % SB) * 2 * g.W + (j >> 5);
           const int w1 = (t % SB) * 2 * g.W + (j >> 5);
           const int yy = ((word_at(cur, w0, lane) >> (j & 31)) & 1) |
                          (((word_at(cur, w1, lane) >> (j & 31)) & 1) << 1);
-          // b is even except for the last segment, whose b = out_begin + n_out
-          // may split a pair
           if (t < c.b) em.put(t - ob, j >> (g.KM1 - 1), bits, bit_off);
-          if (t - 1 < c.b) em.put(t - 1 - ob, (j >> (g.KM1 - 2)) & 1, bits, bit_off);
+          if (t - 1 >= c.a && t - 1 < c.b)
+            em.put(t - 1 - ob, (j >> (g.KM1 - 2)) & 1, bits, bit_off);
           j = 4 * (j & ((g.NS >> 2) - 1)) + yy;
-          if (t - 1 == c.b) c.y = j;
+          if (t - 1 == c.yb) c.y = j;
+          if (t - 1 == c.xa) c.x = j;
         }
       } else {
+        const int lo = max(c.a, B * SB);
         for (; t >= lo; --t) {
           int d;
           if (LAYOUT == kLayoutRotR2) {
@@ -149,7 +154,8 @@ __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_
           }
           if (t < c.b) em.put(t - ob, j >> (g.KM1 - 1), bits, bit_off);
           j = ((j << 1) | d) & (g.NS - 1);
-          if (t == c.b) c.y = j;
+          if (t == c.yb) c.y = j;
+          if (t == c.xa) c.x = j;
         }
       }
       c.j = j;
@@ -171,6 +177,9 @@ __global__ __launch_bounds__(64) void k_tb_seg(const DevCode* __restrict__ codes
   const int lane = threadIdx.x;
   const uint32_t* sv = (const uint32_t*)(surv + it.surv_off);
   const int S = it.n_stages, ob = it.out_begin, n = it.n_out;
+  // pair-aligned time at or above t (every time for radix 2)
+  const bool pairs = LAYOUT == kLayoutNatR4;
+  auto align = [&](int t) { return (pairs && (t & 1) && t < S) ? t + 1 : t; };
   // segment geometry: G segments of L stages, L a multiple of 32
   int G = min(64, (n + 31) / 32);
   const int L = (((n + G - 1) / G) + 31) & ~31;
@@ -179,24 +188,27 @@ __global__ __launch_bounds__(64) void k_tb_seg(const DevCode* __restrict__ codes
   Chase c;
   c.a = ob + lane * L;
   c.b = min(ob + (lane + 1) * L, ob + n);
-  c.top = active ? ((lane == G - 1) ? S : min(S, c.b + warm)) : c.a;
+  c.xa = align(c.a);
+  c.yb = align(c.b);
+  c.top = active ? ((lane == G - 1) ? S : min(S, align(c.b + warm))) : c.a;
   const bool exact = active && c.top == S;
   c.j = exact ? item_end[it.slot] : 0;
-  c.y = -1;
-  chase_all<LAYOUT>(g, sv, lds, c, ob, bits, it.bit_off);
-  // repair rounds: lane g is right when its state at b equals lane g+1's at a
-  bool checked = exact;
+  c.x = c.y = -1;
+  chase_all<LAYOUT>(g, sv, lds, c, active && c.top > c.a, ob, S, bits, it.bit_off);
+  // repair rounds: lane g is right when its state at yb equals lane g+1's
+  // state at its xa (the same time)
   for (int round = 0; round <= G; ++round) {
-    const int x_up = __shfl_down(c.j, 1);
-    const bool bad = active && !checked && lane < G - 1 && c.y != x_up;
+    const int x_up = __shfl_down(c.x, 1) & (g.NS - 1);
+    const bool bad = active && !exact && lane < G - 1 && c.y != x_up;
     if (__ballot(bad) == 0) break;
     // lanes that agree with their neighbour stay idle this round
     Chase r = c;
-    r.top = bad ? c.b : c.a;
-    r.j = bad ? x_up : c.j;
-    chase_all<LAYOUT>(g, sv, lds, r, ob, bits, it.bit_off);
+    r.top = c.yb;
+    r.j = x_up;
+    chase_all<LAYOUT>(g, sv, lds, r, bad, ob, S, bits, it.bit_off);
     if (bad) {
       c.j = r.j;
+      c.x = r.x;
       c.y = x_up;
     }
   }

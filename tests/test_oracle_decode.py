@@ -247,3 +247,20 @@ def test_ber_against_union_bound():
         assert errs >= 100, "too few errors for a valid BER point"
         assert ber <= 1.3 * bound
         assert ber >= bound / 20
+
+
+def test_quantizer_pins():
+    """q = saturate_127(round_half_even(fl32(l * s))), values worked by hand:
+    halves go to the even neighbour, magnitudes past 127 saturate (never to
+    -128), infinities saturate, NaN maps to 0."""
+    x = np.array([0.5, 1.5, 2.5, -2.5, 3.5, -0.5, 0.49999997, 126.5, 127.49, 127.5, 128.0,
+                  1000.0, -1000.0, np.inf, -np.inf, np.nan, 0.0, -0.0], np.float32)
+    want = np.array([0, 2, 2, -2, 4, 0, 0, 126, 127, 127, 127, 127, -127, 127, -127, 0, 0, 0],
+                    np.int8)
+    np.testing.assert_array_equal(oracle.quantize_i8(x, 1.0), want)
+    # the product is rounded to float32 before rounding to an integer:
+    # 0.1f * 25 = 2.5000000372529 in exact arithmetic, 2.5f after rounding -> 2
+    np.testing.assert_array_equal(oracle.quantize_i8(np.array([0.1], np.float32), 25.0), [2])
+    # scale 4: 0.375 -> 1.5 -> 2, 0.625 -> 2.5 -> 2, -0.875 -> -3.5 -> -4
+    np.testing.assert_array_equal(
+        oracle.quantize_i8(np.array([0.375, 0.625, -0.875], np.float32), 4.0), [2, 2, -4])
