@@ -97,8 +97,34 @@ typedef struct {
                        previous-state metrics fetched, 2: one partner metric
                        per lane), radix 4 through LDS, one frame per lane
                        group and 32-bit metrics */
-  int32_t reserved[3];
+  uint32_t flags;   /* MIVIT_PLAN_* scheduling options, below */
+  int32_t reserved[2]; /* must be zero */
 } mivit_opts;
+
+/* Plan scheduling flags (batch scheduling; the paper runs one kernel per
+ * frame set, §III).  Frames of different codes always form separate parts
+ * that run concurrently on plan-owned streams, forked from and joined back
+ * into the caller's stream.
+ *   MIVIT_PLAN_GRAPH       mivit_decode records its whole launch sequence in
+ *                          a hipGraph on the first call with a given (llr,
+ *                          bits, metric, end_state, stream) and replays the
+ *                          graph on later calls with the same arguments (up
+ *                          to 8 recorded argument sets per plan).
+ *   MIVIT_PLAN_PERSISTENT  the rotating forward kernels run as persistent
+ *                          grids: each wavefront takes frame groups in table
+ *                          order (longest frames first) from a device work
+ *                          counter until the table is exhausted.
+ *   MIVIT_PLAN_AUTOTUNE    plan creation times every valid kernel choice of
+ *                          each code's part (radix, exchange variant,
+ *                          persistent launch; radix 4 only when 'radix' is 0
+ *                          or 4, radix 2 only when it is 0 or 2) on
+ *                          synthetic soft values with the plan's frame
+ *                          shapes and keeps the fastest.  All choices give
+ *                          identical results.  Uses extra device memory
+ *                          for the plan's soft-value extent while creating. */
+#define MIVIT_PLAN_GRAPH 1u
+#define MIVIT_PLAN_AUTOTUNE 2u
+#define MIVIT_PLAN_PERSISTENT 4u
 
 typedef struct mivit_plan mivit_plan;
 
@@ -164,9 +190,15 @@ typedef struct {
 } mivit_plan_info;
 mivit_status mivit_plan_get_info(const mivit_plan* plan, mivit_plan_info* info);
 
-/* int8 quantiser for soft values (paper silent; see the readings in the
- * design notes): q[k] = saturate_127(round_half_even(fl32(llr[k] * scale))).
- * llr: device float32 [n]; q: device int8 [n]; scale > 0.  NaN maps to 0. */
+/* Human-readable summary of the plan's parts (one per code): kernel, variant,
+ * launch form, items, wavefronts.  Writes at most len bytes including the
+ * terminating zero into the host buffer buf (truncating). */
+mivit_status mivit_plan_describe(const mivit_plan* plan, char* buf, int32_t len);
+
+/* int8 quantiser for soft values (the paper uses float inputs; this is the
+ * library's choice): q[k] = saturate_127(round_half_even(fl32(llr[k] *
+ * scale))); the product is rounded to float32 first.  llr: device float32
+ * [n]; q: device int8 [n]; scale > 0.  NaN maps to 0. */
 mivit_status mivit_quantize_i8(const float* llr, int8_t* q, int64_t n, float scale,
                                void* stream);
 

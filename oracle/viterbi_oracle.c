@@ -149,16 +149,17 @@ int orc_encode(const orc_code* c, const uint8_t* msg, int32_t n, int32_t termina
 typedef struct {
   int16_t* phi;
   double* margin;
-  int cap_stages;
+  size_t cap;  /* entries (stages x states) the buffers hold */
 } orc_scratch;
 
 static int scratch_reserve(orc_scratch* s, int S, int ns, int want_margin) {
-  if (S <= s->cap_stages && (!want_margin || s->margin)) return 0;
+  const size_t need = (size_t)S * (size_t)ns;
+  if (need <= s->cap && (!want_margin || s->margin)) return 0;
   free(s->phi);
   free(s->margin);
-  s->phi = (int16_t*)malloc((size_t)S * ns * sizeof(int16_t));
-  s->margin = want_margin ? (double*)malloc((size_t)S * ns * sizeof(double)) : NULL;
-  s->cap_stages = S;
+  s->phi = (int16_t*)malloc((need ? need : 1) * sizeof(int16_t));
+  s->margin = want_margin ? (double*)malloc((need ? need : 1) * sizeof(double)) : NULL;
+  s->cap = need;
   return (s->phi && (!want_margin || s->margin)) ? 0 : -1;
 }
 
@@ -431,7 +432,7 @@ typedef struct {
 
 static void* worker(void* arg) {
   orc_job* job = (orc_job*)arg;
-  orc_scratch sc = {0, 0, 0};
+  orc_scratch sc = {0, 0, 0};  /* grows to the largest frame seen */
   orc_trellis* trs = (orc_trellis*)malloc(sizeof(orc_trellis) * (size_t)job->n_codes);
   if (!trs) { pthread_mutex_lock(&job->mu); job->err = -2; pthread_mutex_unlock(&job->mu); return NULL; }
   for (int c = 0; c < job->n_codes; ++c) build_trellis(&job->codes[c], &trs[c]);

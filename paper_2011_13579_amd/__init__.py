@@ -84,7 +84,8 @@ class Plan:
     """
 
     def __init__(self, codes: Sequence, frames: np.ndarray, dtype: str = "f32", radix: int = 0,
-                 chunk: int = 0, overlap: int = 0, variant: int = 0):
+                 chunk: int = 0, overlap: int = 0, variant: int = 0, graph: bool = False,
+                 autotune: bool = False, persistent: bool = False):
         lib = _capi.load()
         self.codes = [_as_code(c) for c in codes]
         self.frames = np.ascontiguousarray(frames, dtype=FRAME_DTYPE)
@@ -93,6 +94,9 @@ class Plan:
         opts = _capi.Opts()
         opts.dtype, opts.radix, opts.chunk, opts.overlap = self.dtype, int(radix), int(chunk), int(overlap)
         opts.variant = int(variant)
+        opts.flags = ((_capi.MIVIT_PLAN_GRAPH if graph else 0) |
+                      (_capi.MIVIT_PLAN_AUTOTUNE if autotune else 0) |
+                      (_capi.MIVIT_PLAN_PERSISTENT if persistent else 0))
         h = ctypes.c_void_p()
         st = lib.mivit_plan_create(ctypes.byref(h), arr, len(self.codes),
                                    self.frames.ctypes.data if len(self.frames) else None,
@@ -112,6 +116,12 @@ class Plan:
             self.n_bit_words = int((ends.max() + 31) // 32)
         else:
             self.n_bit_words = 0
+
+    def describe(self) -> str:
+        """The plan's parts: kernel, variant and launch form per code."""
+        buf = ctypes.create_string_buffer(4096)
+        _capi.check(self._lib.mivit_plan_describe(self._h, buf, len(buf)), "mivit_plan_describe")
+        return buf.value.decode()
 
     @property
     def handle(self) -> int:

@@ -16,8 +16,10 @@ MIVIT_START_KNOWN, MIVIT_END_ZERO = 1, 2
 # every symbol include/mivit.h declares
 EXPORTS = (
     "mivit_plan_create", "mivit_decode", "mivit_forward", "mivit_traceback", "mivit_decode_grad", "mivit_plan_destroy",
-    "mivit_plan_get_info", "mivit_quantize_i8", "mivit_strerror", "mivit_version",
+    "mivit_plan_get_info", "mivit_plan_describe", "mivit_quantize_i8", "mivit_strerror",
+    "mivit_version",
 )
+MIVIT_PLAN_GRAPH, MIVIT_PLAN_AUTOTUNE, MIVIT_PLAN_PERSISTENT = 1, 2, 4
 
 
 class Code(ctypes.Structure):
@@ -45,7 +47,7 @@ assert FRAME_DTYPE.itemsize == ctypes.sizeof(Frame) == 32
 class Opts(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("radix", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("overlap", ctypes.c_int32), ("variant", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -88,6 +90,8 @@ def load(path: str = LIB_PATH):
     lib.mivit_plan_destroy.argtypes = [vp]
     lib.mivit_plan_get_info.restype = ctypes.c_int
     lib.mivit_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    lib.mivit_plan_describe.restype = ctypes.c_int
+    lib.mivit_plan_describe.argtypes = [vp, ctypes.c_char_p, i32]
     lib.mivit_quantize_i8.restype = ctypes.c_int
     lib.mivit_quantize_i8.argtypes = [vp, vp, i64, ctypes.c_float, vp]
     lib.mivit_strerror.restype = ctypes.c_char_p

@@ -1,11 +1,15 @@
 // C ABI of the Viterbi decoder library: argument validation, plan building
-// (chunking of long frames into overlapping windows, §III), work ordering,
-// device memory ownership and kernel launches.
+// (chunking of long frames into overlapping windows, §III), one part per code
+// with its own kernel choice, work ordering, scheduling (concurrent parts on
+// plan-owned streams, persistent work-queue launches, graph capture), the
+// autotuner, device memory ownership and kernel launches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/mivit.h"
@@ -15,9 +19,6 @@ namespace mivit {
 hipError_t launch_fwd(int radix, int nsl, bool is_int, const DevCode* codes, const Item* items,
                       int n_items, const void* llr, uint64_t* surv, void* metric,
                       int32_t* end_out, int32_t* item_end, hipStream_t st);
-hipError_t launch_tb(int radix, const DevCode* codes, const Item* items, int n_items,
-                     const uint64_t* surv, const int32_t* item_end, uint32_t* bits,
-                     hipStream_t st);
 hipError_t launch_grad(const DevCode* codes, const GradFrame* frames, int n_frames,
                        int max_stages, const uint32_t* bits, const float* gm, float* grad,
                        hipStream_t st);
@@ -25,16 +26,19 @@ hipError_t launch_quant(const float* x, int8_t* q, int64_t n, float scale, hipSt
 hipError_t launch_fwd_rot(int K, int beta, bool is_int, int mode, const DevCode* codes,
                           const Item* items, const int2* waves, int n_waves, const void* llr,
                           uint64_t* surv, void* metric, int32_t* end_out, int32_t* item_end,
-                          hipStream_t st);
+                          int32_t* counter, int grid_limit, hipStream_t st);
 hipError_t launch_tb_seg(int layout, const DevCode* codes, const Item* items, int n_items,
                          const uint64_t* surv, const int32_t* item_end, uint32_t* bits,
                          int warm, hipStream_t st);
 hipError_t launch_fwd_r4p(int K, const DevCode* codes, const Item* items, const int2* waves,
                           int n_waves, const int8_t* llr, uint64_t* surv, int64_t* metric,
-                          int32_t* end_out, int32_t* item_end, hipStream_t st);
+                          int32_t* end_out, int32_t* item_end, int32_t* counter, int grid_limit,
+                          hipStream_t st);
 hipError_t launch_tb_r4p(int K, const Item* items, const int2* pairs, int n_pairs,
                          const uint64_t* surv, const int32_t* item_end, uint32_t* bits, int warm,
                          hipStream_t st);
+hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st);
+hipError_t launch_fill_random(void* p, int64_t n, bool is_int, uint32_t seed, hipStream_t st);
 }  // namespace mivit
 
 using namespace mivit;
@@ -47,6 +51,15 @@ constexpr int kWarmStages = 64;  // speculative traceback warm-up
 // 0 all exchanges in the VALU (DPP, permlane swaps), 1 both previous-state
 // metrics via DPP/LDS swizzles, 2 one partner metric via DPP/LDS swizzles
 constexpr int kRotMode[3] = {2, 0, 1};
+constexpr int kMaxAux = 4;     // plan-owned streams for concurrent parts
+constexpr int kMaxGraphs = 8;  // recorded decode graphs kept per plan
+
+// Kernel choice of one part (all frames of one code).
+struct Choice {
+  int radix = 2;
+  int variant = 0;
+  bool persistent = false;
+};
 
 struct PlanGroup {
   int kern;   // forward kernel
@@ -59,28 +72,49 @@ struct PlanGroup {
   int n_waves;
   int pair_off;  // packed radix-4 kernel: first entry in the traceback pair table
   int n_pairs;
+  int counter;   // persistent launch: index of the group's work counter, else -1
+};
+
+struct Part {
+  int code = 0;
+  Choice ch;
+  std::vector<Item> items;
+  std::vector<PlanGroup> groups;
+  int64_t surv_words = 0;
+  int64_t total_stages = 0;
+  Item* d_items = nullptr;
+  int32_t* d_item_end = nullptr;
+  uint64_t* d_surv = nullptr;
+  int2* d_waves = nullptr;  // rotating kernels: (first item, count) per wavefront
+  int2* d_pairs = nullptr;  // packed radix-4 traceback: (first item, count) per frame pair
+  int32_t* d_counters = nullptr;
+  int n_counters = 0;
+};
+
+struct GraphEntry {
+  const void* llr;
+  uint32_t* bits;
+  void* metric;
+  int32_t* end;
+  hipStream_t stream;
+  hipGraphExec_t exec;
 };
 
 struct mivit_plan {
   int device = 0;
   int dtype = MIVIT_F32;
-  int radix = 2;
-  int variant = 0;  // kernel variant (0: default)
+  uint32_t flags = 0;
   int n_frames = 0;
   bool grad_ok = false;
   int grad_max_stages = 0;
-  int64_t total_stages = 0;
-  int64_t surv_words = 0;
-  std::vector<Item> items;
-  std::vector<PlanGroup> groups;
-  std::vector<int> group_keys;
   DevCode* d_codes = nullptr;
-  Item* d_items = nullptr;
-  int32_t* d_item_end = nullptr;
-  uint64_t* d_surv = nullptr;
   GradFrame* d_gframes = nullptr;
-  int2* d_waves = nullptr;  // rotating kernels: (first item, count) per wavefront
-  int2* d_pairs = nullptr;  // packed radix-4 traceback: (first item, count) per frame pair
+  std::vector<Part> parts;
+  hipStream_t origin = nullptr;  // capture stream
+  std::vector<hipStream_t> aux;
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_join;
+  std::vector<GraphEntry> graphs;
 };
 
 namespace {
@@ -109,15 +143,32 @@ mivit_status check_code(const mivit_code& c) {
 
 int nsl_of(int K) { return K <= 7 ? 1 : (1 << (K - 1)) / 64; }
 
+bool packed_ok(const mivit_code& c) { return c.beta == 2 && (c.K == 5 || c.K == 7); }
+
+mivit_status hip_status(hipError_t e) {
+  return e == hipSuccess ? MIVIT_OK : (e == hipErrorOutOfMemory ? MIVIT_ENOMEM : MIVIT_EHIP);
+}
+
+void free_part(Part& q) {
+  (void)hipFree(q.d_items);
+  (void)hipFree(q.d_item_end);
+  (void)hipFree(q.d_surv);
+  (void)hipFree(q.d_waves);
+  (void)hipFree(q.d_pairs);
+  (void)hipFree(q.d_counters);
+  q = Part();
+}
+
 void free_plan(mivit_plan* p) {
   if (!p) return;
+  for (GraphEntry& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+  for (Part& q : p->parts) free_part(q);
   (void)hipFree(p->d_codes);
-  (void)hipFree(p->d_items);
-  (void)hipFree(p->d_item_end);
-  (void)hipFree(p->d_surv);
   (void)hipFree(p->d_gframes);
-  (void)hipFree(p->d_waves);
-  (void)hipFree(p->d_pairs);
+  for (hipEvent_t e : p->ev_join) (void)hipEventDestroy(e);
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  for (hipStream_t s : p->aux) (void)hipStreamDestroy(s);
+  if (p->origin) (void)hipStreamDestroy(p->origin);
   delete p;
 }
 
@@ -128,6 +179,288 @@ hipError_t upload(T** dst, const T* src, size_t n) {
   hipError_t e = hipMalloc((void**)dst, n * sizeof(T));
   if (e != hipSuccess) return e;
   return hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+}
+
+// Work items of the frames fidx (all of one code): whole frames, or the
+// windows of §III for frames longer than the chunk.
+void expand_items(const mivit_code* codes, const mivit_frame* frames, const std::vector<int>& fidx,
+                  const mivit_opts& o, std::vector<Item>& items) {
+  for (int f : fidx) {
+    const mivit_frame& fr = frames[f];
+    const mivit_code& c = codes[fr.code];
+    const int S = fr.n_stages;
+    if (o.chunk > 0 && S > o.chunk) {
+      for (int c0 = 0; c0 < S; c0 += o.chunk) {
+        const int c1 = std::min(S, c0 + o.chunk);
+        const int w0 = std::max(0, c0 - o.overlap);
+        const int w1 = std::min(S, c1 + o.overlap);
+        const bool last = c1 == S;
+        const int e1 = std::min(c1, fr.n_out);
+        const int nout = e1 > c0 ? e1 - c0 : 0;
+        if (nout == 0 && !last) continue;
+        Item it;
+        std::memset(&it, 0, sizeof it);
+        it.llr_off = fr.llr_offset + (int64_t)w0 * c.beta;
+        it.bit_off = fr.bit_offset + c0;
+        it.n_stages = w1 - w0;
+        it.out_begin = c0 - w0;
+        it.n_out = nout;
+        it.code = fr.code;
+        it.start_known = (w0 == 0) && (fr.flags & MIVIT_START_KNOWN);
+        it.end_state = (last && (fr.flags & MIVIT_END_ZERO)) ? 0 : -1;
+        it.frame = last ? f : -1;
+        items.push_back(it);
+      }
+    } else {
+      Item it;
+      std::memset(&it, 0, sizeof it);
+      it.llr_off = fr.llr_offset;
+      it.bit_off = fr.bit_offset;
+      it.n_stages = S;
+      it.out_begin = fr.out_begin;
+      it.n_out = fr.n_out;
+      it.code = fr.code;
+      it.start_known = (fr.flags & MIVIT_START_KNOWN) ? 1 : 0;
+      it.end_state = (fr.flags & MIVIT_END_ZERO) ? 0 : -1;
+      it.frame = f;
+      items.push_back(it);
+    }
+  }
+}
+
+// Build one part: kernel per item, groups, wave and pair tables, survivor
+// memory, device copies.
+mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
+                        const std::vector<int>& fidx, const mivit_opts& o, int dtype, Choice ch,
+                        int code, Part& q) {
+  q = Part();
+  q.code = code;
+  q.ch = ch;
+  std::vector<Item> items;
+  expand_items(codes, frames, fidx, o, items);
+  const mivit_code& c = codes[code];
+  const bool i8 = dtype == MIVIT_I8;
+  int kern;
+  if (ch.radix == 4)
+    kern = (ch.variant == 0 && packed_ok(c) && i8) ? kKernRot4P : kKernGeneric4;
+  else
+    kern = c.K <= 7 ? kKernRot2 : kKernGeneric2;
+  // longest first; items that can share a packed lane group next to each other
+  std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) {
+    if (a.n_stages != b.n_stages) return a.n_stages > b.n_stages;
+    if (a.out_begin != b.out_begin) return a.out_begin < b.out_begin;
+    return a.n_out < b.n_out;
+  });
+  PlanGroup g;
+  g.kern = kern;
+  g.layout = kern == kKernRot2      ? kLayoutRotR2
+             : kern == kKernRot4P   ? kLayoutRot4P
+             : kern == kKernGeneric4 ? kLayoutNatR4
+                                     : kLayoutNatR2;
+  g.nsl = nsl_of(c.K);
+  g.K = c.K;
+  g.beta = c.beta;
+  g.first = 0;
+  g.count = (int)items.size();
+  g.wave_off = g.n_waves = g.pair_off = g.n_pairs = 0;
+  g.counter = -1;
+  for (size_t k = 0; k < items.size(); ++k) {
+    items[k].slot = (int32_t)k;
+    q.total_stages += items[k].n_stages;
+  }
+  // rotating kernels: wavefronts of frames of equal length (radix 2: up to
+  // 64/2^(K-1) frames; packed radix 4: up to 2*64/2^(K-1), where the two
+  // frames of a lane group must also emit the same stages)
+  std::vector<int2> waves, pairs;
+  std::vector<char> pair_hi(items.size(), 0);
+  if (kern == kKernRot2 || kern == kKernRot4P) {
+    const bool packed = kern == kKernRot4P;
+    const int fpw = (packed ? 2 : 1) * (64 >> (c.K - 1));
+    for (int k = 0; k < (int)items.size(); ++k) {
+      if (!waves.empty()) {
+        int2& w = waves.back();
+        const Item& prev = items[k - 1];
+        bool fits = w.y < fpw && items[w.x].n_stages == items[k].n_stages;
+        if (packed && (w.y & 1))
+          fits = fits && prev.out_begin == items[k].out_begin && prev.n_out == items[k].n_out;
+        if (fits) {
+          if (packed) pair_hi[k] = (char)(w.y & 1);
+          w.y++;
+          continue;
+        }
+      }
+      waves.push_back(make_int2(k, 1));
+    }
+    g.n_waves = (int)waves.size();
+    if (packed) {
+      for (const int2& w : waves)
+        for (int s = 0; s < w.y; s += 2) pairs.push_back(make_int2(w.x + s, std::min(2, w.y - s)));
+      g.n_pairs = (int)pairs.size();
+    }
+    if (ch.persistent) g.counter = q.n_counters++;
+  }
+  // survivor memory, 16-byte aligned per item (per frame pair when packed)
+  int64_t words_total = 0;
+  for (size_t k = 0; k < items.size(); ++k) {
+    Item& it = items[k];
+    if (kern == kKernRot4P && pair_hi[k]) {
+      it.surv_off = items[k - 1].surv_off;
+      continue;
+    }
+    it.surv_off = words_total;
+    int64_t words;
+    if (kern == kKernRot2)
+      words = (int64_t)((it.n_stages + 31) / 32) * (1 << (c.K - 1)) / 2;
+    else if (kern == kKernRot4P)  // 2^(K-1) 32-bit words per 8 iterations
+      words = (int64_t)((it.n_stages / 2 + 7) / 8) * (1 << (c.K - 1)) / 2;
+    else
+      words = (int64_t)it.n_stages * words_per_stage(c.K);
+    words_total += (words + 1) & ~(int64_t)1;
+  }
+  words_total += 32;  // the traceback reads whole blocks past an item's end
+  q.surv_words = words_total;
+  if (!items.empty()) q.groups.push_back(g);
+  q.items = items;
+  hipError_t e = upload(&q.d_items, items.data(), items.size());
+  if (e == hipSuccess) e = upload(&q.d_waves, waves.data(), waves.size());
+  if (e == hipSuccess) e = upload(&q.d_pairs, pairs.data(), pairs.size());
+  if (e == hipSuccess && !items.empty())
+    e = hipMalloc((void**)&q.d_item_end, items.size() * sizeof(int32_t));
+  if (e == hipSuccess && !items.empty())
+    e = hipMalloc((void**)&q.d_surv, (size_t)words_total * sizeof(uint64_t));
+  if (e == hipSuccess && q.n_counters > 0)
+    e = hipMalloc((void**)&q.d_counters, q.n_counters * sizeof(int32_t));
+  if (e != hipSuccess) {
+    free_part(q);
+    return hip_status(e);
+  }
+  return MIVIT_OK;
+}
+
+hipError_t part_forward(const mivit_plan* p, const Part& q, const void* llr, void* metric,
+                        int32_t* end_state, hipStream_t st) {
+  const bool is_int = p->dtype == MIVIT_I8;
+  for (const PlanGroup& g : q.groups) {
+    hipError_t e;
+    int32_t* counter = g.counter >= 0 ? q.d_counters + g.counter : nullptr;
+    if (counter) {
+      e = launch_zero_i32(counter, 1, st);
+      if (e != hipSuccess) return e;
+    }
+    if (g.kern == kKernRot4P)
+      e = launch_fwd_r4p(g.K, p->d_codes, q.d_items, q.d_waves + g.wave_off, g.n_waves,
+                         (const int8_t*)llr, q.d_surv, (int64_t*)metric, end_state,
+                         q.d_item_end, counter, 0, st);
+    else if (g.kern == kKernRot2)
+      e = launch_fwd_rot(g.K, g.beta, is_int, kRotMode[q.ch.variant], p->d_codes, q.d_items,
+                         q.d_waves + g.wave_off, g.n_waves, llr, q.d_surv, metric, end_state,
+                         q.d_item_end, counter, 0, st);
+    else
+      e = launch_fwd(g.kern == kKernGeneric4 ? 4 : 2, g.nsl, is_int, p->d_codes,
+                     q.d_items + g.first, g.count, llr, q.d_surv, metric, end_state,
+                     q.d_item_end, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t part_traceback(const mivit_plan* p, const Part& q, uint32_t* bits, hipStream_t st) {
+  for (const PlanGroup& g : q.groups) {
+    hipError_t e =
+        g.kern == kKernRot4P
+            ? launch_tb_r4p(g.K, q.d_items, q.d_pairs + g.pair_off, g.n_pairs, q.d_surv,
+                            q.d_item_end, bits, kWarmStages, st)
+            : launch_tb_seg(g.layout, p->d_codes, q.d_items + g.first, g.count, q.d_surv,
+                            q.d_item_end, bits, kWarmStages, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+enum : int { kPhaseForward = 1, kPhaseTraceback = 2 };
+
+// Run the phases of every part on 'st'.  Two or more parts run concurrently
+// on the plan's streams, forked from and joined back into 'st'.
+hipError_t run_parts(mivit_plan* p, int phases, const void* llr, uint32_t* bits, void* metric,
+                     int32_t* end_state, hipStream_t st) {
+  auto one = [&](const Part& q, hipStream_t s) -> hipError_t {
+    hipError_t e = hipSuccess;
+    if (phases & kPhaseForward) e = part_forward(p, q, llr, metric, end_state, s);
+    if (e == hipSuccess && (phases & kPhaseTraceback)) e = part_traceback(p, q, bits, s);
+    return e;
+  };
+  if (p->parts.size() == 1) return one(p->parts[0], st);
+  hipError_t e = hipEventRecord(p->ev_fork, st);
+  for (size_t k = 0; k < p->parts.size() && e == hipSuccess; ++k) {
+    hipStream_t s = p->aux[k % p->aux.size()];
+    if (k < p->aux.size()) e = hipStreamWaitEvent(s, p->ev_fork, 0);
+    if (e == hipSuccess) e = one(p->parts[k], s);
+  }
+  for (size_t k = 0; k < p->aux.size() && e == hipSuccess; ++k) {
+    e = hipEventRecord(p->ev_join[k], p->aux[k]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_join[k], 0);
+  }
+  return e;
+}
+
+// Candidate kernel choices of a part, for the autotuner.
+std::vector<Choice> candidates(const mivit_code& c, int dtype, int radix) {
+  std::vector<Choice> out;
+  auto add = [&](int r, int v, bool pers) {
+    Choice ch;
+    ch.radix = r;
+    ch.variant = v;
+    ch.persistent = pers;
+    out.push_back(ch);
+  };
+  const bool i8 = dtype == MIVIT_I8;
+  if (radix != 4) {
+    if (c.K <= 7) {
+      for (int v = 0; v < 3; ++v) add(2, v, false);
+      add(2, 0, true);
+    } else {
+      add(2, 0, false);
+    }
+  }
+  if (i8 && radix != 2) {
+    if (packed_ok(c)) {
+      add(4, 0, false);
+      add(4, 0, true);
+    }
+    add(4, 1, false);
+  }
+  return out;
+}
+
+// Time one candidate: two decodes of synthetic soft values, the second
+// timed.  Returns milliseconds, or a negative value on failure.
+float time_part(mivit_plan* p, const Part& q, const void* llr, uint32_t* bits, void* metric,
+                int32_t* end_state) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float ms = -1.0f;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) goto done;
+  if (part_forward(p, q, llr, metric, end_state, p->origin) != hipSuccess) goto done;
+  if (part_traceback(p, q, bits, p->origin) != hipSuccess) goto done;
+  if (hipEventRecord(e0, p->origin) != hipSuccess) goto done;
+  if (part_forward(p, q, llr, metric, end_state, p->origin) != hipSuccess) goto done;
+  if (part_traceback(p, q, bits, p->origin) != hipSuccess) goto done;
+  if (hipEventRecord(e1, p->origin) != hipSuccess) goto done;
+  if (hipEventSynchronize(e1) != hipSuccess) goto done;
+  if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = -1.0f;
+done:
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return ms;
+}
+
+const char* kern_name(int kern) {
+  switch (kern) {
+    case kKernGeneric2: return "radix-2 generic";
+    case kKernGeneric4: return "radix-4 generic";
+    case kKernRot2: return "radix-2 rotating";
+    case kKernRot4P: return "radix-4 packed two-frame";
+  }
+  return "?";
 }
 
 }  // namespace
@@ -145,7 +478,7 @@ const char* mivit_strerror(mivit_status s) {
   return "unknown status";
 }
 
-const char* mivit_version(void) { return "mivit 0.1 (gfx950)"; }
+const char* mivit_version(void) { return "mivit 0.2 (gfx950)"; }
 
 mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_t n_codes,
                                const mivit_frame* frames, int32_t n_frames,
@@ -162,6 +495,9 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
   if (o.radix == 4 && o.dtype != MIVIT_I8) return MIVIT_EINVAL;
   if (o.chunk < 0 || o.overlap < 0 || (o.chunk > 0 && o.chunk % 32 != 0)) return MIVIT_EINVAL;
   if (o.variant < 0 || o.variant > 2) return MIVIT_EINVAL;
+  if (o.flags & ~(MIVIT_PLAN_GRAPH | MIVIT_PLAN_AUTOTUNE | MIVIT_PLAN_PERSISTENT))
+    return MIVIT_EINVAL;
+  if (o.reserved[0] != 0 || o.reserved[1] != 0) return MIVIT_EINVAL;
   for (int c = 0; c < n_codes; ++c) {
     mivit_status s = check_code(codes[c]);
     if (s != MIVIT_OK) return s;
@@ -169,6 +505,7 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
   // frames: ranges and non-overlapping outputs
   std::vector<std::pair<int64_t, int64_t>> words;
   words.reserve(n_frames);
+  int64_t llr_end = 0, word_end = 0;
   for (int f = 0; f < n_frames; ++f) {
     const mivit_frame& fr = frames[f];
     if (fr.code < 0 || fr.code >= n_codes) return MIVIT_EINVAL;
@@ -178,12 +515,19 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
     if (fr.flags & ~(MIVIT_START_KNOWN | MIVIT_END_ZERO)) return MIVIT_EINVAL;
     if (o.chunk > 0 && fr.n_stages > o.chunk && fr.out_begin != 0) return MIVIT_EUNSUPPORTED;
     if (fr.n_out > 0) words.push_back({fr.bit_offset >> 5, (fr.bit_offset + fr.n_out + 31) >> 5});
+    llr_end = std::max(llr_end, fr.llr_offset + (int64_t)fr.n_stages * codes[fr.code].beta);
+    word_end = std::max(word_end, (fr.bit_offset + fr.n_out + 31) >> 5);
   }
   std::sort(words.begin(), words.end());
   for (size_t k = 1; k < words.size(); ++k)
     if (words[k].first < words[k - 1].second) return MIVIT_EINVAL;
 
   mivit_plan* p = nullptr;
+  void* t_llr = nullptr;
+  void* t_bits = nullptr;
+  void* t_metric = nullptr;
+  void* t_end = nullptr;
+  mivit_status status = MIVIT_OK;
   try {
     p = new mivit_plan();
     if (hipGetDevice(&p->device) != hipSuccess) {
@@ -191,165 +535,8 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
       return MIVIT_EHIP;
     }
     p->dtype = o.dtype;
-    p->radix = o.radix == 0 ? 2 : o.radix;
-    p->variant = o.variant;
+    p->flags = o.flags;
     p->n_frames = n_frames;
-    // expand frames into work items
-    std::vector<Item> items;
-    bool chunked_any = false;
-    bool tail_ok = true;
-    for (int f = 0; f < n_frames; ++f) {
-      const mivit_frame& fr = frames[f];
-      const mivit_code& c = codes[fr.code];
-      const int S = fr.n_stages;
-      if (fr.out_begin != 0) tail_ok = false;
-      if (o.chunk > 0 && S > o.chunk) {
-        chunked_any = true;
-        for (int c0 = 0; c0 < S; c0 += o.chunk) {
-          const int c1 = std::min(S, c0 + o.chunk);
-          const int w0 = std::max(0, c0 - o.overlap);
-          const int w1 = std::min(S, c1 + o.overlap);
-          const bool last = c1 == S;
-          const int e1 = std::min(c1, fr.n_out);
-          const int nout = e1 > c0 ? e1 - c0 : 0;
-          if (nout == 0 && !last) continue;
-          Item it;
-          std::memset(&it, 0, sizeof it);
-          it.llr_off = fr.llr_offset + (int64_t)w0 * c.beta;
-          it.bit_off = fr.bit_offset + c0;
-          it.n_stages = w1 - w0;
-          it.out_begin = c0 - w0;
-          it.n_out = nout;
-          it.code = fr.code;
-          it.start_known = (w0 == 0) && (fr.flags & MIVIT_START_KNOWN);
-          it.end_state = (last && (fr.flags & MIVIT_END_ZERO)) ? 0 : -1;
-          it.frame = last ? f : -1;
-          items.push_back(it);
-        }
-      } else {
-        Item it;
-        std::memset(&it, 0, sizeof it);
-        it.llr_off = fr.llr_offset;
-        it.bit_off = fr.bit_offset;
-        it.n_stages = S;
-        it.out_begin = fr.out_begin;
-        it.n_out = fr.n_out;
-        it.code = fr.code;
-        it.start_known = (fr.flags & MIVIT_START_KNOWN) ? 1 : 0;
-        it.end_state = (fr.flags & MIVIT_END_ZERO) ? 0 : -1;
-        it.frame = f;
-        items.push_back(it);
-      }
-    }
-    // choose the forward kernel of every item and group them
-    const int radix = p->radix;
-    auto kern_of = [&](const Item& it) {
-      const mivit_code& c = codes[it.code];
-      if (radix == 4)
-        return (o.variant == 0 && c.beta == 2 && (c.K == 5 || c.K == 7)) ? (int)kKernRot4P
-                                                                          : (int)kKernGeneric4;
-      if (c.K <= 7) return (int)kKernRot2;
-      return (int)kKernGeneric2;
-    };
-    auto key_of = [&](const Item& it) {
-      const mivit_code& c = codes[it.code];
-      const int kern = kern_of(it);
-      // generic kernels group by states per lane; the rotating ones by (K, beta)
-      return (kern == kKernRot2 || kern == kKernRot4P) ? (kern << 16) | (c.K << 8) | c.beta
-                                                       : (kern << 16) | nsl_of(c.K);
-    };
-    std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) {
-      const int ka = key_of(a), kb = key_of(b);
-      if (ka != kb) return ka > kb;
-      if (a.n_stages != b.n_stages) return a.n_stages > b.n_stages;
-      if (a.out_begin != b.out_begin) return a.out_begin < b.out_begin;
-      return a.n_out < b.n_out;
-    });
-    for (size_t k = 0; k < items.size(); ++k) {
-      Item& it = items[k];
-      const mivit_code& c = codes[it.code];
-      const int kern = kern_of(it);
-      it.slot = (int32_t)k;
-      p->total_stages += it.n_stages;
-      const int key = key_of(it);
-      if (p->groups.empty() || p->group_keys.back() != key) {
-        PlanGroup g;
-        g.kern = kern;
-        g.layout = kern == kKernRot2    ? kLayoutRotR2
-                   : kern == kKernRot4P ? kLayoutRot4P
-                   : kern == kKernGeneric4 ? kLayoutNatR4
-                                           : kLayoutNatR2;
-        g.nsl = nsl_of(c.K);
-        g.K = c.K;
-        g.beta = c.beta;
-        g.first = (int)k;
-        g.count = 0;
-        g.pair_off = 0;
-        g.n_pairs = 0;
-        p->groups.push_back(g);
-        p->group_keys.push_back(key);
-      }
-      p->groups.back().count++;
-    }
-    // rotating kernels: wavefronts of frames of equal length (radix 2: up to
-    // 64/2^(K-1) frames; packed radix 4: up to 2*64/2^(K-1), where the two
-    // frames of a lane group must also emit the same stages)
-    std::vector<int2> waves, pairs;
-    std::vector<char> pair_hi(items.size(), 0);
-    for (PlanGroup& g : p->groups) {
-      g.wave_off = (int)waves.size();
-      g.n_waves = 0;
-      if (g.kern != kKernRot2 && g.kern != kKernRot4P) continue;
-      const bool packed = g.kern == kKernRot4P;
-      const int fpw = (packed ? 2 : 1) * (64 >> (g.K - 1));
-      for (int k = g.first; k < g.first + g.count; ++k) {
-        if (g.n_waves > 0) {
-          int2& w = waves.back();
-          const Item& prev = items[k - 1];
-          bool fits = w.y < fpw && items[w.x].n_stages == items[k].n_stages;
-          if (packed && (w.y & 1))
-            fits = fits && prev.out_begin == items[k].out_begin && prev.n_out == items[k].n_out;
-          if (fits) {
-            if (packed) pair_hi[k] = (char)(w.y & 1);
-            w.y++;
-            continue;
-          }
-        }
-        waves.push_back(make_int2(k, 1));
-        g.n_waves++;
-      }
-      if (packed) {
-        g.pair_off = (int)pairs.size();
-        for (int w = g.wave_off; w < g.wave_off + g.n_waves; ++w)
-          for (int s = 0; s < waves[w].y; s += 2)
-            pairs.push_back(make_int2(waves[w].x + s, std::min(2, waves[w].y - s)));
-        g.n_pairs = (int)pairs.size() - g.pair_off;
-      }
-    }
-    // survivor memory, 16-byte aligned per item (per frame pair when packed)
-    int64_t words_total = 0;
-    for (size_t k = 0; k < items.size(); ++k) {
-      Item& it = items[k];
-      const mivit_code& c = codes[it.code];
-      const int kern = kern_of(it);
-      if (kern == kKernRot4P && pair_hi[k]) {
-        it.surv_off = items[k - 1].surv_off;
-        continue;
-      }
-      it.surv_off = words_total;
-      int64_t words;
-      if (kern == kKernRot2)
-        words = (int64_t)((it.n_stages + 31) / 32) * (1 << (c.K - 1)) / 2;
-      else if (kern == kKernRot4P)  // 2^(K-1) 32-bit words per 8 iterations
-        words = (int64_t)((it.n_stages / 2 + 7) / 8) * (1 << (c.K - 1)) / 2;
-      else
-        words = (int64_t)it.n_stages * words_per_stage(c.K);
-      words_total += (words + 1) & ~(int64_t)1;
-    }
-    words_total += 32;  // the traceback reads whole blocks past an item's end
-    p->surv_words = words_total;
-    p->items = items;
-
     std::vector<DevCode> dc(n_codes);
     for (int c = 0; c < n_codes; ++c) {
       dc[c].K = codes[c].K;
@@ -357,46 +544,116 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
       for (int b = 0; b < 4; ++b) dc[c].gen[b] = b < codes[c].beta ? codes[c].gen[b] : 0;
     }
     hipError_t e = upload(&p->d_codes, dc.data(), dc.size());
-    if (e == hipSuccess) e = upload(&p->d_waves, waves.data(), waves.size());
-    if (e == hipSuccess) e = upload(&p->d_pairs, pairs.data(), pairs.size());
-    if (e == hipSuccess) e = upload(&p->d_items, items.data(), items.size());
-    if (e == hipSuccess && !items.empty())
-      e = hipMalloc((void**)&p->d_item_end, items.size() * sizeof(int32_t));
-    if (e == hipSuccess && words_total > 0)
-      e = hipMalloc((void**)&p->d_surv, (size_t)words_total * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->origin, hipStreamNonBlocking);
+    if (e != hipSuccess) throw hip_status(e);
+    // one part per code, largest work first
+    std::vector<std::vector<int>> by_code(n_codes);
+    std::vector<int64_t> work(n_codes, 0);
+    for (int f = 0; f < n_frames; ++f) {
+      by_code[frames[f].code].push_back(f);
+      work[frames[f].code] += (int64_t)frames[f].n_stages << (codes[frames[f].code].K - 1);
+    }
+    std::vector<int> order;
+    for (int c = 0; c < n_codes; ++c)
+      if (!by_code[c].empty()) order.push_back(c);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+    const bool tune = (o.flags & MIVIT_PLAN_AUTOTUNE) != 0;
+    if (tune) {
+      // synthetic soft values covering every frame, and scratch outputs
+      const size_t esz = o.dtype == MIVIT_I8 ? 1 : 4;
+      e = hipMalloc(&t_llr, (size_t)std::max<int64_t>(llr_end, 1) * esz);
+      if (e == hipSuccess) e = hipMalloc(&t_bits, (size_t)std::max<int64_t>(word_end, 1) * 4);
+      if (e == hipSuccess) e = hipMalloc(&t_metric, (size_t)std::max(n_frames, 1) * 8);
+      if (e == hipSuccess) e = hipMalloc(&t_end, (size_t)std::max(n_frames, 1) * 4);
+      if (e == hipSuccess)
+        e = launch_fill_random(t_llr, llr_end, o.dtype == MIVIT_I8, 0x5eed1234u, p->origin);
+      if (e != hipSuccess) throw hip_status(e);
+    }
+    for (int c : order) {
+      Choice base;
+      base.radix = o.radix == 0 ? 2 : o.radix;
+      base.variant = o.variant;
+      base.persistent = (o.flags & MIVIT_PLAN_PERSISTENT) != 0;
+      std::vector<Choice> cand = tune ? candidates(codes[c], o.dtype, o.radix)
+                                      : std::vector<Choice>{base};
+      Part best;
+      float best_ms = 0.0f;
+      bool have = false;
+      for (const Choice& ch : cand) {
+        Part q;
+        mivit_status s = build_part(codes, frames, by_code[c], o, o.dtype, ch, c, q);
+        if (s != MIVIT_OK) throw s;
+        const float ms =
+            cand.size() > 1 ? time_part(p, q, t_llr, (uint32_t*)t_bits, t_metric, (int32_t*)t_end)
+                            : 0.0f;
+        if (cand.size() > 1 && ms < 0.0f) {
+          free_part(q);
+          throw MIVIT_EHIP;
+        }
+        if (!have || ms < best_ms) {
+          if (have) free_part(best);
+          best = q;
+          best_ms = ms;
+          have = true;
+        } else {
+          free_part(q);
+        }
+      }
+      p->parts.push_back(best);
+    }
+    // streams and events for concurrent parts
+    const int n_aux = std::min<int>(kMaxAux, (int)p->parts.size());
+    if (p->parts.size() > 1) {
+      e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+      for (int k = 0; k < n_aux && e == hipSuccess; ++k) {
+        hipStream_t s = nullptr;
+        hipEvent_t ev = nullptr;
+        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e == hipSuccess) p->aux.push_back(s);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) p->ev_join.push_back(ev);
+      }
+      if (e != hipSuccess) throw hip_status(e);
+    }
     // gradient support: whole frames whose bits cover every stage but a zero tail
-    if (e == hipSuccess && !chunked_any && tail_ok) {
-      std::vector<GradFrame> gf(n_frames);
-      bool ok = true;
-      for (int f = 0; f < n_frames && ok; ++f) {
-        const mivit_frame& fr = frames[f];
-        const int K = codes[fr.code].K;
-        const bool term = (fr.flags & MIVIT_END_ZERO) && (fr.flags & MIVIT_START_KNOWN);
-        if (!(fr.n_out == fr.n_stages || (term && fr.n_out + K - 1 == fr.n_stages))) ok = false;
-        gf[f].llr_off = fr.llr_offset;
-        gf[f].bit_off = fr.bit_offset;
-        gf[f].n_stages = fr.n_stages;
-        gf[f].n_out = fr.n_out;
-        gf[f].code = fr.code;
-        gf[f].pad = 0;
-        p->grad_max_stages = std::max(p->grad_max_stages, fr.n_stages);
-      }
-      if (ok) {
-        e = upload(&p->d_gframes, gf.data(), gf.size());
-        p->grad_ok = (e == hipSuccess);
-      }
+    bool grad = std::all_of(frames, frames + n_frames, [&](const mivit_frame& fr) {
+      return o.chunk == 0 || fr.n_stages <= o.chunk;
+    });
+    std::vector<GradFrame> gf(n_frames);
+    for (int f = 0; f < n_frames && grad; ++f) {
+      const mivit_frame& fr = frames[f];
+      const int K = codes[fr.code].K;
+      const bool term = (fr.flags & MIVIT_END_ZERO) && (fr.flags & MIVIT_START_KNOWN);
+      if (fr.out_begin != 0) grad = false;
+      if (!(fr.n_out == fr.n_stages || (term && fr.n_out + K - 1 == fr.n_stages))) grad = false;
+      gf[f].llr_off = fr.llr_offset;
+      gf[f].bit_off = fr.bit_offset;
+      gf[f].n_stages = fr.n_stages;
+      gf[f].n_out = fr.n_out;
+      gf[f].code = fr.code;
+      gf[f].pad = 0;
+      p->grad_max_stages = std::max(p->grad_max_stages, fr.n_stages);
     }
-    if (e != hipSuccess) {
-      mivit_status s = (e == hipErrorOutOfMemory) ? MIVIT_ENOMEM : MIVIT_EHIP;
-      free_plan(p);
-      return s;
+    if (grad && n_frames > 0) {
+      e = upload(&p->d_gframes, gf.data(), gf.size());
+      if (e != hipSuccess) throw hip_status(e);
+      p->grad_ok = true;
     }
+  } catch (mivit_status s) {
+    status = s;
   } catch (const std::bad_alloc&) {
-    free_plan(p);
-    return MIVIT_ENOMEM;
+    status = MIVIT_ENOMEM;
   } catch (...) {
+    status = MIVIT_EHIP;
+  }
+  if (p && p->origin) (void)hipStreamSynchronize(p->origin);
+  (void)hipFree(t_llr);
+  (void)hipFree(t_bits);
+  (void)hipFree(t_metric);
+  (void)hipFree(t_end);
+  if (status != MIVIT_OK) {
     free_plan(p);
-    return MIVIT_EHIP;
+    return status;
   }
   *out = p;
   return MIVIT_OK;
@@ -405,62 +662,62 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
 mivit_status mivit_forward(mivit_plan* p, const void* llr, void* metric, int32_t* end_state,
                            void* stream) {
   if (!p) return MIVIT_EINVAL;
-  if (p->items.empty()) return MIVIT_OK;
+  if (p->parts.empty()) return MIVIT_OK;
   if (!llr) return MIVIT_EINVAL;
   DeviceGuard guard(p->device);
-  hipStream_t st = (hipStream_t)stream;
-  const bool is_int = p->dtype == MIVIT_I8;
-  for (const PlanGroup& g : p->groups) {
-    hipError_t e;
-    if (g.kern == kKernRot4P)
-      e = launch_fwd_r4p(g.K, p->d_codes, p->d_items, p->d_waves + g.wave_off, g.n_waves,
-                         (const int8_t*)llr, p->d_surv, (int64_t*)metric, end_state,
-                         p->d_item_end, st);
-    else if (g.kern == kKernRot2)
-      e = launch_fwd_rot(g.K, g.beta, is_int, kRotMode[p->variant], p->d_codes, p->d_items,
-                         p->d_waves + g.wave_off,
-                         g.n_waves, llr, p->d_surv, metric, end_state, p->d_item_end, st);
-    else
-      e = launch_fwd(g.kern == kKernGeneric4 ? 4 : 2, g.nsl, is_int, p->d_codes,
-                     p->d_items + g.first, g.count, llr, p->d_surv, metric, end_state,
-                     p->d_item_end, st);
-    if (e != hipSuccess) return MIVIT_EHIP;
-  }
-  return MIVIT_OK;
+  return hip_status(run_parts(p, kPhaseForward, llr, nullptr, metric, end_state,
+                              (hipStream_t)stream));
 }
 
 mivit_status mivit_traceback(mivit_plan* p, uint32_t* bits, void* stream) {
   if (!p) return MIVIT_EINVAL;
-  if (p->items.empty()) return MIVIT_OK;
+  if (p->parts.empty()) return MIVIT_OK;
   if (!bits) return MIVIT_EINVAL;
   DeviceGuard guard(p->device);
-  for (const PlanGroup& g : p->groups) {
-    hipError_t e =
-        g.kern == kKernRot4P
-            ? launch_tb_r4p(g.K, p->d_items, p->d_pairs + g.pair_off, g.n_pairs, p->d_surv,
-                            p->d_item_end, bits, kWarmStages, (hipStream_t)stream)
-            : launch_tb_seg(g.layout, p->d_codes, p->d_items + g.first, g.count, p->d_surv,
-                            p->d_item_end, bits, kWarmStages, (hipStream_t)stream);
-    if (e != hipSuccess) return MIVIT_EHIP;
-  }
-  return MIVIT_OK;
+  return hip_status(run_parts(p, kPhaseTraceback, nullptr, bits, nullptr, nullptr,
+                              (hipStream_t)stream));
 }
 
 mivit_status mivit_decode(mivit_plan* p, const void* llr, uint32_t* bits, void* metric,
                           int32_t* end_state, void* stream) {
   if (!p) return MIVIT_EINVAL;
-  if (p->items.empty()) return MIVIT_OK;
+  if (p->parts.empty()) return MIVIT_OK;
   if (!llr || !bits) return MIVIT_EINVAL;
-  mivit_status s = mivit_forward(p, llr, metric, end_state, stream);
-  if (s != MIVIT_OK) return s;
-  return mivit_traceback(p, bits, stream);
+  DeviceGuard guard(p->device);
+  hipStream_t st = (hipStream_t)stream;
+  const int both = kPhaseForward | kPhaseTraceback;
+  if (!(p->flags & MIVIT_PLAN_GRAPH))
+    return hip_status(run_parts(p, both, llr, bits, metric, end_state, st));
+  for (const GraphEntry& g : p->graphs)
+    if (g.llr == llr && g.bits == bits && g.metric == metric && g.end == end_state &&
+        g.stream == st)
+      return hip_status(hipGraphLaunch(g.exec, st));
+  // record the launch sequence once on the plan's own stream, then replay
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipStreamBeginCapture(p->origin, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return MIVIT_EHIP;
+  hipError_t er = run_parts(p, both, llr, bits, metric, end_state, p->origin);
+  e = hipStreamEndCapture(p->origin, &graph);
+  if (er != hipSuccess || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return MIVIT_EHIP;
+  }
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return MIVIT_EHIP;
+  if (p->graphs.size() >= (size_t)kMaxGraphs) {
+    (void)hipGraphExecDestroy(p->graphs.front().exec);
+    p->graphs.erase(p->graphs.begin());
+  }
+  p->graphs.push_back(GraphEntry{llr, bits, metric, end_state, st, exec});
+  return hip_status(hipGraphLaunch(exec, st));
 }
 
 mivit_status mivit_decode_grad(mivit_plan* p, const uint32_t* bits, const float* grad_metric,
                                float* grad_llr, void* stream) {
   if (!p) return MIVIT_EINVAL;
-  if (!p->grad_ok) return MIVIT_EUNSUPPORTED;
-  if (p->n_frames == 0) return MIVIT_OK;
+  if (!p->grad_ok) return p->n_frames == 0 ? MIVIT_OK : MIVIT_EUNSUPPORTED;
   if (!bits || !grad_metric || !grad_llr) return MIVIT_EINVAL;
   DeviceGuard guard(p->device);
   hipError_t e = launch_grad(p->d_codes, p->d_gframes, p->n_frames, p->grad_max_stages, bits,
@@ -473,18 +730,44 @@ mivit_status mivit_plan_destroy(mivit_plan* p) {
   {
     DeviceGuard guard(p->device);
     (void)hipDeviceSynchronize();
+    free_plan(p);
   }
-  free_plan(p);
   return MIVIT_OK;
 }
 
 mivit_status mivit_plan_get_info(const mivit_plan* p, mivit_plan_info* info) {
   if (!p || !info) return MIVIT_EINVAL;
-  info->n_items = (int64_t)p->items.size();
-  info->survivor_bytes = p->surv_words * 8;
-  info->total_stages = p->total_stages;
-  info->radix = p->radix;
+  std::memset(info, 0, sizeof *info);
+  int64_t best = -1;
+  for (const Part& q : p->parts) {
+    info->n_items += (int64_t)q.items.size();
+    info->survivor_bytes += q.surv_words * 8;
+    info->total_stages += q.total_stages;
+    if (q.total_stages > best) {
+      best = q.total_stages;
+      info->radix = q.ch.radix;
+    }
+  }
+  if (best < 0) info->radix = 2;
   info->dtype = p->dtype;
+  return MIVIT_OK;
+}
+
+mivit_status mivit_plan_describe(const mivit_plan* p, char* buf, int32_t len) {
+  if (!p || !buf || len <= 0) return MIVIT_EINVAL;
+  std::string s;
+  for (const Part& q : p->parts) {
+    char line[256];
+    for (const PlanGroup& g : q.groups) {
+      std::snprintf(line, sizeof line,
+                    "%scode %d: K=%d beta=%d, %s forward, variant %d, %s, %d items, %d wavefronts",
+                    s.empty() ? "" : "; ", q.code, g.K, g.beta, kern_name(g.kern), q.ch.variant,
+                    g.counter >= 0 ? "persistent work queue" : "one wavefront per table entry",
+                    g.count, g.n_waves);
+      s += line;
+    }
+  }
+  std::snprintf(buf, (size_t)len, "%s", s.c_str());
   return MIVIT_OK;
 }
 

@@ -1,6 +1,7 @@
 // Device-side descriptors shared by the host plan code and the kernels of the
 // Viterbi decoder library.  Internal header (not part of the C ABI).
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace mivit {
@@ -39,6 +40,19 @@ struct GradFrame {
   int32_t code;
   int32_t pad;
 };
+
+// Workgroups a persistent grid of 'kernel' keeps resident on the device
+// (compute units times resident workgroups per unit), 0 if unknown.
+template <typename Kernel>
+inline int resident_workgroups(Kernel kernel, int threads) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess)
+    return 0;
+  return cus * per;
+}
 
 // Decision words per stage for a code with 2^(K-1) states.
 __host__ __device__ inline int words_per_stage(int K) {

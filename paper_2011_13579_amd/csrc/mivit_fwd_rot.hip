@@ -392,29 +392,22 @@ constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
 // receives the same number of frames (the wavefronts share nothing).
 constexpr int kRotWaves = 4;
 
+// The frames of wave-table entry 'wave', on one wavefront.
 template <int KM1, bool INT, int BETA, int MODE>
-__global__ __launch_bounds__(64 * kRotWaves) void k_fwd_rot(const DevCode* __restrict__ codes,
-                                                const Item* __restrict__ items,
-                                                const int2* __restrict__ waves, int n_waves,
-                                                const void* __restrict__ llr_v,
-                                                uint64_t* __restrict__ surv, void* metric,
-                                                int32_t* end_out, int32_t* item_end) {
+__device__ __forceinline__ void fwd_rot_wave(const DevCode* __restrict__ codes,
+                                             const Item* __restrict__ items,
+                                             const int2* __restrict__ waves, int wave,
+                                             const void* __restrict__ llr_v,
+                                             uint64_t* __restrict__ surv, void* metric,
+                                             int32_t* end_out, int32_t* item_end,
+                                             typename rot::Ty<INT>::T (*bmt)[32 << BETA],
+                                             typename rot::Ty<INT>::T* xpm, int lane) {
   using namespace rot;
   using T = typename Ty<INT>::T;
   using In = typename Ty<INT>::In;
   constexpr int NS = 1 << KM1;
-  constexpr int FPW = 64 / NS;
   constexpr int NP = 1 << BETA;
   constexpr int SUPER = 32 * KM1 / gcd_c(32, KM1);  // lcm(32, K-1)
-  __shared__ T bmt_all[kRotWaves][FPW][32 * NP];
-  __shared__ T xpm_all[kRotWaves][64];
-
-  const int wid = threadIdx.x >> 6;
-  const int wave = blockIdx.x * kRotWaves + wid;
-  if (wave >= n_waves) return;  // no workgroup barriers below: safe to leave
-  T(*bmt)[32 * NP] = bmt_all[wid];
-  T* xpm = xpm_all[wid];
-  const int lane = threadIdx.x & 63;
   const int fr = lane / NS, sl = lane % NS;
   // this wave's frames: waves[w] = (first item, count), all of equal length
   const int2 wv = waves[wave];
@@ -476,36 +469,74 @@ __global__ __launch_bounds__(64 * kRotWaves) void k_fwd_rot(const DevCode* __res
   }
 }
 
+// One wavefront per wave-table entry, or (counter != nullptr) a persistent
+// grid whose wavefronts take entries in table order (longest frames first)
+// from a device counter that starts at zero, until the table is exhausted.
+template <int KM1, bool INT, int BETA, int MODE>
+__global__ __launch_bounds__(64 * kRotWaves) void k_fwd_rot(const DevCode* __restrict__ codes,
+                                                const Item* __restrict__ items,
+                                                const int2* __restrict__ waves, int n_waves,
+                                                const void* __restrict__ llr_v,
+                                                uint64_t* __restrict__ surv, void* metric,
+                                                int32_t* end_out, int32_t* item_end,
+                                                int32_t* counter) {
+  using T = typename rot::Ty<INT>::T;
+  constexpr int FPW = 64 >> KM1;
+  __shared__ T bmt_all[kRotWaves][FPW][32 << BETA];
+  __shared__ T xpm_all[kRotWaves][64];
+  const int wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  if (counter == nullptr) {
+    const int wave = blockIdx.x * kRotWaves + wid;
+    if (wave >= n_waves) return;  // no workgroup barriers: safe to leave
+    fwd_rot_wave<KM1, INT, BETA, MODE>(codes, items, waves, wave, llr_v, surv, metric, end_out,
+                                       item_end, bmt_all[wid], xpm_all[wid], lane);
+    return;
+  }
+  for (;;) {
+    int w = 0;
+    if (lane == 0) w = atomicAdd(counter, 1);
+    w = __builtin_amdgcn_readfirstlane(w);
+    if (w >= n_waves) break;
+    fwd_rot_wave<KM1, INT, BETA, MODE>(codes, items, waves, w, llr_v, surv, metric, end_out,
+                                       item_end, bmt_all[wid], xpm_all[wid], lane);
+  }
+}
+
 hipError_t launch_fwd_rot(int K, int beta, bool is_int, int mode, const DevCode* codes,
                           const Item* items, const int2* waves, int n_waves, const void* llr,
                           uint64_t* surv, void* metric, int32_t* end_out, int32_t* item_end,
-                          hipStream_t st) {
+                          int32_t* counter, int grid_limit, hipStream_t st) {
   if (n_waves <= 0) return hipSuccess;
-  dim3 grid((n_waves + kRotWaves - 1) / kRotWaves), block(64 * kRotWaves);
-#define MV_ROT(KM1, I, B)                                                                     \
-  if (mode == 2)                                                                              \
-    hipLaunchKernelGGL((k_fwd_rot<KM1, I, B, 2>), grid, block, 0, st, codes, items, waves, n_waves, llr, \
-                       surv, metric, end_out, item_end);                                      \
-  else if (mode == 1)                                                                         \
-    hipLaunchKernelGGL((k_fwd_rot<KM1, I, B, 1>), grid, block, 0, st, codes, items, waves, n_waves, llr, \
-                       surv, metric, end_out, item_end);                                      \
-  else                                                                                        \
-    hipLaunchKernelGGL((k_fwd_rot<KM1, I, B, 0>), grid, block, 0, st, codes, items, waves, n_waves, llr, \
-                       surv, metric, end_out, item_end)
-#define MV_ROT_B(KM1, I)         \
-  switch (beta) {                \
-    case 2: MV_ROT(KM1, I, 2); break; \
-    case 3: MV_ROT(KM1, I, 3); break; \
-    case 4: MV_ROT(KM1, I, 4); break; \
+  const int threads = 64 * kRotWaves;
+  auto go = [&](auto kernel) -> hipError_t {
+    int nb = (n_waves + kRotWaves - 1) / kRotWaves;
+    if (counter) {
+      const int lim = grid_limit > 0 ? grid_limit : resident_workgroups(kernel, threads);
+      if (lim > 0 && nb > lim) nb = lim;
+    }
+    hipLaunchKernelGGL(kernel, dim3(nb), dim3(threads), 0, st, codes, items, waves, n_waves, llr,
+                       surv, metric, end_out, item_end, counter);
+    return hipGetLastError();
+  };
+#define MV_ROT(KM1, I, B)                                                   \
+  return mode == 2   ? go(k_fwd_rot<KM1, I, B, 2>)                         \
+         : mode == 1 ? go(k_fwd_rot<KM1, I, B, 1>)                         \
+                     : go(k_fwd_rot<KM1, I, B, 0>)
+#define MV_ROT_B(KM1, I)              \
+  switch (beta) {                     \
+    case 2: MV_ROT(KM1, I, 2);        \
+    case 3: MV_ROT(KM1, I, 3);        \
+    case 4: MV_ROT(KM1, I, 4);        \
     default: return hipErrorInvalidValue; \
   }
-#define MV_ROT_K(I)                  \
-  switch (K) {                       \
-    case 3: MV_ROT_B(2, I); break;   \
-    case 4: MV_ROT_B(3, I); break;   \
-    case 5: MV_ROT_B(4, I); break;   \
-    case 6: MV_ROT_B(5, I); break;   \
-    case 7: MV_ROT_B(6, I); break;   \
+#define MV_ROT_K(I)                   \
+  switch (K) {                        \
+    case 3: MV_ROT_B(2, I);           \
+    case 4: MV_ROT_B(3, I);           \
+    case 5: MV_ROT_B(4, I);           \
+    case 6: MV_ROT_B(5, I);           \
+    case 7: MV_ROT_B(6, I);           \
     default: return hipErrorInvalidValue; \
   }
   if (is_int) {
@@ -516,7 +547,6 @@ hipError_t launch_fwd_rot(int K, int beta, bool is_int, int mode, const DevCode*
 #undef MV_ROT_K
 #undef MV_ROT_B
 #undef MV_ROT
-  return hipGetLastError();
 }
 
 }  // namespace mivit

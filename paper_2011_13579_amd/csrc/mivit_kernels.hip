@@ -494,3 +494,47 @@ hipError_t launch_quant(const float* x, int8_t* q, int64_t n, float scale, hipSt
 }
 
 }  // namespace mivit
+
+namespace mivit {
+
+// Work counters of the persistent forward kernels start at zero; a kernel
+// (not a memset) clears them so that the launch sequence can be recorded in
+// a graph and replayed.
+__global__ __launch_bounds__(64) void k_zero_i32(int32_t* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// Deterministic pseudo-random soft values for the autotuner's timing runs
+// (an integer hash of the index; no statistical claims).
+__global__ __launch_bounds__(256) void k_fill_random(void* __restrict__ p, int64_t n, int is_int,
+                                                     uint32_t seed) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+    uint32_t x = (uint32_t)k * 0x9E3779B1u ^ seed;
+    x ^= x >> 15;
+    x *= 0x85EBCA77u;
+    x ^= x >> 13;
+    if (is_int)
+      ((int8_t*)p)[k] = (int8_t)((int)(x % 129u) - 64);
+    else
+      ((float*)p)[k] = ((float)(x & 0xFFFFu) * (1.0f / 65536.0f) - 0.5f) * 8.0f;
+  }
+}
+
+hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_i32, dim3((n + 63) / 64), dim3(64), 0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_random(void* p, int64_t n, bool is_int, uint32_t seed, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_random, dim3((unsigned)blocks), dim3(256), 0, st, p, n, is_int ? 1 : 0,
+                     seed);
+  return hipGetLastError();
+}
+
+}  // namespace mivit

@@ -288,18 +288,15 @@ constexpr int kR4Waves = 4;
 // One wavefront decodes up to 2 * 64 / 2^(K-1) frames of equal length:
 // lane group m (2^(K-1) lanes) holds frames 2m (low halves) and 2m+1 (high).
 template <int ND>
-__global__ __launch_bounds__(64 * r4p::kR4Waves) void k_fwd_r4p(
-    const DevCode* __restrict__ codes, const Item* __restrict__ items,
-    const int2* __restrict__ waves, int n_waves, const int8_t* __restrict__ llr,
-    uint64_t* __restrict__ surv, int64_t* metric, int32_t* end_out, int32_t* item_end) {
+__device__ __forceinline__ void fwd_r4p_wave(const DevCode* __restrict__ codes,
+                                             const Item* __restrict__ items,
+                                             const int2* __restrict__ waves, int wave,
+                                             const int8_t* __restrict__ llr,
+                                             uint64_t* __restrict__ surv, int64_t* metric,
+                                             int32_t* end_out, int32_t* item_end,
+                                             uint32_t (*tbl_w)[16 * 16], int lane) {
   using namespace r4p;
-  constexpr int KM1 = 2 * ND, NS = 1 << KM1, FPG = 64 / NS, PPL = 256 / NS;
-  __shared__ uint32_t tbl_all[kR4Waves][FPG][16 * 16];
-
-  const int wid = threadIdx.x >> 6;
-  const int wave = blockIdx.x * kR4Waves + wid;
-  if (wave >= n_waves) return;  // no workgroup barriers below
-  const int lane = threadIdx.x & 63;
+  constexpr int KM1 = 2 * ND, NS = 1 << KM1, PPL = 256 / NS;
   const int m = lane / NS, r = lane % NS;
   const int2 wv = waves[wave];
   const bool va = 2 * m < wv.y, vb = 2 * m + 1 < wv.y;
@@ -311,7 +308,7 @@ __global__ __launch_bounds__(64 * r4p::kR4Waves) void k_fwd_r4p(
   const int lead = S & 1, n_it = S >> 1;
 
   Fwd<ND> F;
-  F.tbl = &tbl_all[wid][m][0];
+  F.tbl = &tbl_w[m][0];
   F.r = r;
   F.n_it = n_it;
   F.ib = r & 15;
@@ -595,19 +592,51 @@ __global__ __launch_bounds__(64) void k_tb_r4p(const Item* __restrict__ items,
   }
 }
 
+// One wavefront per wave-table entry, or (counter != nullptr) a persistent
+// grid whose wavefronts take entries in table order from a device counter
+// that starts at zero, until the table is exhausted.
+template <int ND>
+__global__ __launch_bounds__(64 * r4p::kR4Waves) void k_fwd_r4p(
+    const DevCode* __restrict__ codes, const Item* __restrict__ items,
+    const int2* __restrict__ waves, int n_waves, const int8_t* __restrict__ llr,
+    uint64_t* __restrict__ surv, int64_t* metric, int32_t* end_out, int32_t* item_end,
+    int32_t* counter) {
+  constexpr int FPG = 64 >> (2 * ND);
+  __shared__ uint32_t tbl_all[r4p::kR4Waves][FPG][16 * 16];
+  const int wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  if (counter == nullptr) {
+    const int wave = blockIdx.x * r4p::kR4Waves + wid;
+    if (wave >= n_waves) return;  // no workgroup barriers: safe to leave
+    fwd_r4p_wave<ND>(codes, items, waves, wave, llr, surv, metric, end_out, item_end,
+                     tbl_all[wid], lane);
+    return;
+  }
+  for (;;) {
+    int w = 0;
+    if (lane == 0) w = atomicAdd(counter, 1);
+    w = __builtin_amdgcn_readfirstlane(w);
+    if (w >= n_waves) break;
+    fwd_r4p_wave<ND>(codes, items, waves, w, llr, surv, metric, end_out, item_end,
+                     tbl_all[wid], lane);
+  }
+}
+
 hipError_t launch_fwd_r4p(int K, const DevCode* codes, const Item* items, const int2* waves,
                           int n_waves, const int8_t* llr, uint64_t* surv, int64_t* metric,
-                          int32_t* end_out, int32_t* item_end, hipStream_t st) {
+                          int32_t* end_out, int32_t* item_end, int32_t* counter, int grid_limit,
+                          hipStream_t st) {
   if (n_waves <= 0) return hipSuccess;
-  dim3 grid((n_waves + r4p::kR4Waves - 1) / r4p::kR4Waves), block(64 * r4p::kR4Waves);
-  if (K == 7)
-    hipLaunchKernelGGL(k_fwd_r4p<3>, grid, block, 0, st, codes, items, waves, n_waves, llr, surv,
-                       metric, end_out, item_end);
-  else if (K == 5)
-    hipLaunchKernelGGL(k_fwd_r4p<2>, grid, block, 0, st, codes, items, waves, n_waves, llr, surv,
-                       metric, end_out, item_end);
-  else
-    return hipErrorInvalidValue;
+  if (K != 5 && K != 7) return hipErrorInvalidValue;
+  auto kernel = K == 7 ? k_fwd_r4p<3> : k_fwd_r4p<2>;
+  const int threads = 64 * r4p::kR4Waves;
+  int nb = (n_waves + r4p::kR4Waves - 1) / r4p::kR4Waves;
+  if (counter) {
+    const int lim = grid_limit > 0 ? grid_limit : resident_workgroups(kernel, threads);
+    if (lim > 0 && nb > lim) nb = lim;
+  }
+  hipLaunchKernelGGL(kernel, dim3(nb), dim3(threads), 0, st, codes, items, waves, n_waves, llr,
+                     surv, metric, end_out, item_end, counter);
   return hipGetLastError();
 }
 

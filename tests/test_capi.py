@@ -106,10 +106,31 @@ def test_overlapping_outputs():
 
 @pytest.mark.parametrize("opts", [
     dict(dtype=2), dict(radix=3), dict(radix=4, dtype=0), dict(chunk=-1), dict(chunk=100),
-    dict(overlap=-1),
+    dict(overlap=-1), dict(variant=3), dict(flags=8), dict(flags=1 << 31),
 ])
 def test_bad_opts(opts):
     assert _plan_status([K7], _frame(), **opts) == _capi.MIVIT_EINVAL
+
+
+def test_reserved_opts_must_be_zero():
+    for k in range(2):
+        lib = _capi.load()
+        arr = (_capi.Code * 1)(K7)
+        o = _capi.Opts()
+        o.reserved[k] = 1
+        h = ctypes.c_void_p()
+        fr = _frame()
+        assert lib.mivit_plan_create(ctypes.byref(h), arr, 1, fr.ctypes.data, 1,
+                                     ctypes.byref(o)) == _capi.MIVIT_EINVAL
+        assert not h.value
+
+
+def test_plan_flag_values():
+    """The flag constants of the binding match the header's."""
+    text = open(os.path.join(ROOT, "include", "mivit.h")).read()
+    for name in ("MIVIT_PLAN_GRAPH", "MIVIT_PLAN_AUTOTUNE", "MIVIT_PLAN_PERSISTENT"):
+        m = re.search(r"#define %s (\d+)u" % name, text)
+        assert m and int(m.group(1)) == getattr(_capi, name)
 
 
 def test_null_and_misc():
@@ -119,6 +140,7 @@ def test_null_and_misc():
     assert lib.mivit_decode_grad(None, None, None, None, None) == _capi.MIVIT_EINVAL
     assert lib.mivit_plan_destroy(None) == _capi.MIVIT_EINVAL
     assert lib.mivit_plan_get_info(None, None) == _capi.MIVIT_EINVAL
+    assert lib.mivit_plan_describe(None, None, 0) == _capi.MIVIT_EINVAL
     assert lib.mivit_quantize_i8(None, None, -1, 1.0, None) == _capi.MIVIT_EINVAL
     assert lib.mivit_quantize_i8(None, None, 10, 1.0, None) == _capi.MIVIT_EINVAL
     assert lib.mivit_quantize_i8(None, None, 0, 0.0, None) == _capi.MIVIT_EINVAL

@@ -345,3 +345,103 @@ def test_plan_reuse_and_empty():
         bits, m = gpu_decode(b.llr, code, 100)
         ob, om, _ = oracle.decode_uniform(code, b.llr, 100, True, oracle.F32)
         np.testing.assert_array_equal(bits, ob)
+
+
+def _mixed(dtype, F=240, seed=4):
+    """Uneven frames of three codes (K=5 r1/2, K=7 r1/2, K=9 r1/3), log-uniform
+    lengths, per-frame Eb/N0, packed back to back."""
+    from workload import make_mixed_batch
+    codes = [CODE_K5, CODE_K7, CODE_K9]
+    mb = make_mixed_batch(codes, F, 64, 2048, 1.0, 5.0, seed=seed)
+    n = mb.n_info.astype(np.int64)
+    K = np.array([codes[c].K for c in mb.code_idx])
+    S = n + K - 1
+    fr = np.zeros(F, mv.FRAME_DTYPE)
+    ofr = np.zeros(F, oracle.FRAME_DTYPE)
+    for f in range(F):
+        fr[f] = (mb.llr_offset[f], mb.bit_offset[f], S[f], 0, n[f], mb.code_idx[f],
+                 mv.MIVIT_START_KNOWN | mv.MIVIT_END_ZERO)
+        ofr[f] = (mb.llr_offset[f], mb.bit_offset[f], S[f], 0, n[f], 1, 0, mb.code_idx[f])
+    llr = mb.llr if dtype == "f32" else oracle.quantize_i8(mb.llr, 6.0)
+    n_bits = int(mb.bit_offset[-1] + ((n[-1] + 31) // 32) * 32)
+    return codes, fr, ofr, llr, n_bits
+
+
+def _check_mixed(codes, plan, fr, ofr, llr_np, dtype, n_bits, words=None):
+    t = torch.from_numpy(np.ascontiguousarray(llr_np)).to(DEV)
+    if words is None:
+        words, metric, end = plan.decode(t)
+        torch.cuda.synchronize()
+        metric = metric.cpu().numpy()
+    else:
+        metric = None
+    bits = mv.unpack_bits(words.cpu().numpy()[: n_bits // 32], n_bits)
+    mode = oracle.F32 if dtype == "f32" else oracle.I64
+    ob, om, _, _ = oracle.decode_frames(codes, ofr, llr_np, mode, n_bits)
+    for k in range(len(fr)):
+        a, n = int(ofr[k]["bit_offset"]), int(ofr[k]["n_out"])
+        np.testing.assert_array_equal(bits[a:a + n], ob[a:a + n])
+    if metric is not None:
+        np.testing.assert_array_equal(metric[: len(fr)], om)
+
+
+@pytest.mark.parametrize("dtype", ["i8", "f32"])
+@pytest.mark.parametrize("mode", ["default", "persistent", "autotune"])
+def test_mixed_codes_batch(dtype, mode):
+    """Uneven frames of three codes in one plan: one part per code, run
+    concurrently; persistent work-queue and autotuned plans give the same
+    bits and metrics as the oracle."""
+    codes, fr, ofr, llr, n_bits = _mixed(dtype)
+    radix = 4 if (dtype == "i8" and mode != "autotune") else 0
+    print("mixed", dtype, mode, flush=True)
+    plan = mv.Plan(codes, fr, dtype, radix, persistent=(mode == "persistent"),
+                   autotune=(mode == "autotune"))
+    desc = plan.describe()
+    print(desc, flush=True)
+    assert desc.count("code ") == 3
+    if mode == "persistent":
+        assert "persistent work queue" in desc
+    _check_mixed(codes, plan, fr, ofr, llr, dtype, n_bits)
+
+
+def test_graph_replays():
+    """A plan recorded in a hipGraph: replays, interleaved with eager work and
+    synchronisation, all equal the eager decode."""
+    codes, fr, ofr, llr, n_bits = _mixed("i8", F=120, seed=9)
+    t = torch.from_numpy(llr).to(DEV)
+    eager = mv.Plan(codes, fr, "i8", 4)
+    ew, em, ee = eager.decode(t)
+    torch.cuda.synchronize()
+    gplan = mv.Plan(codes, fr, "i8", 4, graph=True)
+    bits, metric, end = gplan.empty_outputs(DEV)
+    for rep in range(4):
+        bits.fill_(-1)
+        metric.fill_(7)
+        gplan.decode(t, bits, metric, end)
+        x = torch.randn(1 << 20, device=DEV).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.isfinite(x)
+        np.testing.assert_array_equal(bits.cpu().numpy(), ew.cpu().numpy())
+        np.testing.assert_array_equal(metric.cpu().numpy(), em.cpu().numpy())
+        np.testing.assert_array_equal(end.cpu().numpy(), ee.cpu().numpy())
+    _check_mixed(codes, gplan, fr, ofr, llr, "i8", n_bits, words=bits)
+
+
+@pytest.mark.parametrize("dtype", ["i8", "f32"])
+def test_persistent_single_code_full_shape(dtype):
+    """Persistent launches on the 4096 x 8192 K=7 shape equal the plain ones."""
+    from workload import int8_scale_for
+    F, n = 4096, 8192
+    b = make_uniform_batch(CODE_K7, F, n, 2.0, seed=2002)
+    llr = b.llr if dtype == "f32" else oracle.quantize_i8(b.llr, int8_scale_for(2.0, 2))
+    t = torch.from_numpy(llr).to(DEV)
+    fr = mv.uniform_frames(CODE_K7, F, n, True)
+    radix = 4 if dtype == "i8" else 2
+    out = []
+    for pers in (False, True):
+        plan = mv.Plan([CODE_K7], fr, dtype, radix, persistent=pers)
+        w, m, e = plan.decode(t)
+        torch.cuda.synchronize()
+        out.append((w.cpu().numpy(), m.cpu().numpy()))
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])

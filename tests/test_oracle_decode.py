@@ -264,3 +264,31 @@ def test_quantizer_pins():
     # scale 4: 0.375 -> 1.5 -> 2, 0.625 -> 2.5 -> 2, -0.875 -> -3.5 -> -4
     np.testing.assert_array_equal(
         oracle.quantize_i8(np.array([0.375, 0.625, -0.875], np.float32), 4.0), [2, 2, -4])
+
+
+def test_mixed_codes_one_call():
+    """Frames of different codes (16 to 256 states, long frames first) in one
+    call decode exactly as each code's frames decoded alone."""
+    from workload import CODE_K5, CODE_K9, make_mixed_batch
+    codes = [CODE_K5, CODE_K7, CODE_K9]
+    mb = make_mixed_batch(codes, 60, 64, 1500, 1.0, 5.0, seed=21)
+    n = mb.n_info.astype(np.int64)
+    K = np.array([codes[c].K for c in mb.code_idx])
+    fr = np.zeros(len(n), oracle.FRAME_DTYPE)
+    for f in range(len(n)):
+        fr[f] = (mb.llr_offset[f], mb.bit_offset[f], n[f] + K[f] - 1, 0, n[f], 1, 0, mb.code_idx[f])
+    order = np.argsort(-(n + K))  # long K=5 frames before short K=9 frames
+    fr = fr[order]
+    q = oracle.quantize_i8(mb.llr, 6.0)
+    n_bits = int(mb.bit_offset.max() + 2048)
+    for threads in (1, 3):
+        bits, metric, _, _ = oracle.decode_frames(codes, fr, q, oracle.I64, n_bits, n_threads=threads)
+        for c in range(3):
+            sel = fr["code"] == c
+            sub = fr[sel].copy()
+            sub["code"] = 0
+            b1, m1, _, _ = oracle.decode_frames([codes[c]], sub, q, oracle.I64, n_bits, n_threads=1)
+            np.testing.assert_array_equal(metric[sel], m1)
+            for row in sub:
+                a, k = int(row["bit_offset"]), int(row["n_out"])
+                np.testing.assert_array_equal(bits[a:a + k], b1[a:a + k])
