@@ -445,3 +445,85 @@ def test_persistent_single_code_full_shape(dtype):
         out.append((w.cpu().numpy(), m.cpu().numpy()))
     np.testing.assert_array_equal(out[0][0], out[1][0])
     np.testing.assert_array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("radix", [4, 2])
+def test_stream_2p26_chunked_full(radix):
+    """A 2^26-bit stream (K=7, 4 dB, int8) in 2048-stage chunks with 64 stages
+    of overlap on each side; 66 sampled windows (first, last and 64 seeded)
+    equal the oracle decoding the same windows; BER reported and bounded."""
+    from workload import int8_scale_for
+    n = 1 << 26
+    msg, llr = make_stream(CODE_K7, n, 4.0, seed=3)
+    q = oracle.quantize_i8(llr, int8_scale_for(4.0, 2))
+    del llr
+    t = torch.from_numpy(q).to(DEV)
+    print("stream", radix, flush=True)
+    words = mv.decode_stream(t, CODE_K7, n, 2048, 64, radix)
+    torch.cuda.synchronize()
+    bits = mv.unpack_bits(words.cpu().numpy(), n)
+    del t
+    fr = oracle.chunked_frames(CODE_K7, n, 2048, 64)
+    rng = np.random.default_rng(33)
+    pick = np.unique(np.concatenate([[0, len(fr) - 1], rng.choice(len(fr), 64, replace=False)]))
+    sub = fr[pick]
+    ob, _, _, _ = oracle.decode_frames([CODE_K7], sub, q, oracle.I64, n)
+    for row in sub:
+        a, k = int(row["bit_offset"]), int(row["n_out"])
+        np.testing.assert_array_equal(bits[a:a + k], ob[a:a + k])
+    ber = float((bits != msg).mean())
+    print("stream BER %.3e" % ber, flush=True)
+    assert ber < 1e-3
+
+
+@pytest.mark.parametrize("dtype", ["i8", "f32"])
+def test_mixed_10000_frames_autotuned_graph(dtype):
+    """10000 frames, lengths log-uniform in [64, 16384], codes K=5 (23,35),
+    K=7 (133,171), K=9 r1/3 (557,663,711), Eb/N0 ~ U[1,5] (int8 scale per
+    frame): one autotuned plan whose decode is recorded in a hipGraph and
+    replayed; 120 seeded sample frames equal the oracle."""
+    from workload import int8_scale_for, make_mixed_batch
+    codes = [CODE_K5, CODE_K7, CODE_K9]
+    F = 10000
+    mb = make_mixed_batch(codes, F, 64, 16384, 1.0, 5.0, seed=4)
+    n = mb.n_info.astype(np.int64)
+    K = np.array([codes[c].K for c in mb.code_idx])
+    beta = np.array([codes[c].beta for c in mb.code_idx])
+    S = n + K - 1
+    fr = np.zeros(F, mv.FRAME_DTYPE)
+    ofr = np.zeros(F, oracle.FRAME_DTYPE)
+    for f in range(F):
+        fr[f] = (mb.llr_offset[f], mb.bit_offset[f], S[f], 0, n[f], mb.code_idx[f],
+                 mv.MIVIT_START_KNOWN | mv.MIVIT_END_ZERO)
+        ofr[f] = (mb.llr_offset[f], mb.bit_offset[f], S[f], 0, n[f], 1, 0, mb.code_idx[f])
+    if dtype == "i8":
+        llr = np.empty(mb.llr.shape, np.int8)
+        for f in range(F):
+            a, b = int(mb.llr_offset[f]), int(mb.llr_offset[f] + S[f] * beta[f])
+            llr[a:b] = oracle.quantize_i8(mb.llr[a:b], int8_scale_for(float(mb.ebn0_db[f]), int(beta[f])))
+        mode = oracle.I64
+    else:
+        llr = mb.llr
+        mode = oracle.F32
+    print("mixed10000", dtype, flush=True)
+    plan = mv.Plan(codes, fr, dtype, 0, autotune=True, graph=True)
+    print(plan.describe(), flush=True)
+    t = torch.from_numpy(llr).to(DEV)
+    bits_t, metric_t, end_t = plan.empty_outputs(DEV)
+    for _ in range(2):
+        plan.decode(t, bits_t, metric_t, end_t)
+        torch.cuda.synchronize()
+    n_bits = int(mb.bit_offset[-1] + ((n[-1] + 31) // 32) * 32)
+    bits = mv.unpack_bits(bits_t.cpu().numpy()[: n_bits // 32], n_bits)
+    metric = metric_t.cpu().numpy()[:F]
+    rng = np.random.default_rng(44)
+    pick = np.sort(rng.choice(F, 120, replace=False))
+    ob, om, _, _ = oracle.decode_frames(codes, ofr[pick], llr, mode, n_bits)
+    np.testing.assert_array_equal(metric[pick], om)
+    for row in ofr[pick]:
+        a, k = int(row["bit_offset"]), int(row["n_out"])
+        np.testing.assert_array_equal(bits[a:a + k], ob[a:a + k])
+    errs = sum(int((bits[int(mb.bit_offset[f]):int(mb.bit_offset[f] + n[f])] != mb.msgs[f]).sum())
+               for f in range(F))
+    print("mixed BER %.3e" % (errs / n.sum()), flush=True)
+    assert errs / n.sum() < 2e-2
