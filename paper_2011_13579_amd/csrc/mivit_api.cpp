@@ -47,6 +47,13 @@ using namespace mivit;
 enum : int { kKernGeneric2 = 0, kKernGeneric4 = 1, kKernRot2 = 2, kKernRot4P = 3 };
 enum : int { kLayoutNatR2 = 0, kLayoutNatR4 = 1, kLayoutRotR2 = 2, kLayoutRot4P = 3 };
 constexpr int kWarmStages = 64;  // speculative traceback warm-up
+// The packed radix-4 traceback runs one wavefront per frame pair, so one
+// mis-started segment (whose boundary state disagrees with the exact lane
+// above) re-chases a whole segment while the rest of the grid idles: a
+// longer warm-up that makes repairs rare costs less than the repairs
+// (4096 x 8192 K=7 frames at 3 dB: 64 stages 0.095 ms, 80 0.085, 96 0.073,
+// 112 0.073, 128 0.076).  The radix-2 tracebacks measured best at 64.
+constexpr int kWarmStagesR4P = 96;
 // rotating forward kernel exchange scheme per plan variant:
 // 0 all exchanges in the VALU (DPP, permlane swaps), 1 both previous-state
 // metrics via DPP/LDS swizzles, 2 one partner metric via DPP/LDS swizzles
@@ -369,7 +376,7 @@ hipError_t part_traceback(const mivit_plan* p, const Part& q, uint32_t* bits, hi
     hipError_t e =
         g.kern == kKernRot4P
             ? launch_tb_r4p(g.K, q.d_items, q.d_pairs + g.pair_off, g.n_pairs, q.d_surv,
-                            q.d_item_end, bits, kWarmStages, st)
+                            q.d_item_end, bits, kWarmStagesR4P, st)
             : launch_tb_seg(g.layout, p->d_codes, q.d_items + g.first, g.count, q.d_surv,
                             q.d_item_end, bits, kWarmStages, st);
     if (e != hipSuccess) return e;

@@ -527,3 +527,42 @@ def test_mixed_10000_frames_autotuned_graph(dtype):
                for f in range(F))
     print("mixed BER %.3e" % (errs / n.sum()), flush=True)
     assert errs / n.sum() < 2e-2
+
+
+def test_r4_packed_varied_frames():
+    """Packed K=7 radix-4 plans (direct and persistent launches) give the
+    oracle's bits, metrics and end states on frames of 1 to 9001 stages, odd
+    and even, known and unknown starts, zero and best ends, in wavefront
+    entries holding one or both frames of a pair."""
+    rng = np.random.default_rng(4242)
+    lens = [1, 2, 3, 5, 17, 64, 65, 127, 300, 1001, 4093, 9001]
+    for copies in (1, 3):
+        cases = [(S, sk, ez) for S in lens for sk in (0, 1) for ez in (0, 1)
+                 if not (ez and S < 7)]
+        cases = [cs for cs in cases for _ in range(copies)]
+        fr = np.zeros(len(cases), mv.FRAME_DTYPE)
+        ofr = np.zeros(len(cases), oracle.FRAME_DTYPE)
+        off = nb = 0
+        for k, (S, sk, ez) in enumerate(cases):
+            n_out = S - 6 if ez else S
+            flags = (mv.MIVIT_START_KNOWN if sk else 0) | (mv.MIVIT_END_ZERO if ez else 0)
+            fr[k] = (off, nb, S, 0, n_out, 0, flags)
+            ofr[k] = (off, nb, S, 0, n_out, sk, 0 if ez else -1, 0)
+            off += 2 * S
+            nb += ((n_out + 31) // 32) * 32
+        llr = np.where(rng.random(off) < 0.1, rng.integers(-128, 128, off),
+                       rng.integers(-20, 21, off)).astype(np.int8)
+        t = torch.from_numpy(llr).to(DEV)
+        ob, om, oend, _ = oracle.decode_frames([CODE_K7], ofr, llr, oracle.I64, nb)
+        for pers in (False, True):
+            print("varied", copies, pers, flush=True)
+            plan = mv.Plan([CODE_K7], fr, "i8", 4, persistent=pers)
+            assert "packed" in plan.describe()
+            w, m, e = plan.decode(t)
+            torch.cuda.synchronize()
+            bits = mv.unpack_bits(w.cpu().numpy()[: nb // 32], nb)
+            np.testing.assert_array_equal(m.cpu().numpy()[: len(fr)], om)
+            np.testing.assert_array_equal(e.cpu().numpy()[: len(fr)], oend)
+            for k in range(len(fr)):
+                s, n = int(ofr[k]["bit_offset"]), int(ofr[k]["n_out"])
+                np.testing.assert_array_equal(bits[s:s + n], ob[s:s + n])
