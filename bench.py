@@ -177,9 +177,9 @@ def ber_sweep(torch, mv, code, frames_plan_i8, frames_plan_f32):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (frames shard across GPUs with no "
-              "exchange; see the design notes); --gpus %d is not supported" % args.gpus,
-              file=sys.stderr)
+        print("bench.py measures one GPU only: frames are independent, so N GPUs would each "
+              "decode their own shard of frames with no exchange; --gpus %d is not supported"
+              % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2011_13579_amd as mv

@@ -49,7 +49,7 @@ typedef enum {
   MIVIT_EINVAL = -1,       /* invalid argument or descriptor */
   MIVIT_ENOMEM = -2,       /* device or host allocation failed */
   MIVIT_EHIP = -3,         /* a HIP runtime call failed */
-  MIVIT_EUNSUPPORTED = -4  /* valid request this build does not implement */
+  MIVIT_EUNSUPPORTED = -4  /* valid request the library does not implement */
 } mivit_status;
 
 typedef enum { MIVIT_F32 = 0, MIVIT_I8 = 1 } mivit_dtype;

@@ -21,7 +21,7 @@ What each function follows (arXiv 2011.13579):
                     soft values: by Eq. (BM) the metric is a sum of
                     (-1)^{bit} l terms along the decoded path.
 
-Readings where the paper is silent (listed again in the design doc): a tie in
+Readings where the paper is silent: a tie in
 Eq. (PM) keeps the lower-index previous state; the final state of a
 terminated frame is state 0, otherwise the best state with ties to the lowest
 index; a known start gives every other state minus infinity, an unknown start
