@@ -46,9 +46,10 @@
 // state at time 1.
 //
 // Survivor layout of a frame pair (lane group of NS lanes): for each group
-// of 8 iterations, NS words; word G*NS + R holds, for the state in lane R
-// after iterations 8G..8G+7, the tags of frame A in bits 15..0 (iteration
-// 8G+k in bits 15-2k..14-2k) and of frame B in bits 31..16.
+// of 8 iterations, NS words; word G*NS + R holds the tags the state in lane R
+// won in iterations 8G..8G+7: iteration 8G+k, frame h (0 = A, 1 = B) in bits
+// 16 (k & 1) + 8 h + 2 (k >> 1) and the bit above.  Two consecutive
+// iterations are gathered by one byte permutation of their max results.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -61,7 +62,7 @@ namespace r4p {
 constexpr uint32_t kBase = 16384;
 constexpr uint32_t kBase2 = kBase | (kBase << 16);
 constexpr uint32_t kStrip = 0xFFFCFFFCu;
-constexpr uint32_t kTags = 0x00030003u;
+constexpr uint32_t kTagBytes = 0x03030303u;
 constexpr int kBias = 2048;   // 4 * max |super-branch metric| for |l| <= 128
 constexpr int kLeadOff = 256;  // max |branch metric| of one stage
 
@@ -70,11 +71,6 @@ typedef unsigned short us2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t pk_max(uint32_t a, uint32_t b) {
   return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(us2, a),
                                                                 __builtin_bit_cast(us2, b)));
-}
-
-__device__ __forceinline__ uint32_t pk_shl(uint32_t a, int s) {
-  const us2 sh = {(unsigned short)s, (unsigned short)s};
-  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(us2, a) << sh);
 }
 
 __device__ __forceinline__ int parity(uint32_t x) { return __popc(x) & 1; }
@@ -145,14 +141,17 @@ struct Fwd {
   uint32_t w0, w1;            // soft values of this lane's row, current block
   uint32_t V;                 // packed metrics, tagged for the next iteration
   uint32_t acc;               // decisions of the current group of 8 iterations
+  uint32_t vs;                // max result of the last even iteration (its tags)
   uint32_t* sv;               // survivor words of the lane group
   int r, n_it;
   bool store;
   uint64_t off0, off1;        // accumulated renormalisation amounts
 };
 
+// One iteration; returns the max result, whose low two bits per half are
+// the winners' tags (the decisions).
 template <int ND, int PH>
-__device__ __forceinline__ void iterate(Fwd<ND>& F, int row) {
+__device__ __forceinline__ uint32_t iterate(Fwd<ND>& F, int row) {
   uint32_t o[4];
   fetch4<PH>(F.V, o);
   const uint32_t c0 = o[0] + F.tp[PH][0][row * 16];
@@ -160,19 +159,35 @@ __device__ __forceinline__ void iterate(Fwd<ND>& F, int row) {
   const uint32_t c2 = o[2] + F.tp[PH][2][row * 16];
   const uint32_t c3 = o[3] + F.tp[PH][3][row * 16];
   const uint32_t v = pk_max(pk_max(c0, c1), pk_max(c2, c3));
-  F.acc = (F.acc << 2) | (v & kTags);
   F.V = (v & kStrip) | F.tag[(PH + 1) % ND];
+  return v;
 }
 
-template <int ND>
-__device__ __forceinline__ void iterate_dyn(Fwd<ND>& F, int row, int ph) {
-  if (ph == 0) {
-    iterate<ND, 0>(F, row);
-  } else if (ph == 1) {
-    iterate<ND, 1 % ND>(F, row);
+// Decisions of iteration K8 (static) of a group: bytes 0 and 2 of the even
+// and the odd iteration's max results in one permutation, then one mask.
+template <int ND, int K8>
+__device__ __forceinline__ void collect(Fwd<ND>& F, uint32_t v) {
+  if constexpr ((K8 & 1) == 0) {
+    F.vs = v;
   } else {
-    iterate<ND, 2 % ND>(F, row);
+    const uint32_t t = __builtin_amdgcn_perm(v, F.vs, 0x06040200u) & kTagBytes;
+    F.acc = K8 == 1 ? t : (F.acc | (t << (K8 - 1)));
   }
+}
+
+// The same for a runtime iteration index k (the last, partial block).
+template <int ND>
+__device__ __forceinline__ void iterate_dyn(Fwd<ND>& F, int row, int ph, int k) {
+  uint32_t v;
+  if (ph == 0) {
+    v = iterate<ND, 0>(F, row);
+  } else if (ph == 1) {
+    v = iterate<ND, 1 % ND>(F, row);
+  } else {
+    v = iterate<ND, 2 % ND>(F, row);
+  }
+  const uint32_t sel = (k & 1) ? 0x02000C0Cu : 0x0C0C0200u;  // 0x0C: a zero byte
+  F.acc |= (__builtin_amdgcn_perm(v, v, sel) & kTagBytes) << (2 * ((k & 7) >> 1));
 }
 
 // End of a group of iterations ending at iteration `last`.
@@ -180,7 +195,7 @@ template <int ND>
 __device__ __forceinline__ void group_end(Fwd<ND>& F, int last) {
   constexpr int NS = Fwd<ND>::NS;
   const int n = (last & 7) + 1;
-  if (F.store) F.sv[(last >> 3) * NS + F.r] = n == 8 ? F.acc : pk_shl(F.acc, 2 * (8 - n));
+  if (F.store) F.sv[(last >> 3) * NS + F.r] = F.acc;
   F.acc = 0;
   if (n == 8) {
     // bring state 0 (lane 0 of the group) back to kBase in both halves
@@ -205,7 +220,7 @@ __device__ __forceinline__ void group_end(Fwd<ND>& F, int last) {
 template <int ND, int P0, int Q>
 __device__ __forceinline__ void iterate_full(Fwd<ND>& F, int it0) {
   if constexpr (Q < 16) {
-    iterate<ND, (P0 + Q) % ND>(F, Q);
+    collect<ND, Q & 7>(F, iterate<ND, (P0 + Q) % ND>(F, Q));
     if constexpr ((Q & 7) == 7) group_end<ND>(F, it0 + Q);
     iterate_full<ND, P0, Q + 1>(F, it0);
   }
@@ -242,7 +257,7 @@ __device__ __forceinline__ void block(Fwd<ND>& F, int it0) {
   } else {
 #pragma unroll 1
     for (int q = 0; q < n; ++q) {
-      iterate_dyn<ND>(F, q, (P0 + q) % ND);
+      iterate_dyn<ND>(F, q, (P0 + q) % ND, q);
       if ((q & 7) == 7 || q == n - 1) group_end<ND>(F, it0 + q);
     }
   }
@@ -493,7 +508,7 @@ __device__ __forceinline__ void chase_all(Chase& c, bool go, bool pair_go, const
         const int pos = slot_pos(it % ND);
         const uint32_t goff = (uint32_t)(((it >> 3) & (64 / NS - 1)) << 11);
         const uint32_t word = *(const uint32_t*)((const char*)lds + base + goff + A);
-        const uint32_t tag = (word >> (16 * h + 2 * (7 - (it & 7)))) & 3u;
+        const uint32_t tag = (word >> (16 * (it & 1) + 8 * h + 2 * ((it & 7) >> 1))) & 3u;
         const uint32_t u = (A >> pos) & 3u;
         A = (A | (3u << pos)) - (tag << pos);
         if (go && c.emit) {
