@@ -14,8 +14,10 @@
 // its new top digit u in slot ph as well and leaves every other digit where
 // it was.  A dragonfly group is therefore the four lanes that differ only in
 // slot ph, and the right states stay in place: slot 0 (lane bits 0-1) is a
-// DPP quad broadcast, slot 1 (bits 2-3) a DPP row rotation by 4, 8, 12, and
-// slot 2 (bits 4-5) three v_permlane32/16_swap operations.
+// DPP quad broadcast, slot 1 (bits 2-3) a DPP row rotation by 4, 8, 12 (the
+// adds take these as DPP operands), and slot 2 (bits 4-5, the rows of 16
+// lanes) a 4 x 4 transpose of candidates that every lane forms for its four
+// successors: two v_permlane32_swap and two v_permlane16_swap.
 //
 // Packed metrics.  Path metrics are unsigned 16-bit numbers, frame A in the
 // low and frame B in the high half of a VGPR.  A metric is stored as
@@ -152,13 +154,30 @@ struct Fwd {
 // the winners' tags (the decisions).
 template <int ND, int PH>
 __device__ __forceinline__ uint32_t iterate(Fwd<ND>& F, int row) {
-  uint32_t o[4];
-  fetch4<PH>(F.V, o);
-  const uint32_t c0 = o[0] + F.tp[PH][0][row * 16];
-  const uint32_t c1 = o[1] + F.tp[PH][1][row * 16];
-  const uint32_t c2 = o[2] + F.tp[PH][2][row * 16];
-  const uint32_t c3 = o[3] + F.tp[PH][3][row * 16];
-  const uint32_t v = pk_max(pk_max(c0, c1), pk_max(c2, c3));
+  uint32_t v;
+  if constexpr (PH == 2) {
+    // slot 2 is the row of 16 lanes: each lane adds the branch metrics of
+    // its four successors (in the same lane of rows 0..3) to its own metric,
+    // and a 4 x 4 transpose across the rows (two 32-lane and two 16-lane
+    // swaps, no copies) hands every lane its four candidates
+    const uint32_t c0 = F.V + F.tp[2][0][row * 16];
+    const uint32_t c1 = F.V + F.tp[2][1][row * 16];
+    const uint32_t c2 = F.V + F.tp[2][2][row * 16];
+    const uint32_t c3 = F.V + F.tp[2][3][row * 16];
+    const auto s02 = __builtin_amdgcn_permlane32_swap(c0, c2, false, false);
+    const auto s13 = __builtin_amdgcn_permlane32_swap(c1, c3, false, false);
+    const auto s01 = __builtin_amdgcn_permlane16_swap(s02[0], s13[0], false, false);
+    const auto s23 = __builtin_amdgcn_permlane16_swap(s02[1], s13[1], false, false);
+    v = pk_max(pk_max(s01[0], s01[1]), pk_max(s23[0], s23[1]));
+  } else {
+    uint32_t o[4];
+    fetch4<PH>(F.V, o);
+    const uint32_t c0 = o[0] + F.tp[PH][0][row * 16];
+    const uint32_t c1 = o[1] + F.tp[PH][1][row * 16];
+    const uint32_t c2 = o[2] + F.tp[PH][2][row * 16];
+    const uint32_t c3 = o[3] + F.tp[PH][3][row * 16];
+    v = pk_max(pk_max(c0, c1), pk_max(c2, c3));
+  }
   F.V = (v & kStrip) | F.tag[(PH + 1) % ND];
   return v;
 }
@@ -278,7 +297,19 @@ __device__ __forceinline__ void super_block(Fwd<ND>& F, int it0) {
 template <int ND, int PH>
 __device__ __forceinline__ void lane_consts(Fwd<ND>& F, const DevCode& c, int lane, int r) {
   constexpr int KM1 = Fwd<ND>::KM1, NS = Fwd<ND>::NS;
-  if constexpr (PH < ND) {
+  if constexpr (PH == 2 && ND == 3) {
+    // source side: the branch from this lane's left state to the right
+    // state held by the same lane of row u after the iteration
+    const int i = rotr_n(r, (2 * PH) % KM1, KM1);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = rotr_n((r & 15) | (u << 4), (2 * (PH + 1)) % KM1, KM1);
+      const int un = j >> (KM1 - 2);  // = u: slot 2 holds the new digit
+      const int mid = ((un & 1) << (KM1 - 1)) | (i >> 1);
+      const int p = branch_out2(c, i, un & 1) | (branch_out2(c, mid, un >> 1) << 2);
+      F.tp[PH][u] = F.tbl + p;
+    }
+  } else if constexpr (PH < ND) {
     uint32_t src[4];
     fetch4<PH>((uint32_t)lane, src);
     const int j = rotr_n(r, (2 * (PH + 1)) % KM1, KM1);  // right state held after the iteration
@@ -290,6 +321,8 @@ __device__ __forceinline__ void lane_consts(Fwd<ND>& F, const DevCode& c, int la
       const int p = branch_out2(c, i, u & 1) | (branch_out2(c, mid, u >> 1) << 2);
       F.tp[PH][k] = F.tbl + p;
     }
+  }
+  if constexpr (PH < ND) {
     const int s = rotr_n(r, (2 * PH) % KM1, KM1);  // left state held entering the iteration
     F.tag[PH] = (uint32_t)(3 - (s & 3)) * 0x10001u;
     lane_consts<ND, PH + 1>(F, c, lane, r);
