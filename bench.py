@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--ebn0", type=float, default=3.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--ber", action="store_true", help="run the equal-BER sweep")
-    ap.add_argument("--variants", default="i8r4,f32r2,i8r2")
+    ap.add_argument("--variants", default="i8r4,f32r2,f16r2,i8r2")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one device copy of %d MiB (scale for HBM counters)" % (COPY_BYTES >> 20))
     return ap.parse_args()
@@ -140,7 +140,7 @@ def cpu_baseline(code, llr_i8_np):
             "single_thread_gbit_s": round(128 * N_INFO / dt1 / 1e9, 6)}
 
 
-def ber_sweep(torch, mv, code, frames_plan_i8, frames_plan_f32):
+def ber_sweep(torch, mv, code, frames_plan_i8, frames_plan_f32, frames_plan_f16=None):
     from workload import make_uniform_batch, int8_scale_for
     out = []
     for db in range(0, 7):
@@ -148,15 +148,20 @@ def ber_sweep(torch, mv, code, frames_plan_i8, frames_plan_f32):
         lf = torch.from_numpy(b.llr).to("cuda:0")
         li = mv.quantize_i8(lf, int8_scale_for(float(db), code.beta))
         row = {"ebn0_db": db, "bits": int(b.msg.size)}
-        for name, plan, llr in (("f32r2", frames_plan_f32, lf), ("i8r4", frames_plan_i8, li)):
+        runs = [("f32r2", frames_plan_f32, lf), ("i8r4", frames_plan_i8, li)]
+        if frames_plan_f16 is not None:
+            runs.append(("f16r2", frames_plan_f16, lf.half()))
+        for name, plan, llr in runs:
             bits, _, _ = plan.decode(llr)
             torch.cuda.synchronize()
             dec = mv.unpack_bits(bits.cpu().numpy()[: N_FRAMES * (N_INFO // 32)].reshape(N_FRAMES, -1), N_INFO)
             row[name + "_errors"] = int((dec != b.msg).sum())
             if name == "f32r2":
                 ref = dec
-            else:
+            elif name == "i8r4":
                 row["paired_differing_bits"] = int((dec != ref).sum())
+            else:
+                row[name + "_differing_bits"] = int((dec != ref).sum())
         out.append(row)
         del lf, li
     def at(target, key):
@@ -171,6 +176,11 @@ def ber_sweep(torch, mv, code, frames_plan_i8, frames_plan_f32):
         a, c = at(tgt, "f32r2_errors"), at(tgt, "i8r4_errors")
         res["ebn0_at_%g" % tgt] = {"f32r2": a, "i8r4": c,
                                    "gap_db": None if a is None or c is None else round(c - a, 4)}
+        if frames_plan_f16 is not None:
+            h = at(tgt, "f16r2_errors")
+            res["ebn0_at_%g" % tgt]["f16r2"] = h
+            res["ebn0_at_%g" % tgt]["f16_gap_db"] = (None if a is None or h is None
+                                                     else round(h - a, 4))
     return res
 
 
@@ -190,6 +200,7 @@ def main():
     b = make_uniform_batch(code, N_FRAMES, N_INFO, args.ebn0, seed=2000 + int(round(args.ebn0)))
     llr_f32 = torch.from_numpy(b.llr).to(dev)
     llr_i8 = mv.quantize_i8(llr_f32, int8_scale_for(args.ebn0, code.beta))
+    llr_f16 = llr_f32.half()
     torch.cuda.synchronize()
     frames = mv.uniform_frames(code, N_FRAMES, N_INFO, True)
     S = N_INFO + code.K - 1
@@ -206,9 +217,10 @@ def main():
     results = {}
     for v in args.variants.split(","):
         base, _, kv = v.partition(":")
-        dt, radix = ("i8", 4) if base == "i8r4" else ("f32", 2) if base == "f32r2" else ("i8", 2)
+        dt, radix = {"i8r4": ("i8", 4), "f32r2": ("f32", 2), "f16r2": ("f16", 2),
+                     "i8r2": ("i8", 2)}[base]
         plans[v] = mv.Plan([code], frames, dt, radix, variant=int(kv[1:]) if kv else 0)
-        llr = llr_i8 if dt == "i8" else llr_f32
+        llr = {"i8": llr_i8, "f32": llr_f32, "f16": llr_f16}[dt]
         ms, fwd, tb, bits, _ = time_variant(torch, mv, plans[v], llr, args.steps, args.warmup)
         dec = mv.unpack_bits(bits.cpu().numpy()[: N_FRAMES * (N_INFO // 32)].reshape(N_FRAMES, -1), N_INFO)
         peak = VALU16_PEAK_TOPS if base in PACKED16 and not kv else VALU32_PEAK_TOPS
@@ -251,7 +263,8 @@ def main():
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(code, llr_i8.cpu().numpy())
     if args.ber:
-        line["equal_ber"] = ber_sweep(torch, mv, code, plans.get("i8r4"), plans.get("f32r2"))
+        line["equal_ber"] = ber_sweep(torch, mv, code, plans.get("i8r4"), plans.get("f32r2"),
+                                      plans.get("f16r2"))
     print(json.dumps(line), flush=True)
 
 

@@ -52,7 +52,11 @@ typedef enum {
   MIVIT_EUNSUPPORTED = -4  /* valid request the library does not implement */
 } mivit_status;
 
-typedef enum { MIVIT_F32 = 0, MIVIT_I8 = 1 } mivit_dtype;
+/* Soft-value types.  float16 values are decoded in float32 arithmetic (each
+ * converts exactly), halving the soft-value bytes of a float32 batch (the
+ * paper's half-precision channel input with single-precision metrics,
+ * §IX-B); radix 2 and variant 0 only (other variants: MIVIT_EUNSUPPORTED). */
+typedef enum { MIVIT_F32 = 0, MIVIT_I8 = 1, MIVIT_F16 = 2 } mivit_dtype;
 
 /* A convolutional code (§II-A): 3 <= K <= 9, 2 <= beta <= 4, 0 < gen[b] < 2^K,
  * and every generator has bit K-1 and bit 0 set (the premise of the
@@ -141,10 +145,10 @@ mivit_status mivit_plan_create(mivit_plan** plan, const mivit_code* codes, int32
                                const mivit_opts* opts);
 
 /* Decode every frame of the plan (forward procedure, then traceback).
- *   llr        device, float32 or int8 per the plan's dtype, read-only
+ *   llr        device, float32, float16 or int8 per the plan's dtype, read-only
  *   bits       device uint32 words; frame f writes the words covering
  *              [bit_offset, bit_offset + n_out), zero-padding the last one
- *   metric     device, one per frame: float32 (float plans) or int64 (int8
+ *   metric     device, one per frame: float32 (float32 and float16 plans) or int64 (int8
  *              plans): the path metric of the decoded path, Eq. (PM) at the
  *              last stage.  For a chunked frame, that of its last window.
  *              May be NULL.

@@ -21,7 +21,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _capi
-from ._capi import FRAME_DTYPE, MIVIT_END_ZERO, MIVIT_F32, MIVIT_I8, MIVIT_START_KNOWN, MivitError
+from ._capi import (FRAME_DTYPE, MIVIT_END_ZERO, MIVIT_F16, MIVIT_F32, MIVIT_I8, MIVIT_START_KNOWN,
+                    MivitError)
 
 __all__ = ["Code", "Plan", "decode", "decode_stream", "quantize_i8", "ViterbiDecode",
            "unpack_bits", "FRAME_DTYPE", "MivitError", "version"]
@@ -89,7 +90,7 @@ class Plan:
         lib = _capi.load()
         self.codes = [_as_code(c) for c in codes]
         self.frames = np.ascontiguousarray(frames, dtype=FRAME_DTYPE)
-        self.dtype = {"f32": MIVIT_F32, "i8": MIVIT_I8}[dtype]
+        self.dtype = {"f32": MIVIT_F32, "i8": MIVIT_I8, "f16": MIVIT_F16}[dtype]
         arr = (_capi.Code * len(self.codes))(*[c.c_struct() for c in self.codes])
         opts = _capi.Opts()
         opts.dtype, opts.radix, opts.chunk, opts.overlap = self.dtype, int(radix), int(chunk), int(overlap)
@@ -130,7 +131,7 @@ class Plan:
     def empty_outputs(self, device):
         torch = _torch()
         bits = torch.zeros(max(self.n_bit_words, 1), dtype=torch.int32, device=device)
-        mdt = torch.float32 if self.dtype == MIVIT_F32 else torch.int64
+        mdt = torch.int64 if self.dtype == MIVIT_I8 else torch.float32
         metric = torch.zeros(max(self.n_frames, 1), dtype=mdt, device=device)
         end = torch.zeros(max(self.n_frames, 1), dtype=torch.int32, device=device)
         return bits, metric, end
@@ -138,7 +139,7 @@ class Plan:
     def decode(self, llr, bits=None, metric=None, end_state=None, stream=None):
         """Decode on the current stream; returns (bit words int32, metric, end state)."""
         torch = _torch()
-        want = torch.float32 if self.dtype == MIVIT_F32 else torch.int8
+        want = {MIVIT_F32: torch.float32, MIVIT_I8: torch.int8, MIVIT_F16: torch.float16}[self.dtype]
         if llr.dtype != want or not llr.is_cuda or not llr.is_contiguous():
             raise ValueError("llr must be a contiguous device tensor of dtype %s" % want)
         if bits is None:
@@ -208,15 +209,22 @@ def _cached_plan(key, make):
     return p
 
 
+def _dtype_name(torch, llr):
+    names = {torch.float32: "f32", torch.int8: "i8", torch.float16: "f16"}
+    if llr.dtype not in names:
+        raise ValueError("soft values must be float32, float16 or int8, not %s" % llr.dtype)
+    return names[llr.dtype]
+
+
 def decode(llr, code, n_info: int, terminated: bool = True, radix: int = 0, stream=None):
-    """Equal-length frames.  llr: device tensor [F, S*beta] float32 or int8.
+    """Equal-length frames.  llr: device tensor [F, S*beta] float32, float16 or int8.
 
     Returns (bit words int32 [F, ceil(N/32)], metric [F]).
     """
     torch = _torch()
     code = _as_code(code)
     F = llr.shape[0] if llr.dim() == 2 else 1
-    dt = "f32" if llr.dtype == torch.float32 else "i8"
+    dt = _dtype_name(torch, llr)
     key = ("u", code, F, n_info, terminated, dt, radix, llr.device.index)
     plan = _cached_plan(key, lambda: Plan([code], uniform_frames(code, F, n_info, terminated),
                                           dt, radix))
@@ -232,7 +240,7 @@ def decode_stream(llr, code, n_info: int, chunk: int = 2048, overlap: int = 64, 
     Returns bit words int32 [ceil(N/32)]."""
     torch = _torch()
     code = _as_code(code)
-    dt = "f32" if llr.dtype == torch.float32 else "i8"
+    dt = _dtype_name(torch, llr)
     fr = np.zeros(1, FRAME_DTYPE)
     fr[0] = (0, 0, n_info, 0, n_info, 0, MIVIT_START_KNOWN)
     key = ("s", code, n_info, chunk, overlap, dt, radix, llr.device.index)

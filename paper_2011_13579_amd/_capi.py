@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmivit.so")
 
 MIVIT_OK, MIVIT_EINVAL, MIVIT_ENOMEM, MIVIT_EHIP, MIVIT_EUNSUPPORTED = 0, -1, -2, -3, -4
-MIVIT_F32, MIVIT_I8 = 0, 1
+MIVIT_F32, MIVIT_I8, MIVIT_F16 = 0, 1, 2
 MIVIT_START_KNOWN, MIVIT_END_ZERO = 1, 2
 
 # every symbol include/mivit.h declares

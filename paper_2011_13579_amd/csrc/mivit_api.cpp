@@ -16,14 +16,14 @@
 #include "mivit_device.h"
 
 namespace mivit {
-hipError_t launch_fwd(int radix, int nsl, bool is_int, const DevCode* codes, const Item* items,
+hipError_t launch_fwd(int radix, int nsl, int dt, const DevCode* codes, const Item* items,
                       int n_items, const void* llr, uint64_t* surv, void* metric,
                       int32_t* end_out, int32_t* item_end, hipStream_t st);
 hipError_t launch_grad(const DevCode* codes, const GradFrame* frames, int n_frames,
                        int max_stages, const uint32_t* bits, const float* gm, float* grad,
                        hipStream_t st);
 hipError_t launch_quant(const float* x, int8_t* q, int64_t n, float scale, hipStream_t st);
-hipError_t launch_fwd_rot(int K, int beta, bool is_int, int mode, const DevCode* codes,
+hipError_t launch_fwd_rot(int K, int beta, int dt, int mode, const DevCode* codes,
                           const Item* items, const int2* waves, int n_waves, const void* llr,
                           uint64_t* surv, void* metric, int32_t* end_out, int32_t* item_end,
                           int32_t* counter, int grid_limit, hipStream_t st);
@@ -38,7 +38,7 @@ hipError_t launch_tb_r4p(int K, const Item* items, const int2* pairs, int n_pair
                          const uint64_t* surv, const int32_t* item_end, uint32_t* bits, int warm,
                          hipStream_t st);
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st);
-hipError_t launch_fill_random(void* p, int64_t n, bool is_int, uint32_t seed, hipStream_t st);
+hipError_t launch_fill_random(void* p, int64_t n, int dt, uint32_t seed, hipStream_t st);
 }  // namespace mivit
 
 using namespace mivit;
@@ -54,9 +54,10 @@ constexpr int kWarmStages = 64;  // speculative traceback warm-up
 // (4096 x 8192 K=7 frames at 3 dB: 64 stages 0.095 ms, 80 0.085, 96 0.073,
 // 112 0.073, 128 0.076).  The radix-2 tracebacks measured best at 64.
 constexpr int kWarmStagesR4P = 96;
-// rotating forward kernel exchange scheme per plan variant:
-// 0 all exchanges in the VALU (DPP, permlane swaps), 1 both previous-state
-// metrics via DPP/LDS swizzles, 2 one partner metric via DPP/LDS swizzles
+// rotating forward kernel: its MODE template argument per plan variant.
+// Variant 0 (MODE 2): all exchanges in the VALU (DPP, permlane swaps);
+// variant 1 (MODE 0): both previous-state metrics via DPP/LDS swizzles;
+// variant 2 (MODE 1): one partner metric via DPP/LDS swizzles.
 constexpr int kRotMode[3] = {2, 0, 1};
 constexpr int kMaxAux = 4;     // plan-owned streams for concurrent parts
 constexpr int kMaxGraphs = 8;  // recorded decode graphs kept per plan
@@ -346,7 +347,7 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
 
 hipError_t part_forward(const mivit_plan* p, const Part& q, const void* llr, void* metric,
                         int32_t* end_state, hipStream_t st) {
-  const bool is_int = p->dtype == MIVIT_I8;
+  const int dt = p->dtype;  // the kernels number the soft-value types as mivit_dtype does
   for (const PlanGroup& g : q.groups) {
     hipError_t e;
     int32_t* counter = g.counter >= 0 ? q.d_counters + g.counter : nullptr;
@@ -359,11 +360,11 @@ hipError_t part_forward(const mivit_plan* p, const Part& q, const void* llr, voi
                          (const int8_t*)llr, q.d_surv, (int64_t*)metric, end_state,
                          q.d_item_end, counter, 0, st);
     else if (g.kern == kKernRot2)
-      e = launch_fwd_rot(g.K, g.beta, is_int, kRotMode[q.ch.variant], p->d_codes, q.d_items,
+      e = launch_fwd_rot(g.K, g.beta, dt, kRotMode[q.ch.variant], p->d_codes, q.d_items,
                          q.d_waves + g.wave_off, g.n_waves, llr, q.d_surv, metric, end_state,
                          q.d_item_end, counter, 0, st);
     else
-      e = launch_fwd(g.kern == kKernGeneric4 ? 4 : 2, g.nsl, is_int, p->d_codes,
+      e = launch_fwd(g.kern == kKernGeneric4 ? 4 : 2, g.nsl, dt, p->d_codes,
                      q.d_items + g.first, g.count, llr, q.d_surv, metric, end_state,
                      q.d_item_end, st);
     if (e != hipSuccess) return e;
@@ -421,6 +422,11 @@ std::vector<Choice> candidates(const mivit_code& c, int dtype, int radix) {
     out.push_back(ch);
   };
   const bool i8 = dtype == MIVIT_I8;
+  if (dtype == MIVIT_F16) {  // the default exchange scheme only
+    add(2, 0, false);
+    if (c.K <= 7) add(2, 0, true);
+    return out;
+  }
   if (radix != 4) {
     if (c.K <= 7) {
       for (int v = 0; v < 3; ++v) add(2, v, false);
@@ -497,7 +503,7 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
   mivit_opts o;
   std::memset(&o, 0, sizeof o);
   if (opts) o = *opts;
-  if (o.dtype != MIVIT_F32 && o.dtype != MIVIT_I8) return MIVIT_EINVAL;
+  if (o.dtype != MIVIT_F32 && o.dtype != MIVIT_I8 && o.dtype != MIVIT_F16) return MIVIT_EINVAL;
   if (o.radix != 0 && o.radix != 2 && o.radix != 4) return MIVIT_EINVAL;
   if (o.radix == 4 && o.dtype != MIVIT_I8) return MIVIT_EINVAL;
   if (o.chunk < 0 || o.overlap < 0 || (o.chunk > 0 && o.chunk % 32 != 0)) return MIVIT_EINVAL;
@@ -509,6 +515,7 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
     mivit_status s = check_code(codes[c]);
     if (s != MIVIT_OK) return s;
   }
+  if (o.dtype == MIVIT_F16 && o.variant != 0) return MIVIT_EUNSUPPORTED;
   // frames: ranges and non-overlapping outputs
   std::vector<std::pair<int64_t, int64_t>> words;
   words.reserve(n_frames);
@@ -567,13 +574,13 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
     const bool tune = (o.flags & MIVIT_PLAN_AUTOTUNE) != 0;
     if (tune) {
       // synthetic soft values covering every frame, and scratch outputs
-      const size_t esz = o.dtype == MIVIT_I8 ? 1 : 4;
+      const size_t esz = o.dtype == MIVIT_I8 ? 1 : o.dtype == MIVIT_F16 ? 2 : 4;
       e = hipMalloc(&t_llr, (size_t)std::max<int64_t>(llr_end, 1) * esz);
       if (e == hipSuccess) e = hipMalloc(&t_bits, (size_t)std::max<int64_t>(word_end, 1) * 4);
       if (e == hipSuccess) e = hipMalloc(&t_metric, (size_t)std::max(n_frames, 1) * 8);
       if (e == hipSuccess) e = hipMalloc(&t_end, (size_t)std::max(n_frames, 1) * 4);
       if (e == hipSuccess)
-        e = launch_fill_random(t_llr, llr_end, o.dtype == MIVIT_I8, 0x5eed1234u, p->origin);
+        e = launch_fill_random(t_llr, llr_end, o.dtype, 0x5eed1234u, p->origin);
       if (e != hipSuccess) throw hip_status(e);
     }
     for (int c : order) {

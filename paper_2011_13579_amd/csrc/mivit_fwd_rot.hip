@@ -46,10 +46,14 @@ __device__ __forceinline__ int rotl(int x, int r, int n) {
 }
 __device__ __forceinline__ int rotr(int x, int r, int n) { return rotl(x, (n - r) % n, n); }
 
-template <bool INT>
+// Soft-value type DT (0: float32, 1: int8, 2: float16) and the metric
+// arithmetic it runs in: float32 for both float types (a float16 value
+// converts to float32 exactly), exact int32 with renormalisation for int8.
+template <int DT>
 struct Ty;
 template <>
-struct Ty<false> {
+struct Ty<0> {
+  static constexpr bool kInt = false;
   using T = float;
   using In = float;
   __device__ static float neg_unreachable() { return -__builtin_inff(); }
@@ -57,19 +61,24 @@ struct Ty<false> {
   __device__ static float from(int x) { return __builtin_bit_cast(float, x); }
 };
 template <>
-struct Ty<true> {
+struct Ty<1> {
+  static constexpr bool kInt = true;
   using T = int;
   using In = int8_t;
   __device__ static int neg_unreachable() { return -(1 << 29); }
   __device__ static int bits(int x) { return x; }
   __device__ static int from(int x) { return x; }
 };
+template <>
+struct Ty<2> : Ty<0> {
+  using In = _Float16;
+};
 
 // Fetch the metrics of the even and odd previous states for lane bit Q.
-template <int Q, bool INT>
-__device__ __forceinline__ void pair_fetch(typename Ty<INT>::T x, int addr_e, int addr_o,
-                                           typename Ty<INT>::T& e, typename Ty<INT>::T& o) {
-  const int xi = Ty<INT>::bits(x);
+template <int Q, int DT>
+__device__ __forceinline__ void pair_fetch(typename Ty<DT>::T x, int addr_e, int addr_o,
+                                           typename Ty<DT>::T& e, typename Ty<DT>::T& o) {
+  const int xi = Ty<DT>::bits(x);
   int ei, oi;
   if constexpr (Q == 0) {
     ei = __builtin_amdgcn_mov_dpp(xi, 0xA0, 0xF, 0xF, true);  // quad_perm [0,0,2,2]
@@ -85,15 +94,15 @@ __device__ __forceinline__ void pair_fetch(typename Ty<INT>::T x, int addr_e, in
     ei = __builtin_amdgcn_ds_bpermute(addr_e, xi);
     oi = __builtin_amdgcn_ds_bpermute(addr_o, xi);
   }
-  e = Ty<INT>::from(ei);
-  o = Ty<INT>::from(oi);
+  e = Ty<DT>::from(ei);
+  o = Ty<DT>::from(oi);
 }
 
 // Fetch the metric of the partner lane (lane XOR 2^Q).  XOR 1, 2 and 8 are
 // single DPP patterns (fused by the compiler into the consuming subtract).
-template <int Q, bool INT>
-__device__ __forceinline__ typename Ty<INT>::T partner_fetch(typename Ty<INT>::T x, int addr_p) {
-  const int xi = Ty<INT>::bits(x);
+template <int Q, int DT>
+__device__ __forceinline__ typename Ty<DT>::T partner_fetch(typename Ty<DT>::T x, int addr_p) {
+  const int xi = Ty<DT>::bits(x);
   int pi;
   if constexpr (Q == 0) {
     pi = __builtin_amdgcn_mov_dpp(xi, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
@@ -106,12 +115,12 @@ __device__ __forceinline__ typename Ty<INT>::T partner_fetch(typename Ty<INT>::T
   } else {
     pi = __builtin_amdgcn_ds_bpermute(addr_p, xi);
   }
-  return Ty<INT>::from(pi);
+  return Ty<DT>::from(pi);
 }
 
-template <int KM1, bool INT, int NP, int MODE>
+template <int KM1, int DT, int NP, int MODE>
 struct Frame {
-  using T = typename Ty<INT>::T;
+  using T = typename Ty<DT>::T;
   T pm;
   uint32_t acc;
   int pat_off[KM1];  // LDS word offset of this lane's pattern, per phase
@@ -142,10 +151,10 @@ struct Mode2 {
   static constexpr bool fixed_roles = (Q == 0 || Q == 1 || Q == 4 || Q == 5);
 };
 
-template <int Q, bool INT>
-__device__ __forceinline__ void pair_fetch_valu(typename Ty<INT>::T x, typename Ty<INT>::T& e,
-                                                typename Ty<INT>::T& o) {
-  const int xi = Ty<INT>::bits(x);
+template <int Q, int DT>
+__device__ __forceinline__ void pair_fetch_valu(typename Ty<DT>::T x, typename Ty<DT>::T& e,
+                                                typename Ty<DT>::T& o) {
+  const int xi = Ty<DT>::bits(x);
   int ei, oi;
   if constexpr (Q == 0) {
     ei = __builtin_amdgcn_mov_dpp(xi, 0xA0, 0xF, 0xF, true);
@@ -162,13 +171,13 @@ __device__ __forceinline__ void pair_fetch_valu(typename Ty<INT>::T x, typename 
     ei = r[0];
     oi = r[1];
   }
-  e = Ty<INT>::from(ei);
-  o = Ty<INT>::from(oi);
+  e = Ty<DT>::from(ei);
+  o = Ty<DT>::from(oi);
 }
 
-template <int Q, bool INT>
-__device__ __forceinline__ typename Ty<INT>::T partner_fetch_valu(typename Ty<INT>::T x) {
-  const int xi = Ty<INT>::bits(x);
+template <int Q, int DT>
+__device__ __forceinline__ typename Ty<DT>::T partner_fetch_valu(typename Ty<DT>::T x) {
+  const int xi = Ty<DT>::bits(x);
   int pi;
   if constexpr (Q == 2) {
     const int hm = __builtin_amdgcn_mov_dpp(xi, 0x141, 0xF, 0xF, true);  // row_half_mirror: ^7
@@ -176,7 +185,7 @@ __device__ __forceinline__ typename Ty<INT>::T partner_fetch_valu(typename Ty<IN
   } else {
     pi = __builtin_amdgcn_mov_dpp(xi, 0x128, 0xF, 0xF, true);  // row_ror:8
   }
-  return Ty<INT>::from(pi);
+  return Ty<DT>::from(pi);
 }
 
 template <typename T>
@@ -193,10 +202,10 @@ __device__ __forceinline__ T tmax(T a, T b) {
 // previous state won" is partner > own where the lane's bit Q is 0 (partner
 // odd) and own > partner where it is 1 (own odd), strict either way, so a tie
 // keeps the even state.
-template <int KM1, bool INT, int NP, int MODE, int Q>
-__device__ __forceinline__ void stage_op(Frame<KM1, INT, NP, MODE>& F, typename Ty<INT>::T m0) {
-  using T = typename Ty<INT>::T;
-  const T cp = partner_fetch<Q, INT>(F.pm, F.addr_p) - m0;
+template <int KM1, int DT, int NP, int MODE, int Q>
+__device__ __forceinline__ void stage_op(Frame<KM1, DT, NP, MODE>& F, typename Ty<DT>::T m0) {
+  using T = typename Ty<DT>::T;
+  const T cp = partner_fetch<Q, DT>(F.pm, F.addr_p) - m0;
   const T co = F.pm + m0;
   F.pm = tmax(co, cp);
   const uint64_t g1 = __builtin_amdgcn_ballot_w64(cp > co);
@@ -206,11 +215,11 @@ __device__ __forceinline__ void stage_op(Frame<KM1, INT, NP, MODE>& F, typename 
 }
 
 // One stage at phase Q: add, compare, select, record.
-template <int KM1, bool INT, int NP, int MODE, int Q>
-__device__ __forceinline__ void stage(Frame<KM1, INT, NP, MODE>& F, typename Ty<INT>::T bm) {
-  using T = typename Ty<INT>::T;
+template <int KM1, int DT, int NP, int MODE, int Q>
+__device__ __forceinline__ void stage(Frame<KM1, DT, NP, MODE>& F, typename Ty<DT>::T bm) {
+  using T = typename Ty<DT>::T;
   T e, o;
-  pair_fetch<Q, INT>(F.pm, F.addr_e, F.addr_o, e, o);
+  pair_fetch<Q, DT>(F.pm, F.addr_e, F.addr_o, e, o);
   const T ce = e + bm;  // even previous state, Eq. (PM) candidate
   const T co = o - bm;  // odd previous state: opposite branch metric
   const bool d = co > ce;
@@ -219,19 +228,19 @@ __device__ __forceinline__ void stage(Frame<KM1, INT, NP, MODE>& F, typename Ty<
 }
 
 // Mode 2 stage: fixed roles (both metrics fetched) or own/partner.
-template <int KM1, bool INT, int NP, int MODE, int Q>
-__device__ __forceinline__ void stage_m2(Frame<KM1, INT, NP, MODE>& F, typename Ty<INT>::T bm) {
-  using T = typename Ty<INT>::T;
+template <int KM1, int DT, int NP, int MODE, int Q>
+__device__ __forceinline__ void stage_m2(Frame<KM1, DT, NP, MODE>& F, typename Ty<DT>::T bm) {
+  using T = typename Ty<DT>::T;
   if constexpr (Mode2<Q>::fixed_roles) {
     T e, o;
-    pair_fetch_valu<Q, INT>(F.pm, e, o);
+    pair_fetch_valu<Q, DT>(F.pm, e, o);
     const T ce = e + bm;
     const T co = o - bm;
     const bool d = co > ce;
     F.pm = d ? co : ce;
     F.acc = push_decision(F.acc, __builtin_amdgcn_ballot_w64(d));
   } else {
-    const T cp = partner_fetch_valu<Q, INT>(F.pm) - bm;
+    const T cp = partner_fetch_valu<Q, DT>(F.pm) - bm;
     const T co = F.pm + bm;
     F.pm = tmax(co, cp);
     const uint64_t g1 = __builtin_amdgcn_ballot_w64(cp > co);
@@ -241,51 +250,51 @@ __device__ __forceinline__ void stage_m2(Frame<KM1, INT, NP, MODE>& F, typename 
   }
 }
 
-template <int KM1, bool INT, int NP, int MODE, int Q>
-__device__ __forceinline__ void stage_any(Frame<KM1, INT, NP, MODE>& F, typename Ty<INT>::T bm) {
+template <int KM1, int DT, int NP, int MODE, int Q>
+__device__ __forceinline__ void stage_any(Frame<KM1, DT, NP, MODE>& F, typename Ty<DT>::T bm) {
   if constexpr (MODE == 2)
-    stage_m2<KM1, INT, NP, MODE, Q>(F, bm);
+    stage_m2<KM1, DT, NP, MODE, Q>(F, bm);
   else if constexpr (MODE == 1)
-    stage_op<KM1, INT, NP, MODE, Q>(F, bm);
+    stage_op<KM1, DT, NP, MODE, Q>(F, bm);
   else
-    stage<KM1, INT, NP, MODE, Q>(F, bm);
+    stage<KM1, DT, NP, MODE, Q>(F, bm);
 }
 
-template <int KM1, bool INT, int NP, int MODE, int P0, int K0>
-__device__ __forceinline__ void stages_full(Frame<KM1, INT, NP, MODE>& F,
-                                            const typename Ty<INT>::T* bmv) {
+template <int KM1, int DT, int NP, int MODE, int P0, int K0>
+__device__ __forceinline__ void stages_full(Frame<KM1, DT, NP, MODE>& F,
+                                            const typename Ty<DT>::T* bmv) {
   if constexpr (K0 < 32) {
-    stage_any<KM1, INT, NP, MODE, (P0 + K0) % KM1>(F, bmv[K0]);
-    stages_full<KM1, INT, NP, MODE, P0, K0 + 1>(F, bmv);
+    stage_any<KM1, DT, NP, MODE, (P0 + K0) % KM1>(F, bmv[K0]);
+    stages_full<KM1, DT, NP, MODE, P0, K0 + 1>(F, bmv);
   }
 }
 
 // A stage whose phase is only known at run time (the last, partial block).
-template <int KM1, bool INT, int NP, int MODE, int Q>
-__device__ __forceinline__ void stage_dyn(Frame<KM1, INT, NP, MODE>& F, const typename Ty<INT>::T* bmrow,
+template <int KM1, int DT, int NP, int MODE, int Q>
+__device__ __forceinline__ void stage_dyn(Frame<KM1, DT, NP, MODE>& F, const typename Ty<DT>::T* bmrow,
                                           int q) {
   if constexpr (Q < KM1) {
     if (q == Q) {
-      stage_any<KM1, INT, NP, MODE, Q>(F, bmrow[F.pat_off[Q]]);
+      stage_any<KM1, DT, NP, MODE, Q>(F, bmrow[F.pat_off[Q]]);
     } else {
-      stage_dyn<KM1, INT, NP, MODE, Q + 1>(F, bmrow, q);
+      stage_dyn<KM1, DT, NP, MODE, Q + 1>(F, bmrow, q);
     }
   }
 }
 
-template <int KM1, bool INT, int NP, int MODE, int P0>
-__device__ __forceinline__ void block(Frame<KM1, INT, NP, MODE>& F, const typename Ty<INT>::T* bmt,
+template <int KM1, int DT, int NP, int MODE, int P0>
+__device__ __forceinline__ void block(Frame<KM1, DT, NP, MODE>& F, const typename Ty<DT>::T* bmt,
                                       int n) {
-  using T = typename Ty<INT>::T;
+  using T = typename Ty<DT>::T;
   if (n == 32) {
     // this lane's branch metric of every stage of the block, read up front
     T bmv[32];
 #pragma unroll
     for (int k = 0; k < 32; ++k) bmv[k] = bmt[k * NP + F.pat_off[(P0 + k) % KM1]];
-    stages_full<KM1, INT, NP, MODE, P0, 0>(F, bmv);
+    stages_full<KM1, DT, NP, MODE, P0, 0>(F, bmv);
   } else {
 #pragma unroll 1
-    for (int k = 0; k < n; ++k) stage_dyn<KM1, INT, NP, MODE, 0>(F, bmt + k * NP, (P0 + k) % KM1);
+    for (int k = 0; k < n; ++k) stage_dyn<KM1, DT, NP, MODE, 0>(F, bmt + k * NP, (P0 + k) % KM1);
   }
 }
 
@@ -301,12 +310,12 @@ __device__ __forceinline__ void wave_sync() {
 
 // Soft values of the stages a lane tabulates in one block: stages
 // sl + k*2^(K-1) for k < max(1, 32/2^(K-1)).
-template <int KM1, bool INT, int BETA>
+template <int KM1, int DT, int BETA>
 struct LlrRegs {
   static constexpr int NS = 1 << KM1;
   static constexpr int NSTG = NS >= 32 ? 1 : 32 / NS;
-  typename Ty<INT>::T v[NSTG][BETA];
-  __device__ __forceinline__ void load(const typename Ty<INT>::In* llr, int tb, int S, int sl,
+  typename Ty<DT>::T v[NSTG][BETA];
+  __device__ __forceinline__ void load(const typename Ty<DT>::In* llr, int tb, int S, int sl,
                                        bool valid) {
 #pragma unroll
     for (int k = 0; k < NSTG; ++k) {
@@ -314,31 +323,31 @@ struct LlrRegs {
       const bool ok = valid && sl + k * NS < 32 && t < S;
 #pragma unroll
       for (int b = 0; b < BETA; ++b)
-        v[k][b] = ok ? (typename Ty<INT>::T)llr[(int64_t)t * BETA + b] : (typename Ty<INT>::T)0;
+        v[k][b] = ok ? (typename Ty<DT>::T)llr[(int64_t)t * BETA + b] : (typename Ty<DT>::T)0;
     }
   }
 };
 
 // State shared by the blocks of one wavefront.
-template <int KM1, bool INT, int BETA, int MODE>
+template <int KM1, int DT, int BETA, int MODE>
 struct BlockCtx {
-  Frame<KM1, INT, (1 << BETA), MODE>* F;
-  typename Ty<INT>::T* bmt;
-  const typename Ty<INT>::In* llr;
+  Frame<KM1, DT, (1 << BETA), MODE>* F;
+  typename Ty<DT>::T* bmt;
+  const typename Ty<DT>::In* llr;
   uint32_t* sv;
   int64_t* offset;
   int* blk;
   int S, sl, lane;
   bool valid;
-  LlrRegs<KM1, INT, BETA> lr;  // soft values of the current block, loaded a block ahead
+  LlrRegs<KM1, DT, BETA> lr;  // soft values of the current block, loaded a block ahead
 };
 
 // One block of up to 32 stages starting at tb, phase (32*BI) mod (K-1).
-template <int KM1, bool INT, int BETA, int MODE, int BI>
-__device__ __forceinline__ void one_block(BlockCtx<KM1, INT, BETA, MODE>& bc, int tb) {
-  using T = typename Ty<INT>::T;
+template <int KM1, int DT, int BETA, int MODE, int BI>
+__device__ __forceinline__ void one_block(BlockCtx<KM1, DT, BETA, MODE>& bc, int tb) {
+  using T = typename Ty<DT>::T;
   constexpr int NS = 1 << KM1, NP = 1 << BETA;
-  constexpr int NSTG = LlrRegs<KM1, INT, BETA>::NSTG;
+  constexpr int NSTG = LlrRegs<KM1, DT, BETA>::NSTG;
   const int n = min(32, bc.S - tb);
   // branch-metric table of this block: Eq. (BM) for every output pattern
 #pragma unroll
@@ -357,7 +366,7 @@ __device__ __forceinline__ void one_block(BlockCtx<KM1, INT, BETA, MODE>& bc, in
   }
   // the next block's soft values are read while this block runs
   bc.lr.load(bc.llr, tb + 32, bc.S, bc.sl, bc.valid);
-  if constexpr (INT) {
+  if constexpr (Ty<DT>::kInt) {
     if (tb > 0) {
       // renormalise by the metric of state 0 (always in the frame's lane 0)
       const T ref = __builtin_amdgcn_ds_bpermute((bc.lane & ~(NS - 1)) << 2, bc.F->pm);
@@ -366,20 +375,20 @@ __device__ __forceinline__ void one_block(BlockCtx<KM1, INT, BETA, MODE>& bc, in
     }
   }
   wave_sync();
-  block<KM1, INT, NP, MODE, (32 * BI) % KM1>(*bc.F, bc.bmt, n);
+  block<KM1, DT, NP, MODE, (32 * BI) % KM1>(*bc.F, bc.bmt, n);
   if (bc.valid) bc.sv[(int64_t)(*bc.blk) * NS + bc.sl] = bc.F->acc << (32 - n);
   bc.F->acc = 0;
   ++*bc.blk;
   wave_sync();
 }
 
-template <int KM1, bool INT, int BETA, int MODE, int BI, int NB>
-__device__ __forceinline__ void super_block(BlockCtx<KM1, INT, BETA, MODE>& bc, int t0) {
+template <int KM1, int DT, int BETA, int MODE, int BI, int NB>
+__device__ __forceinline__ void super_block(BlockCtx<KM1, DT, BETA, MODE>& bc, int t0) {
   if constexpr (BI < NB) {
     const int tb = t0 + 32 * BI;
     if (tb < bc.S) {
-      one_block<KM1, INT, BETA, MODE, BI>(bc, tb);
-      super_block<KM1, INT, BETA, MODE, BI + 1, NB>(bc, t0);
+      one_block<KM1, DT, BETA, MODE, BI>(bc, tb);
+      super_block<KM1, DT, BETA, MODE, BI + 1, NB>(bc, t0);
     }
   }
 }
@@ -393,18 +402,18 @@ constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
 constexpr int kRotWaves = 4;
 
 // The frames of wave-table entry 'wave', on one wavefront.
-template <int KM1, bool INT, int BETA, int MODE>
+template <int KM1, int DT, int BETA, int MODE>
 __device__ __forceinline__ void fwd_rot_wave(const DevCode* __restrict__ codes,
                                              const Item* __restrict__ items,
                                              const int2* __restrict__ waves, int wave,
                                              const void* __restrict__ llr_v,
                                              uint64_t* __restrict__ surv, void* metric,
                                              int32_t* end_out, int32_t* item_end,
-                                             typename rot::Ty<INT>::T (*bmt)[32 << BETA],
-                                             typename rot::Ty<INT>::T* xpm, int lane) {
+                                             typename rot::Ty<DT>::T (*bmt)[32 << BETA],
+                                             typename rot::Ty<DT>::T* xpm, int lane) {
   using namespace rot;
-  using T = typename Ty<INT>::T;
-  using In = typename Ty<INT>::In;
+  using T = typename Ty<DT>::T;
+  using In = typename Ty<DT>::In;
   constexpr int NS = 1 << KM1;
   constexpr int NP = 1 << BETA;
   constexpr int SUPER = 32 * KM1 / gcd_c(32, KM1);  // lcm(32, K-1)
@@ -418,7 +427,7 @@ __device__ __forceinline__ void fwd_rot_wave(const DevCode* __restrict__ codes,
   const In* llr = (const In*)llr_v + it.llr_off;
   uint32_t* sv = (uint32_t*)(surv + it.surv_off);
 
-  Frame<KM1, INT, NP, MODE> F;
+  Frame<KM1, DT, NP, MODE> F;
 #pragma unroll
   for (int q = 0; q < KM1; ++q) {
     const int j = rotr(sl, (q + 1) % KM1, KM1);  // state held after a phase-q stage
@@ -436,15 +445,15 @@ __device__ __forceinline__ void fwd_rot_wave(const DevCode* __restrict__ codes,
   F.addr_e = (lane & ~32) << 2;
   F.addr_o = (lane | 32) << 2;
   F.addr_p = (lane ^ 32) << 2;
-  F.pm = (it.start_known && sl != 0) ? Ty<INT>::neg_unreachable() : (T)0;
+  F.pm = (it.start_known && sl != 0) ? Ty<DT>::neg_unreachable() : (T)0;
   F.acc = 0;
   int64_t offset = 0;
   T* my_bmt = &bmt[fr][0];
 
   int blk = 0;
-  BlockCtx<KM1, INT, BETA, MODE> bc{&F, my_bmt, llr, sv, &offset, &blk, S, sl, lane, valid, {}};
+  BlockCtx<KM1, DT, BETA, MODE> bc{&F, my_bmt, llr, sv, &offset, &blk, S, sl, lane, valid, {}};
   bc.lr.load(llr, 0, S, sl, valid);
-  for (int t0 = 0; t0 < S; t0 += SUPER) super_block<KM1, INT, BETA, MODE, 0, SUPER / 32>(bc, t0);
+  for (int t0 = 0; t0 < S; t0 += SUPER) super_block<KM1, DT, BETA, MODE, 0, SUPER / 32>(bc, t0);
   // final metrics: lane sl holds state rotr(sl, S mod (K-1))
   const int st = rotr(sl, S % KM1, KM1);
   xpm[fr * NS + st] = F.pm;
@@ -460,7 +469,7 @@ __device__ __forceinline__ void fwd_rot_wave(const DevCode* __restrict__ codes,
     if (it.frame >= 0) {
       if (end_out) end_out[it.frame] = js;
       if (metric) {
-        if constexpr (INT)
+        if constexpr (Ty<DT>::kInt)
           ((int64_t*)metric)[it.frame] = (int64_t)xpm[fr * NS + js] + offset;
         else
           ((float*)metric)[it.frame] = xpm[fr * NS + js];
@@ -472,7 +481,7 @@ __device__ __forceinline__ void fwd_rot_wave(const DevCode* __restrict__ codes,
 // One wavefront per wave-table entry, or (counter != nullptr) a persistent
 // grid whose wavefronts take entries in table order (longest frames first)
 // from a device counter that starts at zero, until the table is exhausted.
-template <int KM1, bool INT, int BETA, int MODE>
+template <int KM1, int DT, int BETA, int MODE>
 __global__ __launch_bounds__(64 * kRotWaves) void k_fwd_rot(const DevCode* __restrict__ codes,
                                                 const Item* __restrict__ items,
                                                 const int2* __restrict__ waves, int n_waves,
@@ -480,7 +489,7 @@ __global__ __launch_bounds__(64 * kRotWaves) void k_fwd_rot(const DevCode* __res
                                                 uint64_t* __restrict__ surv, void* metric,
                                                 int32_t* end_out, int32_t* item_end,
                                                 int32_t* counter) {
-  using T = typename rot::Ty<INT>::T;
+  using T = typename rot::Ty<DT>::T;
   constexpr int FPW = 64 >> KM1;
   __shared__ T bmt_all[kRotWaves][FPW][32 << BETA];
   __shared__ T xpm_all[kRotWaves][64];
@@ -489,7 +498,7 @@ __global__ __launch_bounds__(64 * kRotWaves) void k_fwd_rot(const DevCode* __res
   if (counter == nullptr) {
     const int wave = blockIdx.x * kRotWaves + wid;
     if (wave >= n_waves) return;  // no workgroup barriers: safe to leave
-    fwd_rot_wave<KM1, INT, BETA, MODE>(codes, items, waves, wave, llr_v, surv, metric, end_out,
+    fwd_rot_wave<KM1, DT, BETA, MODE>(codes, items, waves, wave, llr_v, surv, metric, end_out,
                                        item_end, bmt_all[wid], xpm_all[wid], lane);
     return;
   }
@@ -498,12 +507,12 @@ __global__ __launch_bounds__(64 * kRotWaves) void k_fwd_rot(const DevCode* __res
     if (lane == 0) w = atomicAdd(counter, 1);
     w = __builtin_amdgcn_readfirstlane(w);
     if (w >= n_waves) break;
-    fwd_rot_wave<KM1, INT, BETA, MODE>(codes, items, waves, w, llr_v, surv, metric, end_out,
+    fwd_rot_wave<KM1, DT, BETA, MODE>(codes, items, waves, w, llr_v, surv, metric, end_out,
                                        item_end, bmt_all[wid], xpm_all[wid], lane);
   }
 }
 
-hipError_t launch_fwd_rot(int K, int beta, bool is_int, int mode, const DevCode* codes,
+hipError_t launch_fwd_rot(int K, int beta, int dt, int mode, const DevCode* codes,
                           const Item* items, const int2* waves, int n_waves, const void* llr,
                           uint64_t* surv, void* metric, int32_t* end_out, int32_t* item_end,
                           int32_t* counter, int grid_limit, hipStream_t st) {
@@ -519,10 +528,13 @@ hipError_t launch_fwd_rot(int K, int beta, bool is_int, int mode, const DevCode*
                        surv, metric, end_out, item_end, counter);
     return hipGetLastError();
   };
+  // float16 soft values: the all-VALU exchange scheme (MODE 2) only
+  if (dt == 2 && mode != 2) return hipErrorInvalidValue;
 #define MV_ROT(KM1, I, B)                                                   \
-  return mode == 2   ? go(k_fwd_rot<KM1, I, B, 2>)                         \
-         : mode == 1 ? go(k_fwd_rot<KM1, I, B, 1>)                         \
-                     : go(k_fwd_rot<KM1, I, B, 0>)
+  if constexpr (I == 2) return go(k_fwd_rot<KM1, I, B, 2>);                \
+  else return mode == 2 ? go(k_fwd_rot<KM1, I, B, 2>)                      \
+              : mode == 1 ? go(k_fwd_rot<KM1, I, B, 1>)                    \
+                          : go(k_fwd_rot<KM1, I, B, 0>)
 #define MV_ROT_B(KM1, I)              \
   switch (beta) {                     \
     case 2: MV_ROT(KM1, I, 2);        \
@@ -539,10 +551,11 @@ hipError_t launch_fwd_rot(int K, int beta, bool is_int, int mode, const DevCode*
     case 7: MV_ROT_B(6, I);           \
     default: return hipErrorInvalidValue; \
   }
-  if (is_int) {
-    MV_ROT_K(true);
-  } else {
-    MV_ROT_K(false);
+  switch (dt) {
+    case 0: MV_ROT_K(0);
+    case 1: MV_ROT_K(1);
+    case 2: MV_ROT_K(2);
+    default: return hipErrorInvalidValue;
   }
 #undef MV_ROT_K
 #undef MV_ROT_B

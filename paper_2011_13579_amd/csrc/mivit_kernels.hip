@@ -34,16 +34,24 @@ __device__ __forceinline__ int branch_out(const DevCode& c, int i, int u) {
   return w;
 }
 
-template <bool INT>
+// Soft-value type DT (0: float32, 1: int8, 2: float16) and its metric
+// arithmetic (float32 for both float types, exact int32 for int8).
+template <int DT>
 struct Arith;
 template <>
-struct Arith<false> {
+struct Arith<0> {
+  static constexpr bool kInt = false;
   using T = float;
   using In = float;
   __device__ static T unreachable() { return -__builtin_inff(); }
 };
 template <>
-struct Arith<true> {
+struct Arith<2> : Arith<0> {
+  using In = _Float16;
+};
+template <>
+struct Arith<1> {
+  static constexpr bool kInt = true;
   using T = int;
   using In = int8_t;
   // Finite stand-in for minus infinity: every reachable metric stays above
@@ -56,11 +64,11 @@ constexpr int kBlk = 64;  // stages per staged block
 
 // Eq. (BM) for every beta-bit output pattern p of stage t0+lane:
 // bmt[lane][p] = sum_b (-1)^{p_b} l[b], summed in increasing b from zero.
-template <bool INT>
-__device__ __forceinline__ void fill_bm_table(const DevCode& c, const typename Arith<INT>::In* llr,
+template <int DT>
+__device__ __forceinline__ void fill_bm_table(const DevCode& c, const typename Arith<DT>::In* llr,
                                               int64_t off, int t0, int nst,
-                                              typename Arith<INT>::T (*bmt)[16]) {
-  using T = typename Arith<INT>::T;
+                                              typename Arith<DT>::T (*bmt)[16]) {
+  using T = typename Arith<DT>::T;
   const int lane = threadIdx.x;
   if (lane < nst) {
     T l[4];
@@ -78,9 +86,9 @@ __device__ __forceinline__ void fill_bm_table(const DevCode& c, const typename A
 }
 
 // Final state and metric of an item (shared by both forward kernels).
-template <bool INT, int NSL>
-__device__ __forceinline__ void finish_item(const Item& it, int NS, const typename Arith<INT>::T* pm,
-                                            const bool* act, typename Arith<INT>::T* xpm,
+template <int DT, int NSL>
+__device__ __forceinline__ void finish_item(const Item& it, int NS, const typename Arith<DT>::T* pm,
+                                            const bool* act, typename Arith<DT>::T* xpm,
                                             int64_t offset, void* metric, int32_t* end_out,
                                             int32_t* item_end) {
   const int lane = threadIdx.x;
@@ -99,7 +107,7 @@ __device__ __forceinline__ void finish_item(const Item& it, int NS, const typena
     if (it.frame >= 0) {
       if (end_out) end_out[it.frame] = js;
       if (metric) {
-        if constexpr (INT)
+        if constexpr (Arith<DT>::kInt)
           ((int64_t*)metric)[it.frame] = (int64_t)xpm[js] + offset;
         else
           ((float*)metric)[it.frame] = (float)xpm[js];
@@ -111,14 +119,14 @@ __device__ __forceinline__ void finish_item(const Item& it, int NS, const typena
 // ---------------------------------------------------------------------------
 // Radix-2 forward procedure.
 // ---------------------------------------------------------------------------
-template <int NSL, bool INT>
+template <int NSL, int DT>
 __global__ __launch_bounds__(64) void k_fwd_r2(const DevCode* __restrict__ codes,
                                                const Item* __restrict__ items,
                                                const void* __restrict__ llr_v,
                                                uint64_t* __restrict__ surv, void* metric,
                                                int32_t* end_out, int32_t* item_end) {
-  using T = typename Arith<INT>::T;
-  using In = typename Arith<INT>::In;
+  using T = typename Arith<DT>::T;
+  using In = typename Arith<DT>::In;
   const In* llr = (const In*)llr_v;
   const Item it = items[blockIdx.x];
   const DevCode c = codes[it.code];
@@ -141,15 +149,15 @@ __global__ __launch_bounds__(64) void k_fwd_r2(const DevCode* __restrict__ codes
     iLo[s] = 2 * f;
     pLo[s] = branch_out(c, 2 * f, u);
     pHi[s] = branch_out(c, 2 * f + 1, u);
-    pm[s] = (it.start_known && j != 0) ? Arith<INT>::unreachable() : (T)0;
+    pm[s] = (it.start_known && j != 0) ? Arith<DT>::unreachable() : (T)0;
     svlo[s] = svhi[s] = 0;
   }
   int64_t offset = 0;  // integer metrics: total subtracted by renormalisation
   const int S = it.n_stages;
   for (int t0 = 0; t0 < S; t0 += kBlk) {
     const int nst = min(kBlk, S - t0);
-    fill_bm_table<INT>(c, llr, it.llr_off, t0, nst, bmt);
-    if constexpr (INT) {
+    fill_bm_table<DT>(c, llr, it.llr_off, t0, nst, bmt);
+    if constexpr (Arith<DT>::kInt) {
       if (t0 > 0) {
         // subtract the metric of state 0 (held by lane 0, slot 0) from all
         const T ref = __builtin_amdgcn_readfirstlane(pm[0]);
@@ -185,7 +193,7 @@ __global__ __launch_bounds__(64) void k_fwd_r2(const DevCode* __restrict__ codes
       for (int s = 0; s < NSL; ++s) dst[s] = ((uint64_t)svhi[s] << 32) | svlo[s];
     }
   }
-  finish_item<INT, NSL>(it, NS, pm, act, xpm, offset, metric, end_out, item_end);
+  finish_item<DT, NSL>(it, NS, pm, act, xpm, offset, metric, end_out, item_end);
 }
 
 // ---------------------------------------------------------------------------
@@ -236,14 +244,14 @@ __global__ __launch_bounds__(64) void k_fwd_r4(const DevCode* __restrict__ codes
       q1[s][y] = (uint8_t)branch_out(c, i, u1);
       q2[s][y] = (uint8_t)branch_out(c, m, u2);
     }
-    pm[s] = (it.start_known && j != 0) ? Arith<true>::unreachable() : 0;
+    pm[s] = (it.start_known && j != 0) ? Arith<1>::unreachable() : 0;
     svlo[s] = svhi[s] = 0;
   }
   int64_t offset = 0;
   const int S = it.n_stages;
   for (int t0 = 0; t0 < S; t0 += kBlk) {
     const int nst = min(kBlk, S - t0);
-    fill_bm_table<true>(c, llr, it.llr_off, t0, nst, bmt);
+    fill_bm_table<1>(c, llr, it.llr_off, t0, nst, bmt);
     if (t0 > 0) {
       const T ref = __builtin_amdgcn_readfirstlane(pm[0]);
 #pragma unroll
@@ -312,7 +320,7 @@ __global__ __launch_bounds__(64) void k_fwd_r4(const DevCode* __restrict__ codes
       for (int s = 0; s < NSL; ++s) dst[s] = ((uint64_t)svhi[s] << 32) | svlo[s];
     }
   }
-  finish_item<true, NSL>(it, NS, pm, act, xpm, offset, metric, end_out, item_end);
+  finish_item<1, NSL>(it, NS, pm, act, xpm, offset, metric, end_out, item_end);
 }
 
 // ---------------------------------------------------------------------------
@@ -431,7 +439,7 @@ __global__ __launch_bounds__(256) void k_quant_i8(const float* __restrict__ x,
 }
 
 // Host-side launch helpers (called by the C ABI layer).
-hipError_t launch_fwd(int radix, int nsl, bool is_int, const DevCode* codes, const Item* items,
+hipError_t launch_fwd(int radix, int nsl, int dt, const DevCode* codes, const Item* items,
                       int n_items, const void* llr, uint64_t* surv, void* metric,
                       int32_t* end_out, int32_t* item_end, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
@@ -446,13 +454,17 @@ hipError_t launch_fwd(int radix, int nsl, bool is_int, const DevCode* codes, con
       default: return hipErrorInvalidValue;
     }
   } else {
-    switch (nsl * 2 + (is_int ? 1 : 0)) {
-      case 2: MV_FWD2(1, false); break;
-      case 3: MV_FWD2(1, true); break;
-      case 4: MV_FWD2(2, false); break;
-      case 5: MV_FWD2(2, true); break;
-      case 8: MV_FWD2(4, false); break;
-      case 9: MV_FWD2(4, true); break;
+    if (dt < 0 || dt > 2) return hipErrorInvalidValue;
+    switch (nsl * 4 + dt) {
+      case 4: MV_FWD2(1, 0); break;
+      case 5: MV_FWD2(1, 1); break;
+      case 6: MV_FWD2(1, 2); break;
+      case 8: MV_FWD2(2, 0); break;
+      case 9: MV_FWD2(2, 1); break;
+      case 10: MV_FWD2(2, 2); break;
+      case 16: MV_FWD2(4, 0); break;
+      case 17: MV_FWD2(4, 1); break;
+      case 18: MV_FWD2(4, 2); break;
       default: return hipErrorInvalidValue;
     }
   }
@@ -507,7 +519,7 @@ __global__ __launch_bounds__(64) void k_zero_i32(int32_t* __restrict__ p, int n)
 
 // Deterministic pseudo-random soft values for the autotuner's timing runs
 // (an integer hash of the index; no statistical claims).
-__global__ __launch_bounds__(256) void k_fill_random(void* __restrict__ p, int64_t n, int is_int,
+__global__ __launch_bounds__(256) void k_fill_random(void* __restrict__ p, int64_t n, int dt,
                                                      uint32_t seed) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
@@ -515,10 +527,13 @@ __global__ __launch_bounds__(256) void k_fill_random(void* __restrict__ p, int64
     x ^= x >> 15;
     x *= 0x85EBCA77u;
     x ^= x >> 13;
-    if (is_int)
+    const float f = ((float)(x & 0xFFFFu) * (1.0f / 65536.0f) - 0.5f) * 8.0f;
+    if (dt == 1)
       ((int8_t*)p)[k] = (int8_t)((int)(x % 129u) - 64);
+    else if (dt == 2)
+      ((_Float16*)p)[k] = (_Float16)f;
     else
-      ((float*)p)[k] = ((float)(x & 0xFFFFu) * (1.0f / 65536.0f) - 0.5f) * 8.0f;
+      ((float*)p)[k] = f;
   }
 }
 
@@ -528,12 +543,11 @@ hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_fill_random(void* p, int64_t n, bool is_int, uint32_t seed, hipStream_t st) {
+hipError_t launch_fill_random(void* p, int64_t n, int dt, uint32_t seed, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_fill_random, dim3((unsigned)blocks), dim3(256), 0, st, p, n, is_int ? 1 : 0,
-                     seed);
+  hipLaunchKernelGGL(k_fill_random, dim3((unsigned)blocks), dim3(256), 0, st, p, n, dt, seed);
   return hipGetLastError();
 }
 

@@ -105,11 +105,27 @@ def test_overlapping_outputs():
 
 
 @pytest.mark.parametrize("opts", [
-    dict(dtype=2), dict(radix=3), dict(radix=4, dtype=0), dict(chunk=-1), dict(chunk=100),
+    dict(dtype=3), dict(dtype=-1), dict(radix=3), dict(radix=4, dtype=0), dict(radix=4, dtype=2),
+    dict(chunk=-1), dict(chunk=100),
     dict(overlap=-1), dict(variant=3), dict(flags=8), dict(flags=1 << 31),
 ])
 def test_bad_opts(opts):
     assert _plan_status([K7], _frame(), **opts) == _capi.MIVIT_EINVAL
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_f16_other_variants_unsupported(variant):
+    """float16 soft values run the default exchange scheme only."""
+    assert _plan_status([K7], _frame(), dtype=_capi.MIVIT_F16, variant=variant) == \
+        _capi.MIVIT_EUNSUPPORTED
+
+
+def test_dtype_values():
+    """The soft-value type constants of the binding match the header's."""
+    text = open(os.path.join(ROOT, "include", "mivit.h")).read()
+    m = re.search(r"MIVIT_F32 = (\d+), MIVIT_I8 = (\d+), MIVIT_F16 = (\d+)", text)
+    assert m and tuple(int(x) for x in m.groups()) == (_capi.MIVIT_F32, _capi.MIVIT_I8,
+                                                          _capi.MIVIT_F16)
 
 
 def test_reserved_opts_must_be_zero():

@@ -123,7 +123,7 @@ def _plan_decode(code, frames, llr_np, dtype, radix=0, chunk=0, overlap=0):
 
 
 @pytest.mark.parametrize("code", [CODE_K5, CODE_K7, CODE_K9], ids=cid)
-@pytest.mark.parametrize("dtype,radix", [("f32", 2), ("i8", 2), ("i8", 4)])
+@pytest.mark.parametrize("dtype,radix", [("f32", 2), ("f16", 2), ("i8", 2), ("i8", 4)])
 def test_free_end_and_unknown_start(code, dtype, radix):
     """Frames with a best-state end and with an unknown start (all-zero
     initial metrics), mixed lengths in one plan."""
@@ -141,12 +141,17 @@ def test_free_end_and_unknown_start(code, dtype, radix):
     if dtype == "f32":
         llr = rng.normal(0, 3, off).astype(np.float32)
         mode = oracle.F32
+    elif dtype == "f16":
+        llr = rng.normal(0, 3, off).astype(np.float16)
+        mode = oracle.F32
     else:
         llr = rng.integers(-3, 4, off).astype(np.int8)
         mode = oracle.I64
     print("free-end", cid(code), dtype, radix, flush=True)
     _, bits, metric, end = _plan_decode(code, fr, llr, dtype, radix)
-    ob, om, oend, _ = oracle.decode_frames([code], ofr, llr, mode, boff)
+    # float16 values convert to float32 exactly: the float32 oracle decides
+    ref = llr.astype(np.float32) if dtype == "f16" else llr
+    ob, om, oend, _ = oracle.decode_frames([code], ofr, ref, mode, boff)
     np.testing.assert_array_equal(end, oend)
     np.testing.assert_array_equal(metric, om)
     for k in range(len(fr)):
@@ -154,7 +159,7 @@ def test_free_end_and_unknown_start(code, dtype, radix):
         np.testing.assert_array_equal(bits[a:a + S], ob[a:a + S])
 
 
-@pytest.mark.parametrize("dtype", ["i8", "f32"])
+@pytest.mark.parametrize("dtype", ["i8", "f32", "f16"])
 def test_chunked_stream(dtype):
     """A continuous stream split into 2048-stage chunks with 64 stages of
     overlap on each side; identical to the oracle using the same chunking."""
@@ -166,12 +171,15 @@ def test_chunked_stream(dtype):
         mode = oracle.I64
     else:
         mode = oracle.F32
+        if dtype == "f16":
+            llr = llr.astype(np.float16)
     t = torch.from_numpy(llr).to(DEV)
+    ref = llr.astype(np.float32) if dtype == "f16" else llr
     for radix in ((2, 4) if dtype == "i8" else (2,)):
         words = mv.decode_stream(t, CODE_K7, n, 2048, 64, radix)
         torch.cuda.synchronize()
         bits = mv.unpack_bits(words.cpu().numpy(), n)
-        ob, _, _ = oracle.decode_chunked(CODE_K7, llr, n, 2048, 64, mode)
+        ob, _, _ = oracle.decode_chunked(CODE_K7, ref, n, 2048, 64, mode)
         np.testing.assert_array_equal(bits, ob)
         assert (bits != msg).sum() < 50
 
@@ -362,7 +370,8 @@ def _mixed(dtype, F=240, seed=4):
         fr[f] = (mb.llr_offset[f], mb.bit_offset[f], S[f], 0, n[f], mb.code_idx[f],
                  mv.MIVIT_START_KNOWN | mv.MIVIT_END_ZERO)
         ofr[f] = (mb.llr_offset[f], mb.bit_offset[f], S[f], 0, n[f], 1, 0, mb.code_idx[f])
-    llr = mb.llr if dtype == "f32" else oracle.quantize_i8(mb.llr, 6.0)
+    llr = {"f32": lambda: mb.llr, "f16": lambda: mb.llr.astype(np.float16),
+           "i8": lambda: oracle.quantize_i8(mb.llr, 6.0)}[dtype]()
     n_bits = int(mb.bit_offset[-1] + ((n[-1] + 31) // 32) * 32)
     return codes, fr, ofr, llr, n_bits
 
@@ -376,8 +385,9 @@ def _check_mixed(codes, plan, fr, ofr, llr_np, dtype, n_bits, words=None):
     else:
         metric = None
     bits = mv.unpack_bits(words.cpu().numpy()[: n_bits // 32], n_bits)
-    mode = oracle.F32 if dtype == "f32" else oracle.I64
-    ob, om, _, _ = oracle.decode_frames(codes, ofr, llr_np, mode, n_bits)
+    mode = oracle.I64 if dtype == "i8" else oracle.F32
+    ref = llr_np.astype(np.float32) if dtype == "f16" else llr_np
+    ob, om, _, _ = oracle.decode_frames(codes, ofr, ref, mode, n_bits)
     for k in range(len(fr)):
         a, n = int(ofr[k]["bit_offset"]), int(ofr[k]["n_out"])
         np.testing.assert_array_equal(bits[a:a + n], ob[a:a + n])
@@ -385,7 +395,7 @@ def _check_mixed(codes, plan, fr, ofr, llr_np, dtype, n_bits, words=None):
         np.testing.assert_array_equal(metric[: len(fr)], om)
 
 
-@pytest.mark.parametrize("dtype", ["i8", "f32"])
+@pytest.mark.parametrize("dtype", ["i8", "f32", "f16"])
 @pytest.mark.parametrize("mode", ["default", "persistent", "autotune"])
 def test_mixed_codes_batch(dtype, mode):
     """Uneven frames of three codes in one plan: one part per code, run
@@ -566,3 +576,23 @@ def test_r4_packed_varied_frames():
             for k in range(len(fr)):
                 s, n = int(ofr[k]["bit_offset"]), int(ofr[k]["n_out"])
                 np.testing.assert_array_equal(bits[s:s + n], ob[s:s + n])
+
+
+@pytest.mark.parametrize("code", [CODE_K5, CODE_K7, CODE_K9], ids=cid)
+def test_f16_uniform_and_variants(code):
+    """float16 soft values (the half-precision channel input with float32
+    path metrics): bits and metrics equal the float32 oracle on the same
+    values converted to float32, terminated frames of several lengths; the
+    result also equals the float32 path fed those converted values."""
+    for n, F, eb in [(1, 3, 2.0), (61, 5, 1.0), (777, 4, 2.0), (3000, 2, 3.0)]:
+        b = make_uniform_batch(code, F, n, eb, seed=3100 + n + code.K)
+        h = b.llr.astype(np.float16)
+        print("f16", cid(code), n, F, flush=True)
+        bits, metric = gpu_decode(h, code, n, True, 2)
+        f = h.astype(np.float32)
+        ob, om, _ = oracle.decode_uniform(code, f, n, True, oracle.F32)
+        np.testing.assert_array_equal(bits, ob)
+        np.testing.assert_array_equal(metric, om)
+        bits32, metric32 = gpu_decode(f, code, n, True, 2)
+        np.testing.assert_array_equal(bits, bits32)
+        np.testing.assert_array_equal(metric, metric32)
