@@ -257,6 +257,10 @@ def quantize_i8(llr, scale: float, out=None, stream=None):
     llr = llr.contiguous()
     if out is None:
         out = torch.empty(llr.shape, dtype=torch.int8, device=llr.device)
+    elif (out.dtype != torch.int8 or out.device != llr.device or not out.is_contiguous()
+          or out.numel() < llr.numel()):
+        raise ValueError("out must be a contiguous int8 tensor on the device of llr with at "
+                         "least llr.numel() elements")
     st = _capi.load().mivit_quantize_i8(_dptr(llr), _dptr(out), llr.numel(), float(scale),
                                         _stream_handle(stream))
     _capi.check(st, "mivit_quantize_i8")

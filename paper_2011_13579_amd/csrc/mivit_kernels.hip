@@ -425,16 +425,39 @@ __global__ __launch_bounds__(256) void k_grad(const DevCode* __restrict__ codes,
 // ---------------------------------------------------------------------------
 // int8 quantiser: saturate_127(round_half_even(fl32(x * scale))), NaN -> 0.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int quant1(float x, float scale) {
+  float r = __builtin_rintf(x * scale);
+  r = r > 127.0f ? 127.0f : r;
+  r = r < -127.0f ? -127.0f : r;
+  if (r != r) r = 0.0f;
+  return (int)r;
+}
+
 __global__ __launch_bounds__(256) void k_quant_i8(const float* __restrict__ x,
                                                   int8_t* __restrict__ q, int64_t n,
                                                   float scale) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
-    float r = __builtin_rintf(x[k] * scale);
-    r = r > 127.0f ? 127.0f : r;
-    r = r < -127.0f ? -127.0f : r;
-    if (r != r) r = 0.0f;
-    q[k] = (int8_t)(int)r;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
+    q[k] = (int8_t)quant1(x[k], scale);
+}
+
+// Same values, four per thread and step: one 16-byte load, one 4-byte store
+// (x 16-byte and q 4-byte aligned); the n mod 4 last values one by one.
+__global__ __launch_bounds__(256) void k_quant_i8_v4(const float4* __restrict__ x,
+                                                     uint32_t* __restrict__ q, int64_t n,
+                                                     float scale) {
+  const int64_t n4 = n >> 2;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t k = t; k < n4; k += stride) {
+    const float4 v = x[k];
+    q[k] = (uint32_t)(quant1(v.x, scale) & 0xFF) | ((uint32_t)(quant1(v.y, scale) & 0xFF) << 8) |
+           ((uint32_t)(quant1(v.z, scale) & 0xFF) << 16) |
+           ((uint32_t)(quant1(v.w, scale) & 0xFF) << 24);
+  }
+  if (t < (n & 3)) {
+    const int64_t k = 4 * n4 + t;
+    ((int8_t*)q)[k] = (int8_t)quant1(((const float*)x)[k], scale);
   }
 }
 
@@ -499,6 +522,14 @@ hipError_t launch_grad(const DevCode* codes, const GradFrame* frames, int n_fram
 
 hipError_t launch_quant(const float* x, int8_t* q, int64_t n, float scale, hipStream_t st) {
   if (n <= 0) return hipSuccess;
+  if (((uintptr_t)x & 15) == 0 && ((uintptr_t)q & 3) == 0) {
+    int64_t blocks = ((n >> 2) + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_quant_i8_v4, dim3((unsigned)blocks), dim3(256), 0, st,
+                       (const float4*)x, (uint32_t*)q, n, scale);
+    return hipGetLastError();
+  }
   int64_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_quant_i8, dim3((unsigned)blocks), dim3(256), 0, st, x, q, n, scale);

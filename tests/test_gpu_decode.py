@@ -240,6 +240,18 @@ def test_quantizer_exact():
     for scale in (1.0, 0.37, 16 * 0.5011872336272722, 3.0):
         q_gpu = mv.quantize_i8(torch.from_numpy(x).to(DEV), scale).cpu().numpy()
         np.testing.assert_array_equal(q_gpu, oracle.quantize_i8(x, scale))
+    # ragged lengths and unaligned input / output (the one-value-per-thread path)
+    xd = torch.from_numpy(x).to(DEV)
+    qbuf = torch.zeros(x.size + 8, dtype=torch.int8, device=DEV)
+    for n, xo, qo in [(1, 0, 0), (3, 0, 0), (5, 0, 0), (100013, 0, 0), (100013, 1, 0),
+                      (100010, 0, 2), (7, 3, 1)]:
+        qbuf.fill_(77)
+        mv.quantize_i8(xd[xo:xo + n], 3.0, out=qbuf[qo:qo + n])
+        got = qbuf.cpu().numpy()
+        np.testing.assert_array_equal(got[qo:qo + n], oracle.quantize_i8(x[xo:xo + n], 3.0))
+        assert (got[:qo] == 77).all() and (got[qo + n:] == 77).all()
+    with pytest.raises(ValueError):
+        mv.quantize_i8(xd[:100], 1.0, out=qbuf[:99])
 
 
 @pytest.mark.parametrize("variant", [0, 1, 2])
