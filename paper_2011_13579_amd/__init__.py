@@ -115,8 +115,12 @@ class Plan:
         if len(self.frames):
             ends = self.frames["bit_offset"] + self.frames["n_out"]
             self.n_bit_words = int((ends.max() + 31) // 32)
+            beta = np.array([c.beta for c in self.codes], np.int64)[self.frames["code"]]
+            self.llr_extent = int((self.frames["llr_offset"] +
+                                   self.frames["n_stages"].astype(np.int64) * beta).max())
         else:
             self.n_bit_words = 0
+            self.llr_extent = 0
 
     def describe(self) -> str:
         """The plan's parts: kernel, variant and launch form per code."""
@@ -136,14 +140,29 @@ class Plan:
         end = torch.zeros(max(self.n_frames, 1), dtype=torch.int32, device=device)
         return bits, metric, end
 
-    def decode(self, llr, bits=None, metric=None, end_state=None, stream=None):
-        """Decode on the current stream; returns (bit words int32, metric, end state)."""
+    def _check_io(self, llr=None, bits=None, metric=None, end_state=None):
+        """The library takes raw device pointers: tensors must have the plan's
+        types and at least the extents its frames address."""
         torch = _torch()
-        want = {MIVIT_F32: torch.float32, MIVIT_I8: torch.int8, MIVIT_F16: torch.float16}[self.dtype]
-        if llr.dtype != want or not llr.is_cuda or not llr.is_contiguous():
-            raise ValueError("llr must be a contiguous device tensor of dtype %s" % want)
+        want = {MIVIT_F32: torch.float32, MIVIT_I8: torch.int8, MIVIT_F16: torch.float16}
+        mdt = torch.int64 if self.dtype == MIVIT_I8 else torch.float32
+        for name, t, dt, n in (("llr", llr, want[self.dtype], self.llr_extent),
+                               ("bits", bits, torch.int32, self.n_bit_words),
+                               ("metric", metric, mdt, self.n_frames),
+                               ("end_state", end_state, torch.int32, self.n_frames)):
+            if t is None:
+                continue
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous() or t.numel() < n:
+                raise ValueError("%s must be a contiguous device tensor of dtype %s with at "
+                                 "least %d elements" % (name, dt, n))
+
+    def decode(self, llr, bits=None, metric=None, end_state=None, stream=None):
+        """Decode on the current stream; returns (bit words int32, metric, end state).
+        Without bits, all three outputs are allocated; metric and end_state
+        may otherwise be None (not written)."""
         if bits is None:
             bits, metric, end_state = self.empty_outputs(llr.device)
+        self._check_io(llr, bits, metric, end_state)
         st = self._lib.mivit_decode(self._h, _dptr(llr), _dptr(bits), _dptr(metric),
                                     _dptr(end_state), _stream_handle(stream))
         _capi.check(st, "mivit_decode")
@@ -151,17 +170,28 @@ class Plan:
 
     def forward(self, llr, metric=None, end_state=None, stream=None):
         """Forward procedure only (decisions stay in the plan)."""
+        self._check_io(llr, None, metric, end_state)
         st = self._lib.mivit_forward(self._h, _dptr(llr), _dptr(metric), _dptr(end_state),
                                      _stream_handle(stream))
         _capi.check(st, "mivit_forward")
 
     def traceback(self, bits, stream=None):
         """Traceback of the decisions left by the last forward call."""
+        self._check_io(None, bits)
         st = self._lib.mivit_traceback(self._h, _dptr(bits), _stream_handle(stream))
         _capi.check(st, "mivit_traceback")
         return bits
 
     def decode_grad(self, bits, grad_metric, grad_llr, stream=None):
+        """d(metric)/d(llr) of the decode that wrote bits (float32 tensors)."""
+        torch = _torch()
+        self._check_io(None, bits)
+        for name, t, n in (("grad_metric", grad_metric, self.n_frames),
+                           ("grad_llr", grad_llr, self.llr_extent)):
+            if (t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous()
+                    or t.numel() < n):
+                raise ValueError("%s must be a contiguous float32 device tensor with at least "
+                                 "%d elements" % (name, n))
         st = self._lib.mivit_decode_grad(self._h, _dptr(bits), _dptr(grad_metric),
                                          _dptr(grad_llr), _stream_handle(stream))
         _capi.check(st, "mivit_decode_grad")

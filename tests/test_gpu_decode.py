@@ -608,3 +608,34 @@ def test_f16_uniform_and_variants(code):
         bits32, metric32 = gpu_decode(f, code, n, True, 2)
         np.testing.assert_array_equal(bits, bits32)
         np.testing.assert_array_equal(metric, metric32)
+
+
+def test_binding_rejects_bad_tensors():
+    """The binding checks every tensor against the plan before handing raw
+    pointers to the library: wrong dtype, host memory or too few elements
+    raise ValueError and launch nothing."""
+    code = CODE_K7
+    F, n = 3, 100
+    fr = mv.uniform_frames(code, F, n, True)
+    plan = mv.Plan([code], fr, "f32", 2)
+    S = n + code.K - 1
+    good = torch.zeros(F * S * 2, device=DEV)
+    bits, metric, end = plan.empty_outputs(DEV)
+    bad = [
+        dict(llr=good[:-1]),                                   # one value short
+        dict(llr=good.half()),                                 # wrong soft-value type
+        dict(llr=good.cpu()),                                  # host memory
+        dict(llr=good, bits=bits[:-1]),                        # output words short
+        dict(llr=good, bits=bits, metric=metric.long()),       # metric type of int8 plans
+        dict(llr=good, bits=bits, end_state=end[:F - 1]),      # end states short
+    ]
+    for kw in bad:
+        with pytest.raises(ValueError):
+            plan.decode(**kw)
+    with pytest.raises(ValueError):
+        plan.forward(good[:-2], metric, end)
+    with pytest.raises(ValueError):
+        plan.traceback(bits.float())
+    w, m, e = plan.decode(good, bits, None, None)  # optional outputs may be omitted
+    torch.cuda.synchronize()
+    assert w is bits
