@@ -191,6 +191,10 @@ typedef struct {
   int64_t total_stages;    /* sum of stages over work items */
   int32_t radix;           /* radix in use */
   int32_t dtype;
+  int64_t llr_elems;       /* soft values the frames address: max(llr_offset + S*beta) */
+  int64_t bit_words;       /* output words the frames address: max(ceil((bit_offset + n_out)/32)) */
+  int32_t n_frames;        /* frames as passed to mivit_plan_create */
+  int32_t device;          /* HIP device the plan lives on */
 } mivit_plan_info;
 mivit_status mivit_plan_get_info(const mivit_plan* plan, mivit_plan_info* info);
 
@@ -198,6 +202,32 @@ mivit_status mivit_plan_get_info(const mivit_plan* plan, mivit_plan_info* info);
  * launch form, items, wavefronts.  Writes at most len bytes including the
  * terminating zero into the host buffer buf (truncating). */
 mivit_status mivit_plan_describe(const mivit_plan* plan, char* buf, int32_t len);
+
+/* Host pipeline (not in the paper, which leaves the host transfers aside;
+ * its §III notes that frames and streams give the GPU independent work):
+ * decode a sequence of batches held in host memory, each laid out exactly as
+ * the plan's frames describe, with the copy of one batch to the device, the
+ * decode of another and the copy of a third one's results back in flight at
+ * once (three HIP streams, `depth` device buffer sets of the plan's extents).
+ *
+ * mivit_pipe_create: depth 2..8 buffer sets on the plan's device; the plan
+ *   must outlive the pipe and must not be used by other calls while
+ *   mivit_pipe_run runs.
+ * mivit_pipe_run: batch b reads llr_elems soft values (the plan's dtype) at
+ *   host_llr + b * llr_elems, writes bit_words words at host_bits +
+ *   b * bit_words and, if host_metric is not NULL, n_frames metrics (float32,
+ *   or int64 for int8 plans) at host_metric + b * n_frames; the sizes are
+ *   those of mivit_plan_get_info.  Blocks until every batch's results are in
+ *   host memory.  The copies overlap the decodes only for page-locked host
+ *   memory (hipHostMalloc, or torch's pin_memory); other host memory still
+ *   gives the same results.  Errors: MIVIT_EINVAL for null arguments or
+ *   n_batches < 0; a decode's own status; MIVIT_EHIP if a copy fails.
+ * mivit_pipe_destroy: waits for the pipe's streams and frees its memory. */
+typedef struct mivit_pipe mivit_pipe;
+mivit_status mivit_pipe_create(mivit_pipe** pipe, mivit_plan* plan, int32_t depth);
+mivit_status mivit_pipe_run(mivit_pipe* pipe, const void* host_llr, uint32_t* host_bits,
+                            void* host_metric, int64_t n_batches);
+mivit_status mivit_pipe_destroy(mivit_pipe* pipe);
 
 /* int8 quantiser for soft values (the paper uses float inputs; this is the
  * library's choice): q[k] = saturate_127(round_half_even(fl32(llr[k] *

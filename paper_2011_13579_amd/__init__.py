@@ -10,6 +10,7 @@ Entry points
   decode(llr, code, n_info, terminated, radix)       equal-length frames
   decode_stream(llr, code, n_info, chunk, overlap)   one long stream, chunked
   quantize_i8(llr, scale)                            float32 -> int8 soft values
+  Pipeline(plan, depth).run(host_llr, host_bits)     batches from host memory
   ViterbiDecode.apply(llr, code, n_info)             autograd on the best metric
 """
 from __future__ import annotations
@@ -24,7 +25,7 @@ from . import _capi
 from ._capi import (FRAME_DTYPE, MIVIT_END_ZERO, MIVIT_F16, MIVIT_F32, MIVIT_I8, MIVIT_START_KNOWN,
                     MivitError)
 
-__all__ = ["Code", "Plan", "decode", "decode_stream", "quantize_i8", "ViterbiDecode",
+__all__ = ["Code", "Plan", "Pipeline", "decode", "decode_stream", "quantize_i8", "ViterbiDecode",
            "unpack_bits", "FRAME_DTYPE", "MivitError", "version"]
 
 
@@ -200,6 +201,61 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.mivit_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Pipeline:
+    """Host pipeline over a plan (mivit_pipe_*): batches of soft values in
+    host memory, each laid out as the plan's frames describe, are copied in,
+    decoded and their bits (and metrics) copied back, with copy-in, decode
+    and copy-out of different batches overlapping.  The plan must stay
+    alive and unused by other calls while run() runs."""
+
+    def __init__(self, plan: "Plan", depth: int = 3):
+        self._lib = _capi.load()
+        self.plan = plan
+        info = _capi.PlanInfo()
+        _capi.check(self._lib.mivit_plan_get_info(plan._h, ctypes.byref(info)),
+                    "mivit_plan_get_info")
+        self.llr_elems, self.bit_words, self.n_frames = (int(info.llr_elems),
+                                                         int(info.bit_words), int(info.n_frames))
+        h = ctypes.c_void_p()
+        _capi.check(self._lib.mivit_pipe_create(ctypes.byref(h), plan._h, int(depth)),
+                    "mivit_pipe_create")
+        self._h = h
+
+    def run(self, host_llr, host_bits, host_metric=None, n_batches: Optional[int] = None):
+        """Decode n_batches batches (default: as many as host_llr holds);
+        blocks until the results are in host memory.  Page-locked tensors
+        (pin_memory) let the copies overlap the decodes."""
+        torch = _torch()
+        want = {MIVIT_F32: torch.float32, MIVIT_I8: torch.int8, MIVIT_F16: torch.float16}
+        mdt = torch.int64 if self.plan.dtype == MIVIT_I8 else torch.float32
+        if n_batches is None:
+            n_batches = host_llr.numel() // max(self.llr_elems, 1)
+        for name, t, dt, n in (("host_llr", host_llr, want[self.plan.dtype], self.llr_elems),
+                               ("host_bits", host_bits, torch.int32, self.bit_words),
+                               ("host_metric", host_metric, mdt, self.n_frames)):
+            if t is None:
+                continue
+            if (t.dtype != dt or t.is_cuda or not t.is_contiguous()
+                    or t.numel() < n * n_batches):
+                raise ValueError("%s must be a contiguous host tensor of dtype %s with at least "
+                                 "%d elements" % (name, dt, n * n_batches))
+        st = self._lib.mivit_pipe_run(self._h, host_llr.data_ptr(), host_bits.data_ptr(),
+                                      host_metric.data_ptr() if host_metric is not None else None,
+                                      int(n_batches))
+        _capi.check(st, "mivit_pipe_run")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.mivit_pipe_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

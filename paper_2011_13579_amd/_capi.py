@@ -17,7 +17,7 @@ MIVIT_START_KNOWN, MIVIT_END_ZERO = 1, 2
 EXPORTS = (
     "mivit_plan_create", "mivit_decode", "mivit_forward", "mivit_traceback", "mivit_decode_grad", "mivit_plan_destroy",
     "mivit_plan_get_info", "mivit_plan_describe", "mivit_quantize_i8", "mivit_strerror",
-    "mivit_version",
+    "mivit_version", "mivit_pipe_create", "mivit_pipe_run", "mivit_pipe_destroy",
 )
 MIVIT_PLAN_GRAPH, MIVIT_PLAN_AUTOTUNE, MIVIT_PLAN_PERSISTENT = 1, 2, 4
 
@@ -53,7 +53,9 @@ class Opts(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n_items", ctypes.c_int64), ("survivor_bytes", ctypes.c_int64),
                 ("total_stages", ctypes.c_int64), ("radix", ctypes.c_int32),
-                ("dtype", ctypes.c_int32)]
+                ("dtype", ctypes.c_int32), ("llr_elems", ctypes.c_int64),
+                ("bit_words", ctypes.c_int64), ("n_frames", ctypes.c_int32),
+                ("device", ctypes.c_int32)]
 
 
 class MivitError(RuntimeError):
@@ -98,6 +100,12 @@ def load(path: str = LIB_PATH):
     lib.mivit_strerror.argtypes = [ctypes.c_int]
     lib.mivit_version.restype = ctypes.c_char_p
     lib.mivit_version.argtypes = []
+    lib.mivit_pipe_create.restype = ctypes.c_int
+    lib.mivit_pipe_create.argtypes = [ctypes.POINTER(vp), vp, i32]
+    lib.mivit_pipe_run.restype = ctypes.c_int
+    lib.mivit_pipe_run.argtypes = [vp, vp, vp, vp, i64]
+    lib.mivit_pipe_destroy.restype = ctypes.c_int
+    lib.mivit_pipe_destroy.argtypes = [vp]
     _lib = lib
     return lib
 

@@ -113,6 +113,8 @@ struct mivit_plan {
   int dtype = MIVIT_F32;
   uint32_t flags = 0;
   int n_frames = 0;
+  int64_t llr_end = 0;   // soft values the frames address
+  int64_t word_end = 0;  // output words the frames address
   bool grad_ok = false;
   int grad_max_stages = 0;
   DevCode* d_codes = nullptr;
@@ -551,6 +553,8 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
     p->dtype = o.dtype;
     p->flags = o.flags;
     p->n_frames = n_frames;
+    p->llr_end = llr_end;
+    p->word_end = word_end;
     std::vector<DevCode> dc(n_codes);
     for (int c = 0; c < n_codes; ++c) {
       dc[c].K = codes[c].K;
@@ -764,6 +768,10 @@ mivit_status mivit_plan_get_info(const mivit_plan* p, mivit_plan_info* info) {
   }
   if (best < 0) info->radix = 2;
   info->dtype = p->dtype;
+  info->llr_elems = p->llr_end;
+  info->bit_words = p->word_end;
+  info->n_frames = p->n_frames;
+  info->device = p->device;
   return MIVIT_OK;
 }
 

@@ -149,6 +149,16 @@ def test_plan_flag_values():
         assert m and int(m.group(1)) == getattr(_capi, name)
 
 
+def test_pipe_null_arguments():
+    lib = _capi.load()
+    h = ctypes.c_void_p()
+    assert lib.mivit_pipe_create(None, None, 3) == _capi.MIVIT_EINVAL
+    assert lib.mivit_pipe_create(ctypes.byref(h), None, 3) == _capi.MIVIT_EINVAL
+    assert not h.value
+    assert lib.mivit_pipe_run(None, None, None, None, 1) == _capi.MIVIT_EINVAL
+    assert lib.mivit_pipe_destroy(None) == _capi.MIVIT_EINVAL
+
+
 def test_null_and_misc():
     lib = _capi.load()
     assert lib.mivit_plan_create(None, None, 0, None, 0, None) == _capi.MIVIT_EINVAL

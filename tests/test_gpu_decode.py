@@ -639,3 +639,41 @@ def test_binding_rejects_bad_tensors():
     w, m, e = plan.decode(good, bits, None, None)  # optional outputs may be omitted
     torch.cuda.synchronize()
     assert w is bits
+
+
+@pytest.mark.parametrize("depth", [2, 3])
+def test_pipeline_matches_decode(depth):
+    """Batches decoded by the host pipeline (copy in, decode, copy out on
+    three streams) equal plan.decode of each batch on the device: mixed codes
+    and lengths, int8 radix 4 and float32 radix 2, page-locked and ordinary
+    host memory, and runs of 0, 1 and 5 batches."""
+    codes, fr, ofr, _, n_bits = _mixed("f32", F=60, seed=21)
+    rng = np.random.default_rng(99)
+    for dtype, radix in (("i8", 4), ("f32", 2)):
+        plan = mv.Plan(codes, fr, dtype, radix)
+        pipe = mv.Pipeline(plan, depth)
+        E, W, F = pipe.llr_elems, pipe.bit_words, pipe.n_frames
+        nb = 5
+        if dtype == "i8":
+            llr = torch.from_numpy(rng.integers(-40, 41, size=nb * E).astype(np.int8))
+        else:
+            llr = torch.from_numpy(rng.normal(0, 3, size=nb * E).astype(np.float32))
+        for pinned in (True, False):
+            h_llr = llr.pin_memory() if pinned else llr.clone()
+            bits = torch.full((nb * W,), -1, dtype=torch.int32)
+            metric = torch.zeros(nb * F, dtype=torch.int64 if dtype == "i8" else torch.float32)
+            if pinned:
+                bits, metric = bits.pin_memory(), metric.pin_memory()
+            print("pipeline", depth, dtype, pinned, flush=True)
+            pipe.run(h_llr, bits, metric, 0)
+            assert (bits == -1).all()
+            pipe.run(h_llr, bits, metric, 1)
+            pipe.run(h_llr, bits, metric, nb)
+            for b in range(nb):
+                w, m, _ = plan.decode(llr[b * E:(b + 1) * E].to(DEV))
+                torch.cuda.synchronize()
+                np.testing.assert_array_equal(bits[b * W:(b + 1) * W].numpy(), w.cpu().numpy()[:W])
+                np.testing.assert_array_equal(metric[b * F:(b + 1) * F].numpy(), m.cpu().numpy()[:F])
+        with pytest.raises(ValueError):
+            pipe.run(h_llr, bits[:-1], None, nb)
+        pipe.close()
