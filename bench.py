@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--ber", action="store_true", help="run the equal-BER sweep")
     ap.add_argument("--variants", default="i8r4,f32r2,f16r2,i8r2")
+    ap.add_argument("--configs", action="store_true",
+                    help="also measure the single-frame, stream, mixed-batch and backward workloads")
     ap.add_argument("--pcie", action="store_true",
                     help="also time the host pipeline (page-locked host memory in and out)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -217,6 +219,115 @@ def pcie_pipeline(torch, mv, plan, llr_dev, n_batches=8, depth=3):
             "note": "host pipeline, page-locked host buffers; context, not the headline"}
 
 
+def _gpu_ms(torch, fn, reps):
+    """Median GPU time of fn() in ms (HIP events on the current stream)."""
+    fn()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1))
+    return float(np.median(out))
+
+
+def _quantize_per_frame(torch, llr, ebn0, offsets, lengths, betas):
+    """int8 soft values with each frame's own scale (16 sigma^2 of its Eb/N0),
+    the library quantiser's rule applied on the GPU by torch."""
+    from workload import int8_scale_for
+    scale = np.repeat(np.array([int8_scale_for(float(e), int(b)) for e, b in zip(ebn0, betas)],
+                               np.float32), lengths)
+    assert int(offsets[0]) == 0 and scale.size == llr.shape[0]
+    x = torch.from_numpy(llr).to("cuda:0") * torch.from_numpy(scale).to("cuda:0")
+    return torch.clamp(torch.round(x), -127, 127).to(torch.int8)
+
+
+def other_configs(torch, mv):
+    """The single-frame (latency), 2^26-bit stream, 10000-frame mixed batch and
+    backward workloads: GPU times (HIP events, median) and rates."""
+    from workload import (CODE_K5, CODE_K7, CODE_K9, make_mixed_batch, make_stream,
+                          make_uniform_batch, int8_scale_for)
+    out = {}
+    dev = "cuda:0"
+    # single frame, 1024 bits, 3 dB: latency
+    b = make_uniform_batch(CODE_K7, 1, 1024, 3.0, seed=1)
+    lf = torch.from_numpy(b.llr).to(dev)
+    li = mv.quantize_i8(lf, int8_scale_for(3.0, 2))
+    fr = mv.uniform_frames(CODE_K7, 1, 1024, True)
+    c1 = {}
+    for name, dt, rx, llr in (("f32r2", "f32", 2, lf), ("i8r4", "i8", 4, li)):
+        plan = mv.Plan([CODE_K7], fr, dt, rx)
+        bits, metric, end = plan.empty_outputs(dev)
+        gpu = _gpu_ms(torch, lambda: plan.decode(llr, bits, metric, end), 50)
+        t0 = time.perf_counter()
+        for _ in range(50):
+            plan.decode(llr, bits, metric, end)
+            torch.cuda.synchronize()
+        c1[name] = {"gpu_us": round(gpu * 1e3, 1),
+                    "call_and_sync_us": round((time.perf_counter() - t0) / 50 * 1e6, 1)}
+    out["single_frame_1024"] = c1
+    # one 2^26-bit stream, 4 dB, int8, chunks of 2048 with 64 stages of overlap
+    n = 1 << 26
+    _, llr = make_stream(CODE_K7, n, 4.0, seed=3)
+    ls = mv.quantize_i8(torch.from_numpy(llr).to(dev), int8_scale_for(4.0, 2))
+    del llr
+    one = np.zeros(1, mv.FRAME_DTYPE)
+    one[0] = (0, 0, n, 0, n, 0, mv.MIVIT_START_KNOWN)
+    plan = mv.Plan([CODE_K7], one, "i8", 4, 2048, 64)
+    bits, metric, end = plan.empty_outputs(dev)
+    ms = _gpu_ms(torch, lambda: plan.decode(ls, bits, metric, end), 5)
+    ops = 3 * 64 * plan.total_stages
+    out["stream_2p26_chunk2048_ov64"] = {
+        "ms": round(ms, 3), "gbit_s": round(n / ms / 1e6, 2), "stages": plan.total_stages,
+        "tops": round(ops / ms / 1e9, 2), "frac_packed_peak": round(ops / ms / 1e9 / VALU16_PEAK_TOPS, 3)}
+    del ls, bits
+    # 10000 frames, log-uniform lengths, three codes, Eb/N0 U[1,5]
+    codes = [CODE_K5, CODE_K7, CODE_K9]
+    F = 10000
+    mb = make_mixed_batch(codes, F, 64, 16384, 1.0, 5.0, seed=4)
+    nn = mb.n_info.astype(np.int64)
+    K = np.array([codes[c].K for c in mb.code_idx])
+    beta = np.array([codes[c].beta for c in mb.code_idx])
+    S = nn + K - 1
+    frm = np.zeros(F, mv.FRAME_DTYPE)
+    for f in range(F):
+        frm[f] = (mb.llr_offset[f], mb.bit_offset[f], S[f], 0, nn[f], mb.code_idx[f],
+                  mv.MIVIT_START_KNOWN | mv.MIVIT_END_ZERO)
+    ops = float((3 * (2.0 ** (K - 1)) * S).sum())
+    c4 = {"frames": F, "info_bits": int(nn.sum()), "acs_ops": ops,
+          "longest_stages": int(S.max())}
+    inputs = {"f32": torch.from_numpy(mb.llr).to(dev),
+              "i8": _quantize_per_frame(torch, mb.llr, mb.ebn0_db, mb.llr_offset, S * beta, beta)}
+    for dt in ("i8", "f32"):
+        plan = mv.Plan(codes, frm, dt, 0, autotune=True, graph=True)
+        bits, metric, end = plan.empty_outputs(dev)
+        ms = _gpu_ms(torch, lambda: plan.decode(inputs[dt], bits, metric, end), 5)
+        peak = VALU16_PEAK_TOPS if dt == "i8" else VALU32_PEAK_TOPS
+        c4[dt] = {"ms": round(ms, 3), "gbit_s": round(nn.sum() / ms / 1e6, 2),
+                  "tops": round(ops / ms / 1e9, 2), "roofline_ms": round(ops / peak / 1e9, 3),
+                  "frac": round(ops / ms / 1e9 / peak, 3), "plan": plan.describe()}
+    out["mixed_10000"] = c4
+    del inputs
+    # backward: 2048 x 1024 bits, 2 dB, float32
+    b = make_uniform_batch(CODE_K7, 2048, 1024, 2.0, seed=5)
+    lf = torch.from_numpy(b.llr).to(dev)
+    plan = mv.Plan([CODE_K7], mv.uniform_frames(CODE_K7, 2048, 1024, True), "f32", 2)
+    bits, metric, end = plan.empty_outputs(dev)
+    g = torch.linspace(0.5, 1.5, 2048, device=dev)
+    grad = torch.empty_like(lf)
+    fwd = _gpu_ms(torch, lambda: plan.decode(lf, bits, metric, end), 20)
+    bwd = _gpu_ms(torch, lambda: plan.decode_grad(bits, g, grad), 20)
+    out["backward_2048x1024"] = {"forward_us": round(fwd * 1e3, 1),
+                                 "backward_us": round(bwd * 1e3, 1),
+                                 "backward_bytes": int(lf.numel() * 4 + bits.numel() * 4),
+                                 "backward_tb_s": round((lf.numel() * 4 + bits.numel() * 4)
+                                                        / bwd / 1e9, 2)}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -293,6 +404,8 @@ def main():
                      "work": "3 ops x 64 states x %d stages x %d frames per launch" % (S, N_FRAMES)},
         "variants": results,
     }
+    if args.configs:
+        line["configs"] = other_configs(torch, mv)
     if args.pcie and "i8r4" in plans:
         line["pcie_inclusive"] = pcie_pipeline(torch, mv, plans["i8r4"], llr_i8)
     if not args.no_cpu:

@@ -95,11 +95,14 @@ typedef struct {
   int32_t overlap;  /* stages of overlap on each side of a chunk, >= 0 */
   int32_t variant;  /* kernel variant for tuning and comparison; 0: default
                        (butterfly exchanges through DPP and permlane swaps;
-                       radix 4 with K = 5 or 7, beta = 2: two frames per
-                       register in packed 16-bit metrics); 1 and 2: radix-2
-                       forward exchanging through LDS swizzles (1: both
+                       radix 2 with K = 8 or 9: one frame per wavefront with
+                       2^(K-1)/64 states per lane in registers; radix 4
+                       with K = 5 or 7, beta = 2: two frames per register
+                       in packed 16-bit metrics); 1 and 2: radix-2 forward
+                       exchanging through LDS swizzles (1: both
                        previous-state metrics fetched, 2: one partner metric
-                       per lane), radix 4 through LDS, one frame per lane
+                       per lane; K = 8, 9: metrics exchanged through LDS
+                       every stage), radix 4 through LDS, one frame per lane
                        group and 32-bit metrics */
   uint32_t flags;   /* MIVIT_PLAN_* scheduling options, below */
   int32_t reserved[2]; /* must be zero */

@@ -75,6 +75,13 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError("libmivit.so is not built (%s); run __graft_entry__.build() or "
                            "python -m paper_2011_13579_amd.build" % path)
+    # The library takes torch's device pointers and streams, so it must bind to
+    # the HIP runtime torch ships: load torch first, then the library resolves
+    # its libamdhip64 to that copy instead of loading a second runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     lib.mivit_plan_create.restype = ctypes.c_int

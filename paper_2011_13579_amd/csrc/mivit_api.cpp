@@ -27,6 +27,9 @@ hipError_t launch_fwd_rot(int K, int beta, int dt, int mode, const DevCode* code
                           const Item* items, const int2* waves, int n_waves, const void* llr,
                           uint64_t* surv, void* metric, int32_t* end_out, int32_t* item_end,
                           int32_t* counter, int grid_limit, hipStream_t st);
+hipError_t launch_fwd_wide(int K, int beta, int dt, const DevCode* codes, const Item* items,
+                           int n_items, const void* llr, uint64_t* surv, void* metric,
+                           int32_t* end_out, int32_t* item_end, hipStream_t st);
 hipError_t launch_tb_seg(int layout, const DevCode* codes, const Item* items, int n_items,
                          const uint64_t* surv, const int32_t* item_end, uint32_t* bits,
                          int warm, hipStream_t st);
@@ -44,8 +47,14 @@ hipError_t launch_fill_random(void* p, int64_t n, int dt, uint32_t seed, hipStre
 using namespace mivit;
 
 // forward kernels and the survivor layouts they write
-enum : int { kKernGeneric2 = 0, kKernGeneric4 = 1, kKernRot2 = 2, kKernRot4P = 3 };
-enum : int { kLayoutNatR2 = 0, kLayoutNatR4 = 1, kLayoutRotR2 = 2, kLayoutRot4P = 3 };
+enum : int { kKernGeneric2 = 0, kKernGeneric4 = 1, kKernRot2 = 2, kKernRot4P = 3, kKernWide = 4 };
+enum : int {
+  kLayoutNatR2 = 0,
+  kLayoutNatR4 = 1,
+  kLayoutRotR2 = 2,
+  kLayoutRot4P = 3,
+  kLayoutRotNat = 4,  // per stage, 2^(K-1)/64 uint64 words of positions (wide kernel)
+};
 constexpr int kWarmStages = 64;  // speculative traceback warm-up
 // The packed radix-4 traceback runs one wavefront per frame pair, so one
 // mis-started segment (whose boundary state disagrees with the exact lane
@@ -129,9 +138,15 @@ struct mivit_plan {
 
 namespace {
 
+// Kernel launches report failure through hipGetLastError, which would also
+// return an unrelated earlier failure of the calling thread (another
+// library's, say): every entry point that launches clears it first.
+inline void clear_stale_error() { (void)hipGetLastError(); }
+
 struct DeviceGuard {
   int prev = -1;
   explicit DeviceGuard(int dev) {
+    clear_stale_error();
     if (hipGetDevice(&prev) != hipSuccess) prev = -1;
     if (prev != dev) (void)hipSetDevice(dev);
   }
@@ -254,7 +269,7 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
   if (ch.radix == 4)
     kern = (ch.variant == 0 && packed_ok(c) && i8) ? kKernRot4P : kKernGeneric4;
   else
-    kern = c.K <= 7 ? kKernRot2 : kKernGeneric2;
+    kern = c.K <= 7 ? kKernRot2 : (ch.variant == 0 ? kKernWide : kKernGeneric2);
   // longest first; items that can share a packed lane group next to each other
   std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) {
     if (a.n_stages != b.n_stages) return a.n_stages > b.n_stages;
@@ -265,6 +280,7 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
   g.kern = kern;
   g.layout = kern == kKernRot2      ? kLayoutRotR2
              : kern == kKernRot4P   ? kLayoutRot4P
+             : kern == kKernWide    ? kLayoutRotNat
              : kern == kKernGeneric4 ? kLayoutNatR4
                                      : kLayoutNatR2;
   g.nsl = nsl_of(c.K);
@@ -361,6 +377,9 @@ hipError_t part_forward(const mivit_plan* p, const Part& q, const void* llr, voi
       e = launch_fwd_r4p(g.K, p->d_codes, q.d_items, q.d_waves + g.wave_off, g.n_waves,
                          (const int8_t*)llr, q.d_surv, (int64_t*)metric, end_state,
                          q.d_item_end, counter, 0, st);
+    else if (g.kern == kKernWide)
+      e = launch_fwd_wide(g.K, g.beta, dt, p->d_codes, q.d_items + g.first, g.count, llr,
+                          q.d_surv, metric, end_state, q.d_item_end, st);
     else if (g.kern == kKernRot2)
       e = launch_fwd_rot(g.K, g.beta, dt, kRotMode[q.ch.variant], p->d_codes, q.d_items,
                          q.d_waves + g.wave_off, g.n_waves, llr, q.d_surv, metric, end_state,
@@ -429,12 +448,14 @@ std::vector<Choice> candidates(const mivit_code& c, int dtype, int radix) {
     if (c.K <= 7) add(2, 0, true);
     return out;
   }
+  // K >= 8: variant 0 holds the states in registers, 1 and 2 exchange through LDS
   if (radix != 4) {
     if (c.K <= 7) {
       for (int v = 0; v < 3; ++v) add(2, v, false);
       add(2, 0, true);
     } else {
-      add(2, 0, false);
+      add(2, 0, false);  // registers (wide kernel)
+      add(2, 1, false);  // LDS exchanges (generic kernel)
     }
   }
   if (i8 && radix != 2) {
@@ -473,6 +494,7 @@ const char* kern_name(int kern) {
     case kKernGeneric2: return "radix-2 generic";
     case kKernGeneric4: return "radix-4 generic";
     case kKernRot2: return "radix-2 rotating";
+    case kKernWide: return "radix-2 rotating, states in registers";
     case kKernRot4P: return "radix-4 packed two-frame";
   }
   return "?";
@@ -502,6 +524,7 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
   *out = nullptr;
   if (!codes || n_codes <= 0 || n_codes > 32767 || n_frames < 0 || (n_frames > 0 && !frames))
     return MIVIT_EINVAL;
+  clear_stale_error();
   mivit_opts o;
   std::memset(&o, 0, sizeof o);
   if (opts) o = *opts;
@@ -797,6 +820,7 @@ mivit_status mivit_quantize_i8(const float* llr, int8_t* q, int64_t n, float sca
                                void* stream) {
   if (n < 0 || (n > 0 && (!llr || !q))) return MIVIT_EINVAL;
   if (!(scale > 0.0f) || scale > 3.0e38f) return MIVIT_EINVAL;
+  clear_stale_error();
   hipError_t e = launch_quant(llr, q, n, scale, (hipStream_t)stream);
   return e == hipSuccess ? MIVIT_OK : MIVIT_EHIP;
 }

@@ -1,0 +1,398 @@
+// Radix-2 forward procedure for K = 8 and 9 (128 and 256 states): one
+// wavefront per frame, R = 2^(K-1)/64 states per lane held in registers.
+//
+// The state-to-position map rotates as in the K <= 7 kernel: at time t the
+// state s sits at position rotl_n(s, t mod n), n = K-1, and position p is
+// register p >> 6 of lane p & 63.  At stage t (phase q = t mod n) both
+// previous states (Eq. (radix2:S): 2f and 2f+1) of the state at position p
+// sit at the positions p with bit q cleared and set, and the new state stays
+// at p.  For q < 6 that is an exchange between lanes, done for each of the R
+// registers (DPP quad permutations for bits 0 and 1, ds_swizzle for bits 2
+// and 3, v_permlane16/32_swap for bits 4 and 5); for q >= 6 the two previous
+// states are two registers of the same lane and nothing moves.  The R
+// registers are independent dependency chains, which keeps a lone wavefront
+// busy.
+//
+// Branch metrics: Eq. (BM) for the even previous state on the new state's
+// input; by the corollary of §IV the odd previous state's branch has the
+// opposite value.  A per-wavefront LDS table holds the 2^beta pattern values
+// of each stage of a 32-stage block.
+//
+// Decisions: d = 1 when the odd previous state wins (strict, so a tie keeps
+// the even, lower-index one).  The ballot of register r at stage t is the
+// 64-bit word of positions 64r..64r+63; stage t's R words are stored
+// together (R uint64 per stage), position p at bit p mod 64 of word p / 64:
+// the natural layout with positions in place of states.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mivit_device.h"
+
+namespace mivit {
+
+namespace wide {
+
+template <int DT>
+struct Ty;
+template <>
+struct Ty<0> {
+  static constexpr bool kInt = false;
+  using T = float;
+  using In = float;
+  __device__ static float unreachable() { return -__builtin_inff(); }
+  __device__ static int bits(float x) { return __builtin_bit_cast(int, x); }
+  __device__ static float from(int x) { return __builtin_bit_cast(float, x); }
+};
+template <>
+struct Ty<1> {
+  static constexpr bool kInt = true;
+  using T = int;
+  using In = int8_t;
+  __device__ static int unreachable() { return -(1 << 29); }
+  __device__ static int bits(int x) { return x; }
+  __device__ static int from(int x) { return x; }
+};
+template <>
+struct Ty<2> : Ty<0> {
+  using In = _Float16;
+};
+
+__device__ __forceinline__ int parity(uint32_t x) { return __popc(x) & 1; }
+
+__device__ __forceinline__ int branch_out(const DevCode& c, int i, int u) {
+  const uint32_t reg = ((uint32_t)u << (c.K - 1)) | (uint32_t)i;
+  int w = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+    if (b < c.beta) w |= parity(c.gen[b] & reg) << b;
+  return w;
+}
+
+__device__ __forceinline__ int rotl(int x, int r, int n) {
+  return r == 0 ? x : (((x << r) | (x >> (n - r))) & ((1 << n) - 1));
+}
+__device__ __forceinline__ int rotr(int x, int r, int n) { return rotl(x, (n - r) % n, n); }
+
+// Metrics of the even and odd previous states across lane bit Q (Q < 6).
+template <int Q, int DT>
+__device__ __forceinline__ void pair_fetch(typename Ty<DT>::T x, typename Ty<DT>::T& e,
+                                           typename Ty<DT>::T& o) {
+  const int xi = Ty<DT>::bits(x);
+  int ei, oi;
+  if constexpr (Q == 0) {
+    ei = __builtin_amdgcn_mov_dpp(xi, 0xA0, 0xF, 0xF, true);  // quad_perm [0,0,2,2]
+    oi = __builtin_amdgcn_mov_dpp(xi, 0xF5, 0xF, 0xF, true);  // quad_perm [1,1,3,3]
+  } else if constexpr (Q == 1) {
+    ei = __builtin_amdgcn_mov_dpp(xi, 0x44, 0xF, 0xF, true);  // quad_perm [0,1,0,1]
+    oi = __builtin_amdgcn_mov_dpp(xi, 0xEE, 0xF, 0xF, true);  // quad_perm [2,3,2,3]
+  } else if constexpr (Q <= 3) {
+    // bit-mask mode within 32 lanes: lane' = (lane & and_mask) | or_mask
+    ei = __builtin_amdgcn_ds_swizzle(xi, 0x1F & ~(1 << Q));
+    oi = __builtin_amdgcn_ds_swizzle(xi, 0x1F | ((1 << Q) << 5));
+  } else if constexpr (Q == 4) {
+    // even rows of 16 to every row, odd rows to every row
+    const auto r = __builtin_amdgcn_permlane16_swap(xi, xi, false, false);
+    ei = r[0];
+    oi = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(xi, xi, false, false);
+    ei = r[0];
+    oi = r[1];
+  }
+  e = Ty<DT>::from(ei);
+  o = Ty<DT>::from(oi);
+}
+
+template <int DT, int R>
+struct Wave {
+  using T = typename Ty<DT>::T;
+  T pm[R];          // metric of the state at position 64 r + lane
+  uint32_t sv[2 * R];  // lane k: the 2R decision words of stage k of the block
+};
+
+// Add, compare, select for one position: the even and odd previous states'
+// metrics e and o, m the even one's branch metric.
+template <typename T>
+__device__ __forceinline__ T acs(T e, T o, T m, bool& d) {
+  const T ce = e + m;
+  const T co = o - m;
+  d = co > ce;
+  return d ? co : ce;
+}
+
+// One stage at phase Q; k is the stage's index in the block (the lane that
+// keeps its decision words), bm[r] the branch metric of position 64r + lane.
+template <int KM1, int DT, int R, int Q>
+__device__ __forceinline__ void stage(Wave<DT, R>& W, const typename Ty<DT>::T (&bm)[R], int k) {
+  using T = typename Ty<DT>::T;
+  T nv[R];
+  bool d[R];
+  if constexpr (Q < 6) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      T e, o;
+      pair_fetch<Q, DT>(W.pm[r], e, o);
+      nv[r] = acs(e, o, bm[r], d[r]);
+    }
+  } else {
+    constexpr int rb = 1 << (Q - 6);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int re = r & ~rb, ro = r | rb;
+      nv[r] = acs(W.pm[re], W.pm[ro], bm[r], d[r]);
+    }
+  }
+  const bool mine = (int)(threadIdx.x & 63) == k;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    W.pm[r] = nv[r];
+    const uint64_t m = __builtin_amdgcn_ballot_w64(d[r]);
+    if (mine) {
+      W.sv[2 * r] = (uint32_t)m;
+      W.sv[2 * r + 1] = (uint32_t)(m >> 32);
+    }
+  }
+}
+
+// Stages K0..31 of a full block starting at phase P0 (static phases).
+template <int KM1, int DT, int R, int NP, int P0, int K0>
+__device__ __forceinline__ void stages_full(Wave<DT, R>& W, const typename Ty<DT>::T* bmt,
+                                            const int (&pat)[KM1][R]) {
+  if constexpr (K0 < 32) {
+    constexpr int Q = (P0 + K0) % KM1;
+    typename Ty<DT>::T bm[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) bm[r] = bmt[K0 * NP + pat[Q][r]];
+    stage<KM1, DT, R, Q>(W, bm, K0);
+    stages_full<KM1, DT, R, NP, P0, K0 + 1>(W, bmt, pat);
+  }
+}
+
+// A stage whose phase is only known at run time (the last, partial block).
+template <int KM1, int DT, int R, int NP, int Q>
+__device__ __forceinline__ void stage_dyn(Wave<DT, R>& W, const typename Ty<DT>::T* bmrow,
+                                          const int (&pat)[KM1][R], int q, int k) {
+  if constexpr (Q < KM1) {
+    if (q == Q) {
+      typename Ty<DT>::T bm[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) bm[r] = bmrow[pat[Q][r]];
+      stage<KM1, DT, R, Q>(W, bm, k);
+    } else {
+      stage_dyn<KM1, DT, R, NP, Q + 1>(W, bmrow, pat, q, k);
+    }
+  }
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
+
+struct Ctx {
+  int64_t offset;  // integer metrics: total subtracted by renormalisation
+  int S, lane;
+};
+
+// One block of up to 32 stages starting at tb; BI its index in the period
+// of the phase pattern.  lv: this lane's soft values of stage tb + lane
+// (lanes < 32), replaced by those of the next block.
+template <int KM1, int DT, int BETA, int BI>
+__device__ __forceinline__ void one_block(Wave<DT, 1 << (KM1 - 6)>& W, Ctx& cx,
+                                          typename Ty<DT>::T* bmt,
+                                          const typename Ty<DT>::In* llr,
+                                          typename Ty<DT>::T (&lv)[BETA],
+                                          const int (&pat)[KM1][1 << (KM1 - 6)],
+                                          uint64_t* sv, int tb) {
+  using T = typename Ty<DT>::T;
+  constexpr int R = 1 << (KM1 - 6), NP = 1 << BETA;
+  const int n = min(32, cx.S - tb);
+  if (cx.lane < 32) {
+#pragma unroll
+    for (int p = 0; p < NP / 2; ++p) {
+      T v = (T)0;
+#pragma unroll
+      for (int b = 0; b < BETA; ++b) v += ((p >> b) & 1) ? -lv[b] : lv[b];
+      bmt[cx.lane * NP + p] = v;
+      bmt[cx.lane * NP + (NP - 1 - p)] = -v;
+    }
+  }
+  {
+    const int t = tb + 32 + cx.lane;
+    const bool ok = cx.lane < 32 && t < cx.S;
+#pragma unroll
+    for (int b = 0; b < BETA; ++b) lv[b] = ok ? (T)llr[(int64_t)t * BETA + b] : (T)0;
+  }
+  if constexpr (Ty<DT>::kInt) {
+    if (tb > 0) {
+      // renormalise by the metric of state 0 (always position 0: lane 0, register 0)
+      const T ref = __builtin_amdgcn_readfirstlane(W.pm[0]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) W.pm[r] -= ref;
+      cx.offset += ref;
+    }
+  }
+  wave_sync();
+  constexpr int P0 = (32 * BI) % KM1;
+  if (n == 32) {
+    stages_full<KM1, DT, R, NP, P0, 0>(W, bmt, pat);
+  } else {
+#pragma unroll 1
+    for (int k = 0; k < n; ++k) stage_dyn<KM1, DT, R, NP, 0>(W, bmt + k * NP, pat, (P0 + k) % KM1, k);
+  }
+  if (cx.lane < n) {
+    uint64_t* dst = sv + (int64_t)(tb + cx.lane) * R;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[r] = ((uint64_t)W.sv[2 * r + 1] << 32) | W.sv[2 * r];
+  }
+  wave_sync();
+}
+
+template <int KM1, int DT, int BETA, int BI, int NB>
+__device__ __forceinline__ void super_block(Wave<DT, 1 << (KM1 - 6)>& W, Ctx& cx,
+                                            typename Ty<DT>::T* bmt,
+                                            const typename Ty<DT>::In* llr,
+                                            typename Ty<DT>::T (&lv)[BETA],
+                                            const int (&pat)[KM1][1 << (KM1 - 6)],
+                                            uint64_t* sv, int t0) {
+  if constexpr (BI < NB) {
+    const int tb = t0 + 32 * BI;
+    if (tb < cx.S) {
+      one_block<KM1, DT, BETA, BI>(W, cx, bmt, llr, lv, pat, sv, tb);
+      super_block<KM1, DT, BETA, BI + 1, NB>(W, cx, bmt, llr, lv, pat, sv, t0);
+    }
+  }
+}
+
+constexpr int kWideWaves = 4;  // independent wavefronts (frames) per workgroup
+
+}  // namespace wide
+
+// One wavefront per item (frame or chunk window).
+template <int KM1, int DT, int BETA>
+__global__ __launch_bounds__(64 * wide::kWideWaves) void k_fwd_wide(
+    const DevCode* __restrict__ codes, const Item* __restrict__ items, int n_items,
+    const void* __restrict__ llr_v, uint64_t* __restrict__ surv, void* metric,
+    int32_t* end_out, int32_t* item_end) {
+  using namespace wide;
+  using T = typename Ty<DT>::T;
+  using In = typename Ty<DT>::In;
+  constexpr int R = 1 << (KM1 - 6), NS = 1 << KM1, NP = 1 << BETA;
+  constexpr int SUPER = 32 * KM1 / gcd_c(32, KM1);  // lcm(32, K-1)
+  __shared__ T bmt_all[kWideWaves][32 * NP];
+  __shared__ T xpm_all[kWideWaves][NS];
+  const int wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int item = blockIdx.x * kWideWaves + wid;
+  if (item >= n_items) return;  // no workgroup barriers: safe to leave
+  const Item it = items[item];
+  const DevCode c = codes[it.code];
+  const In* llr = (const In*)llr_v + it.llr_off;
+  uint64_t* sv = surv + it.surv_off;
+  T* bmt = bmt_all[wid];
+  T* xpm = xpm_all[wid];
+
+  // table offset (pattern) of position 64 r + lane at each phase: the even
+  // previous state's branch into the state held there after the stage
+  int pat[KM1][R];
+#pragma unroll
+  for (int q = 0; q < KM1; ++q) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j = rotr(64 * r + lane, (q + 1) % KM1, KM1);
+      pat[q][r] = branch_out(c, (j << 1) & (NS - 1), j >> (KM1 - 1));
+    }
+  }
+  Wave<DT, R> W;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    W.pm[r] = (it.start_known && (r != 0 || lane != 0)) ? Ty<DT>::unreachable() : (T)0;
+    W.sv[2 * r] = W.sv[2 * r + 1] = 0;
+  }
+  Ctx cx{0, it.n_stages, lane};
+  T lv[BETA];
+  {
+    const bool ok = lane < 32 && lane < cx.S;
+#pragma unroll
+    for (int b = 0; b < BETA; ++b) lv[b] = ok ? (T)llr[(int64_t)lane * BETA + b] : (T)0;
+  }
+  for (int t0 = 0; t0 < cx.S; t0 += SUPER)
+    super_block<KM1, DT, BETA, 0, SUPER / 32>(W, cx, bmt, llr, lv, pat, sv, t0);
+
+  // final metrics: position p holds state rotr(p, S mod (K-1)); best state
+  // with ties to the lowest index
+  const int S = cx.S;
+  T bv = Ty<DT>::unreachable();
+  int bs = NS;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int s = rotr(64 * r + lane, S % KM1, KM1);
+    xpm[s] = W.pm[r];
+    if (W.pm[r] > bv || (W.pm[r] == bv && s < bs)) {
+      bv = W.pm[r];
+      bs = s;
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const T ov = Ty<DT>::from(__shfl_xor(Ty<DT>::bits(bv), o));
+    const int os = __shfl_xor(bs, o);
+    if (ov > bv || (ov == bv && os < bs)) {
+      bv = ov;
+      bs = os;
+    }
+  }
+  wave_sync();
+  if (lane == 0) {
+    const int js = it.end_state >= 0 ? it.end_state : bs;
+    const T vj = xpm[js];
+    item_end[it.slot] = js;
+    if (it.frame >= 0) {
+      if (end_out) end_out[it.frame] = js;
+      if (metric) {
+        if constexpr (Ty<DT>::kInt)
+          ((int64_t*)metric)[it.frame] = (int64_t)vj + cx.offset;
+        else
+          ((float*)metric)[it.frame] = vj;
+      }
+    }
+  }
+}
+
+hipError_t launch_fwd_wide(int K, int beta, int dt, const DevCode* codes, const Item* items,
+                           int n_items, const void* llr, uint64_t* surv, void* metric,
+                           int32_t* end_out, int32_t* item_end, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  const dim3 grid((n_items + wide::kWideWaves - 1) / wide::kWideWaves), block(64 * wide::kWideWaves);
+#define MV_WIDE(KM1, D, B)                                                                  \
+  hipLaunchKernelGGL((k_fwd_wide<KM1, D, B>), grid, block, 0, st, codes, items, n_items, llr, \
+                     surv, metric, end_out, item_end);                                        \
+  return hipGetLastError()
+#define MV_WIDE_B(KM1, D)             \
+  switch (beta) {                     \
+    case 2: MV_WIDE(KM1, D, 2);       \
+    case 3: MV_WIDE(KM1, D, 3);       \
+    case 4: MV_WIDE(KM1, D, 4);       \
+    default: return hipErrorInvalidValue; \
+  }
+#define MV_WIDE_D(KM1)                \
+  switch (dt) {                       \
+    case 0: MV_WIDE_B(KM1, 0);        \
+    case 1: MV_WIDE_B(KM1, 1);        \
+    case 2: MV_WIDE_B(KM1, 2);        \
+    default: return hipErrorInvalidValue; \
+  }
+  switch (K) {
+    case 8: MV_WIDE_D(7);
+    case 9: MV_WIDE_D(8);
+    default: return hipErrorInvalidValue;
+  }
+#undef MV_WIDE_D
+#undef MV_WIDE_B
+#undef MV_WIDE
+}
+
+}  // namespace mivit

@@ -257,12 +257,14 @@ def test_quantizer_exact():
 @pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("dtype", ["f32", "i8"])
 def test_kernel_variants_agree(dtype, variant):
-    """Every radix-2 forward variant gives the oracle's result (K=3..7)."""
+    """Every radix-2 forward variant gives the oracle's result (K=3..9; for
+    K=8, 9 variant 0 holds the states in registers, 1 and 2 use LDS)."""
     from workload import int8_scale_for
     for code in (Code.from_octal(3, ["7", "5"]), Code.from_octal(4, ["17", "13"]), CODE_K5,
-                 Code.from_octal(6, ["65", "57"]), CODE_K7):
+                 Code.from_octal(6, ["65", "57"]), CODE_K7, Code.from_octal(8, ["247", "371"]),
+                 CODE_K9):
         b = make_uniform_batch(code, 16, 700, 1.0, seed=44)
-        llr = b.llr if dtype == "f32" else oracle.quantize_i8(b.llr, int8_scale_for(1.0, 2))
+        llr = b.llr if dtype == "f32" else oracle.quantize_i8(b.llr, int8_scale_for(1.0, code.beta))
         fr = mv.uniform_frames(code, 16, 700, True)
         plan = mv.Plan([code], fr, dtype, 2, variant=variant)
         words, metric, _ = plan.decode(torch.from_numpy(llr).to(DEV))
@@ -271,6 +273,49 @@ def test_kernel_variants_agree(dtype, variant):
         ob, om, _ = oracle.decode_uniform(code, llr, 700, True, oracle.F32 if dtype == "f32" else oracle.I64)
         np.testing.assert_array_equal(bits, ob)
         np.testing.assert_array_equal(metric.cpu().numpy()[:16], om)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "i8", "f16"])
+@pytest.mark.parametrize("code", [Code.from_octal(8, ["247", "371"]), CODE_K9], ids=cid)
+def test_wide_kernel_long_and_ragged(code, dtype):
+    """K = 8, 9 in registers (one frame per wavefront): frames of 1 to 5000
+    stages (partial last blocks, every phase), known and unknown starts, best
+    and zero ends, equal to the oracle; int8 frames cross many range-control
+    steps."""
+    rng = np.random.default_rng(700 + code.K)
+    lens = [1, 2, 7, 8, 9, 31, 32, 33, 255, 1000, 4999]
+    cases = [(S, sk, ez) for S in lens for sk in (0, 1) for ez in (0, 1)
+             if not (ez and S < code.K - 1)]
+    fr = np.zeros(len(cases), mv.FRAME_DTYPE)
+    ofr = np.zeros(len(cases), oracle.FRAME_DTYPE)
+    off = nb = 0
+    for k, (S, sk, ez) in enumerate(cases):
+        n_out = S - (code.K - 1) if ez else S
+        flags = (mv.MIVIT_START_KNOWN if sk else 0) | (mv.MIVIT_END_ZERO if ez else 0)
+        fr[k] = (off, nb, S, 0, n_out, 0, flags)
+        ofr[k] = (off, nb, S, 0, n_out, sk, 0 if ez else -1, 0)
+        off += code.beta * S
+        nb += ((n_out + 31) // 32) * 32
+    if dtype == "i8":
+        llr = np.where(rng.random(off) < 0.05, rng.integers(-128, 128, off),
+                       rng.integers(-9, 10, off)).astype(np.int8)
+        ref, mode = llr, oracle.I64
+    else:
+        llr = rng.normal(0, 2.5, off).astype(np.float32 if dtype == "f32" else np.float16)
+        ref, mode = llr.astype(np.float32), oracle.F32
+    print("wide", cid(code), dtype, flush=True)
+    plan = mv.Plan([code], fr, dtype, 2)
+    assert "registers" in plan.describe()
+    t = torch.from_numpy(llr).to(DEV)
+    w, m, e = plan.decode(t)
+    torch.cuda.synchronize()
+    bits = mv.unpack_bits(w.cpu().numpy()[: nb // 32], nb)
+    ob, om, oend, _ = oracle.decode_frames([code], ofr, ref, mode, nb)
+    np.testing.assert_array_equal(e.cpu().numpy()[: len(fr)], oend)
+    np.testing.assert_array_equal(m.cpu().numpy()[: len(fr)], om)
+    for k in range(len(fr)):
+        s, n = int(ofr[k]["bit_offset"]), int(ofr[k]["n_out"])
+        np.testing.assert_array_equal(bits[s:s + n], ob[s:s + n])
 
 
 def test_determinism():
@@ -677,3 +722,20 @@ def test_pipeline_matches_decode(depth):
         with pytest.raises(ValueError):
             pipe.run(h_llr, bits[:-1], None, nb)
         pipe.close()
+
+
+def test_library_loaded_before_torch_shares_its_runtime():
+    """Loading the binding first in a fresh process (before any torch import)
+    still binds the library to torch's HIP runtime: a launch succeeds."""
+    import subprocess
+    import sys
+    import os
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2011_13579_amd import _capi; _capi.load()\n"
+            "import torch, paper_2011_13579_amd as mv\n"
+            "q = mv.quantize_i8(torch.ones(4099, device='cuda:0'), 3.0)\n"
+            "torch.cuda.synchronize(); print(int(q.sum()))\n") % os.path.dirname(
+                os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.strip().endswith(str(3 * 4099))
