@@ -395,31 +395,43 @@ __global__ __launch_bounds__(64) void k_tb_r4(const DevCode* __restrict__ codes,
 // ---------------------------------------------------------------------------
 // Backward of the best path metric: grad = g * (-1)^{coded bit of the
 // decoded path}, the decoded bits re-encoded with the encoder of §II-A.
-// grid: x over stages (256 per block), y over frames.
+// grid: x over chunks of kGradChunk stages, y over frames; each thread
+// takes every 256th stage of its block's chunk.
 // ---------------------------------------------------------------------------
+constexpr int kGradChunk = 512;
+
 __global__ __launch_bounds__(256) void k_grad(const DevCode* __restrict__ codes,
                                               const GradFrame* __restrict__ frames,
                                               const uint32_t* __restrict__ bits,
                                               const float* __restrict__ gm,
                                               float* __restrict__ grad) {
   const GradFrame fr = frames[blockIdx.y];
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= fr.n_stages) return;
   const DevCode c = codes[fr.code];
   const int K = c.K;
-  uint32_t reg = 0;
-  for (int k = 0; k < K; ++k) {
-    const int tt = t - (K - 1 - k);  // register bit k holds the input K-1-k stages back
-    int u = 0;
-    if (tt >= 0 && tt < fr.n_out) {
-      const int64_t bi = fr.bit_off + tt;
-      u = (int)((bits[bi >> 5] >> (bi & 31)) & 1);
-    }
-    reg |= (uint32_t)u << k;
-  }
   const float g = gm[blockIdx.y];
-  float* dst = grad + fr.llr_off + (int64_t)t * c.beta;
-  for (int b = 0; b < c.beta; ++b) dst[b] = parity32(c.gen[b] & reg) ? -g : g;
+  const int t_end = min(fr.n_stages, (int)(blockIdx.x + 1) * kGradChunk);
+  for (int t = blockIdx.x * kGradChunk + threadIdx.x; t < t_end; t += 256) {
+    // register bit k holds the input K-1-k stages back, i.e. the input of
+    // stage lo + k; inputs before stage 0 and from stage n_out on are zero.
+    // The window [max(lo, 0), min(t, n_out - 1)] spans at most two words.
+    const int lo = t - (K - 1);
+    const int a = lo > 0 ? lo : 0;
+    const int e = t < fr.n_out - 1 ? t : fr.n_out - 1;
+    uint32_t reg = 0;
+    if (a <= e) {
+      const int64_t ba = fr.bit_off + a;
+      const int sh = (int)(ba & 31);
+      const uint32_t w0 = bits[ba >> 5];
+      const uint32_t w1 = sh + (e - a) >= 32 ? bits[(ba >> 5) + 1] : 0u;
+      uint64_t v = ((((uint64_t)w1) << 32) | w0) >> sh;  // bit 0: the input of stage a
+      v &= (1ull << (e - a + 1)) - 1;
+      reg = (uint32_t)(v << (a - lo));
+    }
+    float* dst = grad + fr.llr_off + (int64_t)t * c.beta;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (b < c.beta) dst[b] = parity32(c.gen[b] & reg) ? -g : g;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -514,7 +526,7 @@ hipError_t launch_grad(const DevCode* codes, const GradFrame* frames, int n_fram
   if (n_frames <= 0 || max_stages <= 0) return hipSuccess;
   for (int f0 = 0; f0 < n_frames; f0 += 65535) {
     const int nf = n_frames - f0 < 65535 ? n_frames - f0 : 65535;
-    dim3 g((max_stages + 255) / 256, nf), b(256);
+    dim3 g((max_stages + kGradChunk - 1) / kGradChunk, nf), b(256);
     hipLaunchKernelGGL(k_grad, g, b, 0, st, codes, frames + f0, bits, gm + f0, grad);
   }
   return hipGetLastError();

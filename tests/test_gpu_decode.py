@@ -739,3 +739,25 @@ def test_library_loaded_before_torch_shares_its_runtime():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stderr[-2000:]
     assert out.stdout.strip().endswith(str(3 * 4099))
+
+
+def test_gradient_mixed_codes():
+    """Backward through a mixed-code plan (K=5, 7 and 9 r1/3 frames of uneven
+    length): every frame's gradient equals the oracle's g * (-1)^c of its
+    decoded codeword, frame starts and tails included."""
+    codes, fr, ofr, llr, n_bits = _mixed("f32", F=90, seed=31)
+    plan = mv.Plan(codes, fr, "f32", 2)
+    t = torch.from_numpy(llr).to(DEV)
+    bits_t, metric_t, end_t = plan.decode(t)
+    g = torch.linspace(0.25, 2.0, len(fr), device=DEV)
+    grad = torch.full_like(t, 7.0)
+    plan.decode_grad(bits_t, g, grad)
+    torch.cuda.synchronize()
+    bits = mv.unpack_bits(bits_t.cpu().numpy()[: n_bits // 32], n_bits)
+    gr, gn = grad.cpu().numpy(), g.cpu().numpy()
+    for k in range(len(fr)):
+        code = codes[int(fr[k]["code"])]
+        a, n = int(fr[k]["bit_offset"]), int(fr[k]["n_out"])
+        lo, S = int(fr[k]["llr_offset"]), int(fr[k]["n_stages"])
+        ref = oracle.metric_grad(code, bits[a:a + n], gn[k])
+        np.testing.assert_array_equal(gr[lo:lo + S * code.beta], ref.astype(np.float32))
