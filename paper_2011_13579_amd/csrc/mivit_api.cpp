@@ -53,7 +53,7 @@ enum : int {
   kLayoutNatR4 = 1,
   kLayoutRotR2 = 2,
   kLayoutRot4P = 3,
-  kLayoutRotNat = 4,  // per stage, 2^(K-1)/64 uint64 words of positions (wide kernel)
+  kLayoutRotByte = 4,  // per 8 stages, 2^(K-1) bytes of positions (wide kernel)
 };
 constexpr int kWarmStages = 64;  // speculative traceback warm-up
 // The packed radix-4 traceback runs one wavefront per frame pair, so one
@@ -280,7 +280,7 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
   g.kern = kern;
   g.layout = kern == kKernRot2      ? kLayoutRotR2
              : kern == kKernRot4P   ? kLayoutRot4P
-             : kern == kKernWide    ? kLayoutRotNat
+             : kern == kKernWide    ? kLayoutRotByte
              : kern == kKernGeneric4 ? kLayoutNatR4
                                      : kLayoutNatR2;
   g.nsl = nsl_of(c.K);
@@ -339,6 +339,8 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
       words = (int64_t)((it.n_stages + 31) / 32) * (1 << (c.K - 1)) / 2;
     else if (kern == kKernRot4P)  // 2^(K-1) 32-bit words per 8 iterations
       words = (int64_t)((it.n_stages / 2 + 7) / 8) * (1 << (c.K - 1)) / 2;
+    else if (kern == kKernWide)  // 2^(K-1) bytes per 8 stages, whole 32-stage blocks
+      words = (int64_t)((it.n_stages + 31) / 32) * (1 << (c.K - 1)) / 2;
     else
       words = (int64_t)it.n_stages * words_per_stage(c.K);
     words_total += (words + 1) & ~(int64_t)1;

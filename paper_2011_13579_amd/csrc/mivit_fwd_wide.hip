@@ -19,10 +19,11 @@
 // of each stage of a 32-stage block.
 //
 // Decisions: d = 1 when the odd previous state wins (strict, so a tie keeps
-// the even, lower-index one).  The ballot of register r at stage t is the
-// 64-bit word of positions 64r..64r+63; stage t's R words are stored
-// together (R uint64 per stage), position p at bit p mod 64 of word p / 64:
-// the natural layout with positions in place of states.
+// the even, lower-index one).  Every position shifts its decision into a
+// 32-bit word; every 32 stages its four bytes go out: per group of 8 stages, 2^(K-1) bytes, byte p
+// holding position p's decisions with stage 8g + i at bit 7 - i.  A group of
+// 8 stages is then 64 (K = 9) or 32 (K = 8) words, the unit the traceback
+// stages through LDS.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -107,8 +108,9 @@ template <int DT, int R>
 struct Wave {
   using T = typename Ty<DT>::T;
   T pm[R];          // metric of the state at position 64 r + lane
-  uint32_t sv[2 * R];  // lane k: the 2R decision words of stage k of the block
+  uint32_t acc[R];  // decisions of position 64 r + lane in the current block
 };
+
 
 // Add, compare, select for one position: the even and odd previous states'
 // metrics e and o, m the even one's branch metric.
@@ -120,10 +122,9 @@ __device__ __forceinline__ T acs(T e, T o, T m, bool& d) {
   return d ? co : ce;
 }
 
-// One stage at phase Q; k is the stage's index in the block (the lane that
-// keeps its decision words), bm[r] the branch metric of position 64r + lane.
+// One stage at phase Q; bm[r] the branch metric of position 64r + lane.
 template <int KM1, int DT, int R, int Q>
-__device__ __forceinline__ void stage(Wave<DT, R>& W, const typename Ty<DT>::T (&bm)[R], int k) {
+__device__ __forceinline__ void stage(Wave<DT, R>& W, const typename Ty<DT>::T (&bm)[R]) {
   using T = typename Ty<DT>::T;
   T nv[R];
   bool d[R];
@@ -142,15 +143,10 @@ __device__ __forceinline__ void stage(Wave<DT, R>& W, const typename Ty<DT>::T (
       nv[r] = acs(W.pm[re], W.pm[ro], bm[r], d[r]);
     }
   }
-  const bool mine = (int)(threadIdx.x & 63) == k;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     W.pm[r] = nv[r];
-    const uint64_t m = __builtin_amdgcn_ballot_w64(d[r]);
-    if (mine) {
-      W.sv[2 * r] = (uint32_t)m;
-      W.sv[2 * r + 1] = (uint32_t)(m >> 32);
-    }
+    W.acc[r] = 2u * W.acc[r] + (d[r] ? 1u : 0u);
   }
 }
 
@@ -163,7 +159,7 @@ __device__ __forceinline__ void stages_full(Wave<DT, R>& W, const typename Ty<DT
     typename Ty<DT>::T bm[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) bm[r] = bmt[K0 * NP + pat[Q][r]];
-    stage<KM1, DT, R, Q>(W, bm, K0);
+    stage<KM1, DT, R, Q>(W, bm);
     stages_full<KM1, DT, R, NP, P0, K0 + 1>(W, bmt, pat);
   }
 }
@@ -171,15 +167,15 @@ __device__ __forceinline__ void stages_full(Wave<DT, R>& W, const typename Ty<DT
 // A stage whose phase is only known at run time (the last, partial block).
 template <int KM1, int DT, int R, int NP, int Q>
 __device__ __forceinline__ void stage_dyn(Wave<DT, R>& W, const typename Ty<DT>::T* bmrow,
-                                          const int (&pat)[KM1][R], int q, int k) {
+                                          const int (&pat)[KM1][R], int q) {
   if constexpr (Q < KM1) {
     if (q == Q) {
       typename Ty<DT>::T bm[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) bm[r] = bmrow[pat[Q][r]];
-      stage<KM1, DT, R, Q>(W, bm, k);
+      stage<KM1, DT, R, Q>(W, bm);
     } else {
-      stage_dyn<KM1, DT, R, NP, Q + 1>(W, bmrow, pat, q, k);
+      stage_dyn<KM1, DT, R, NP, Q + 1>(W, bmrow, pat, q);
     }
   }
 }
@@ -241,12 +237,19 @@ __device__ __forceinline__ void one_block(Wave<DT, 1 << (KM1 - 6)>& W, Ctx& cx,
     stages_full<KM1, DT, R, NP, P0, 0>(W, bmt, pat);
   } else {
 #pragma unroll 1
-    for (int k = 0; k < n; ++k) stage_dyn<KM1, DT, R, NP, 0>(W, bmt + k * NP, pat, (P0 + k) % KM1, k);
+    for (int k = 0; k < n; ++k) stage_dyn<KM1, DT, R, NP, 0>(W, bmt + k * NP, pat, (P0 + k) % KM1);
   }
-  if (cx.lane < n) {
-    uint64_t* dst = sv + (int64_t)(tb + cx.lane) * R;
+  // four groups of 8 stages: group g of the block is byte 3 - g of acc
+  {
+    constexpr int NS = 1 << KM1;
+    uint8_t* dst = (uint8_t*)sv + (int64_t)(tb >> 3) * NS + cx.lane;
 #pragma unroll
-    for (int r = 0; r < R; ++r) dst[r] = ((uint64_t)W.sv[2 * r + 1] << 32) | W.sv[2 * r];
+    for (int r = 0; r < R; ++r) {
+      const uint32_t a = n == 32 ? W.acc[r] : W.acc[r] << (32 - n);
+#pragma unroll
+      for (int g = 0; g < 4; ++g) dst[g * NS + 64 * r] = (uint8_t)(a >> (24 - 8 * g));
+      W.acc[r] = 0;
+    }
   }
   wave_sync();
 }
@@ -310,7 +313,7 @@ __global__ __launch_bounds__(64 * wide::kWideWaves) void k_fwd_wide(
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     W.pm[r] = (it.start_known && (r != 0 || lane != 0)) ? Ty<DT>::unreachable() : (T)0;
-    W.sv[2 * r] = W.sv[2 * r + 1] = 0;
+    W.acc[r] = 0;
   }
   Ctx cx{0, it.n_stages, lane};
   T lv[BETA];

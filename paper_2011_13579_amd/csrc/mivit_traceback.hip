@@ -31,8 +31,9 @@ enum : int {
   kLayoutNatR2 = 0,  // per stage, ceil(NS/64) uint64 words, bit j = decision of state j
   kLayoutNatR4 = 1,  // same words; stage pairs (t, t+1) from 0 hold bits 0 and 1 of y
   kLayoutRotR2 = 2,  // per 32 stages, NS uint32 words; rotating state-to-word map
-  kLayoutRotNat = 4, // per stage, NS/64 uint64 words, bit p = decision at position p,
-                     // state j after stage t at position rotl(j, (t+1) mod (K-1))
+  kLayoutRotByte = 4,  // per 8 stages, NS bytes: byte p = decisions at position p (stage
+                       // 8g + i at bit 7 - i); the state j after stage t is at position
+                       // rotl(j, (t+1) mod (K-1))
 };
 
 template <int LAYOUT>
@@ -45,6 +46,9 @@ struct TbGeom {
     if (LAYOUT == kLayoutRotR2) {
       SB = 32;
       WB = NS;
+    } else if (LAYOUT == kLayoutRotByte) {
+      SB = 2048 / NS;  // 64 words of NS / 4 words per 8 stages
+      WB = 64;
     } else {
       SB = 32 / W;
       WB = 64;
@@ -150,10 +154,10 @@ __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_
           if (LAYOUT == kLayoutRotR2) {
             const int w = rotl_bits(j, (t + 1) % g.KM1, g.KM1);
             d = (word_at(cur, w, lane) >> (31 - (t & 31))) & 1;
-          } else if (LAYOUT == kLayoutRotNat) {
+          } else if (LAYOUT == kLayoutRotByte) {
             const int p = rotl_bits(j, (t + 1) % g.KM1, g.KM1);
-            const int w = (t % SB) * 2 * g.W + (p >> 5);
-            d = (word_at(cur, w, lane) >> (p & 31)) & 1;
+            const int w = ((t % SB) >> 3) * (g.NS >> 2) + (p >> 2);
+            d = (word_at(cur, w, lane) >> (8 * (p & 3) + 7 - (t & 7))) & 1;
           } else {
             const int w = (t % SB) * 2 * g.W + (j >> 5);
             d = (word_at(cur, w, lane) >> (j & 31)) & 1;
@@ -238,8 +242,8 @@ hipError_t launch_tb_seg(int layout, const DevCode* codes, const Item* items, in
       hipLaunchKernelGGL(k_tb_seg<kLayoutRotR2>, grid, block, 0, st, codes, items, surv,
                          item_end, bits, warm);
       break;
-    case kLayoutRotNat:
-      hipLaunchKernelGGL(k_tb_seg<kLayoutRotNat>, grid, block, 0, st, codes, items, surv,
+    case kLayoutRotByte:
+      hipLaunchKernelGGL(k_tb_seg<kLayoutRotByte>, grid, block, 0, st, codes, items, surv,
                          item_end, bits, warm);
       break;
     default:
