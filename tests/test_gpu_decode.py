@@ -128,7 +128,7 @@ def test_free_end_and_unknown_start(code, dtype, radix):
     """Frames with a best-state end and with an unknown start (all-zero
     initial metrics), mixed lengths in one plan."""
     rng = np.random.default_rng(5 + code.K)
-    lens = [1, 2, 5, 63, 64, 65, 300, 1000]
+    lens = [0, 1, 2, 5, 63, 64, 65, 300, 1000]  # 0: an empty frame (metric 0, state 0)
     fr = np.zeros(len(lens) * 2, mv.FRAME_DTYPE)
     ofr = np.zeros(len(lens) * 2, oracle.FRAME_DTYPE)
     off = 0
@@ -283,7 +283,7 @@ def test_wide_kernel_long_and_ragged(code, dtype):
     and zero ends, equal to the oracle; int8 frames cross many range-control
     steps."""
     rng = np.random.default_rng(700 + code.K)
-    lens = [1, 2, 7, 8, 9, 31, 32, 33, 255, 1000, 4999]
+    lens = [0, 1, 2, 7, 8, 9, 31, 32, 33, 255, 1000, 4999]
     cases = [(S, sk, ez) for S in lens for sk in (0, 1) for ez in (0, 1)
              if not (ez and S < code.K - 1)]
     fr = np.zeros(len(cases), mv.FRAME_DTYPE)
@@ -602,7 +602,7 @@ def test_r4_packed_varied_frames():
     and even, known and unknown starts, zero and best ends, in wavefront
     entries holding one or both frames of a pair."""
     rng = np.random.default_rng(4242)
-    lens = [1, 2, 3, 5, 17, 64, 65, 127, 300, 1001, 4093, 9001]
+    lens = [0, 1, 2, 3, 5, 17, 64, 65, 127, 300, 1001, 4093, 9001]
     for copies in (1, 3):
         cases = [(S, sk, ez) for S in lens for sk in (0, 1) for ez in (0, 1)
                  if not (ez and S < 7)]
