@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--ebn0", type=float, default=3.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--ber", action="store_true", help="run the equal-BER sweep")
-    ap.add_argument("--variants", default="i8r4,f32r2,f16r2,i8r2")
+    ap.add_argument("--variants", default="i8r4,f32r2,f16r2,i8r2,i8r8")
     ap.add_argument("--configs", action="store_true",
                     help="also measure the single-frame, stream, mixed-batch and backward workloads")
     ap.add_argument("--pcie", action="store_true",
@@ -362,7 +362,7 @@ def main():
     for v in args.variants.split(","):
         base, _, kv = v.partition(":")
         dt, radix = {"i8r4": ("i8", 4), "f32r2": ("f32", 2), "f16r2": ("f16", 2),
-                     "i8r2": ("i8", 2)}[base]
+                     "i8r2": ("i8", 2), "i8r8": ("i8", 8)}[base]
         plans[v] = mv.Plan([code], frames, dt, radix, variant=int(kv[1:]) if kv else 0)
         llr = {"i8": llr_i8, "f32": llr_f32, "f16": llr_f16}[dt]
         ms, fwd, tb, bits, _ = time_variant(torch, mv, plans[v], llr, args.steps, args.warmup)

@@ -88,7 +88,10 @@ typedef struct {
 /* Plan options.  Zero-initialised means: choose automatically. */
 typedef struct {
   int32_t dtype;    /* mivit_dtype of every frame's soft values */
-  int32_t radix;    /* 0: choose; 2: radix-2; 4: radix-4 (int8 only) */
+  int32_t radix;    /* 0: choose; 2: radix-2; 4: radix-4 (int8 only);
+                       8: radix-8, three stages per iteration (the
+                       radix-2^rho form of §VIII with rho = 3; int8 only,
+                       every code K >= 4, variant 0) */
   int32_t chunk;    /* >0: split every frame longer than chunk stages into
                        windows of chunk core stages plus 'overlap' stages on
                        each side (§III); 0: decode whole frames */
@@ -124,10 +127,12 @@ typedef struct {
  *   MIVIT_PLAN_AUTOTUNE    plan creation times every valid kernel choice of
  *                          each code's part (radix, exchange variant,
  *                          persistent launch; radix 4 only when 'radix' is 0
- *                          or 4, radix 2 only when it is 0 or 2) on
+ *                          or 4, radix 8 only when it is 0 or 8, radix 2
+ *                          only when it is 0 or 2) on
  *                          synthetic soft values with the plan's frame
  *                          shapes and keeps the fastest.  All choices give
- *                          identical results.  Uses extra device memory
+ *                          identical results (for int8, radices 2, 4 and 8
+ *                          the same path, ties included).  Uses extra device memory
  *                          for the plan's soft-value extent while creating. */
 #define MIVIT_PLAN_GRAPH 1u
 #define MIVIT_PLAN_AUTOTUNE 2u
@@ -141,7 +146,9 @@ typedef struct mivit_plan mivit_plan;
  * per frame or window, §III) on the current device.  codes/frames/opts are
  * host pointers and are copied.  On success *plan owns device memory until
  * mivit_plan_destroy.  Errors: MIVIT_EINVAL (bad code or frame, overlapping
- * or unaligned outputs, radix 4 with float32), MIVIT_EUNSUPPORTED,
+ * or unaligned outputs, radix 4 or 8 with float soft values),
+ * MIVIT_EUNSUPPORTED (among others: a code without both end taps, radix 8
+ * with K = 3 or a nonzero variant, float16 with a nonzero variant),
  * MIVIT_ENOMEM, MIVIT_EHIP. */
 mivit_status mivit_plan_create(mivit_plan** plan, const mivit_code* codes, int32_t n_codes,
                                const mivit_frame* frames, int32_t n_frames,

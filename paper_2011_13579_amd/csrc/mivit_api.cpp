@@ -47,13 +47,21 @@ hipError_t launch_fill_random(void* p, int64_t n, int dt, uint32_t seed, hipStre
 using namespace mivit;
 
 // forward kernels and the survivor layouts they write
-enum : int { kKernGeneric2 = 0, kKernGeneric4 = 1, kKernRot2 = 2, kKernRot4P = 3, kKernWide = 4 };
+enum : int {
+  kKernGeneric2 = 0,
+  kKernGeneric4 = 1,
+  kKernRot2 = 2,
+  kKernRot4P = 3,
+  kKernWide = 4,
+  kKernGeneric8 = 5,
+};
 enum : int {
   kLayoutNatR2 = 0,
   kLayoutNatR4 = 1,
   kLayoutRotR2 = 2,
   kLayoutRot4P = 3,
   kLayoutRotByte = 4,  // per 8 stages, 2^(K-1) bytes of positions (wide kernel)
+  kLayoutNatR8 = 5,
 };
 constexpr int kWarmStages = 64;  // speculative traceback warm-up
 // The packed radix-4 traceback runs one wavefront per frame pair, so one
@@ -266,7 +274,9 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
   const mivit_code& c = codes[code];
   const bool i8 = dtype == MIVIT_I8;
   int kern;
-  if (ch.radix == 4)
+  if (ch.radix == 8)
+    kern = kKernGeneric8;
+  else if (ch.radix == 4)
     kern = (ch.variant == 0 && packed_ok(c) && i8) ? kKernRot4P : kKernGeneric4;
   else
     kern = c.K <= 7 ? kKernRot2 : (ch.variant == 0 ? kKernWide : kKernGeneric2);
@@ -282,6 +292,7 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
              : kern == kKernRot4P   ? kLayoutRot4P
              : kern == kKernWide    ? kLayoutRotByte
              : kern == kKernGeneric4 ? kLayoutNatR4
+             : kern == kKernGeneric8 ? kLayoutNatR8
                                      : kLayoutNatR2;
   g.nsl = nsl_of(c.K);
   g.K = c.K;
@@ -387,7 +398,8 @@ hipError_t part_forward(const mivit_plan* p, const Part& q, const void* llr, voi
                          q.d_waves + g.wave_off, g.n_waves, llr, q.d_surv, metric, end_state,
                          q.d_item_end, counter, 0, st);
     else
-      e = launch_fwd(g.kern == kKernGeneric4 ? 4 : 2, g.nsl, dt, p->d_codes,
+      e = launch_fwd(g.kern == kKernGeneric4 ? 4 : g.kern == kKernGeneric8 ? 8 : 2, g.nsl, dt,
+                     p->d_codes,
                      q.d_items + g.first, g.count, llr, q.d_surv, metric, end_state,
                      q.d_item_end, st);
     if (e != hipSuccess) return e;
@@ -451,7 +463,7 @@ std::vector<Choice> candidates(const mivit_code& c, int dtype, int radix) {
     return out;
   }
   // K >= 8: variant 0 holds the states in registers, 1 and 2 exchange through LDS
-  if (radix != 4) {
+  if (radix == 0 || radix == 2) {
     if (c.K <= 7) {
       for (int v = 0; v < 3; ++v) add(2, v, false);
       add(2, 0, true);
@@ -460,13 +472,14 @@ std::vector<Choice> candidates(const mivit_code& c, int dtype, int radix) {
       add(2, 1, false);  // LDS exchanges (generic kernel)
     }
   }
-  if (i8 && radix != 2) {
+  if (i8 && (radix == 0 || radix == 4)) {
     if (packed_ok(c)) {
       add(4, 0, false);
       add(4, 0, true);
     }
     add(4, 1, false);
   }
+  if (i8 && (radix == 0 || radix == 8) && c.K >= 4) add(8, 0, false);
   return out;
 }
 
@@ -498,6 +511,7 @@ const char* kern_name(int kern) {
     case kKernRot2: return "radix-2 rotating";
     case kKernWide: return "radix-2 rotating, states in registers";
     case kKernRot4P: return "radix-4 packed two-frame";
+    case kKernGeneric8: return "radix-8 generic";
   }
   return "?";
 }
@@ -531,8 +545,8 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
   std::memset(&o, 0, sizeof o);
   if (opts) o = *opts;
   if (o.dtype != MIVIT_F32 && o.dtype != MIVIT_I8 && o.dtype != MIVIT_F16) return MIVIT_EINVAL;
-  if (o.radix != 0 && o.radix != 2 && o.radix != 4) return MIVIT_EINVAL;
-  if (o.radix == 4 && o.dtype != MIVIT_I8) return MIVIT_EINVAL;
+  if (o.radix != 0 && o.radix != 2 && o.radix != 4 && o.radix != 8) return MIVIT_EINVAL;
+  if ((o.radix == 4 || o.radix == 8) && o.dtype != MIVIT_I8) return MIVIT_EINVAL;
   if (o.chunk < 0 || o.overlap < 0 || (o.chunk > 0 && o.chunk % 32 != 0)) return MIVIT_EINVAL;
   if (o.variant < 0 || o.variant > 2) return MIVIT_EINVAL;
   if (o.flags & ~(MIVIT_PLAN_GRAPH | MIVIT_PLAN_AUTOTUNE | MIVIT_PLAN_PERSISTENT))
@@ -543,6 +557,11 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
     if (s != MIVIT_OK) return s;
   }
   if (o.dtype == MIVIT_F16 && o.variant != 0) return MIVIT_EUNSUPPORTED;
+  if (o.radix == 8) {  // one kernel, and at least 8 states
+    if (o.variant != 0) return MIVIT_EUNSUPPORTED;
+    for (int c = 0; c < n_codes; ++c)
+      if (codes[c].K < 4) return MIVIT_EUNSUPPORTED;
+  }
   // frames: ranges and non-overlapping outputs
   std::vector<std::pair<int64_t, int64_t>> words;
   words.reserve(n_frames);

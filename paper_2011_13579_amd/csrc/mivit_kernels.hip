@@ -1,19 +1,21 @@
 // Kernels of the soft-decision Viterbi decoder for gfx950 (wave64).
 //
-// Paper: arXiv 2011.13579.  The forward procedure evaluates Eq. (BM) and
-// Eq. (PM)/(SP0) of §II-B stage by stage (Algorithm 1); the traceback walks
-// the stored decisions backwards (Algorithm 2).  The radix-4 forward kernel
+// Paper: arXiv 2011.13579.  The generic forward procedures: radix 2 evaluates
+// Eq. (BM) and Eq. (PM)/(SP0) of §II-B stage by stage (Algorithm 1); radix 4
 // evaluates Eqs. (radix4:BM)/(radix4:PM)/(radix4:SP0) of §VIII-A, two stages
-// per iteration, with the left/right state maps of Eq. (radix4:S).
+// per iteration, with the left/right state maps of Eq. (radix4:S); radix 8
+// takes three stages per iteration (the radix-2^rho form with rho = 3).
+// Their decisions are traced back by the segmented traceback.  Also here: the
+// gradient of the best path metric, the int8 quantiser and small helpers.
 //
 // Mapping (one wavefront per trellis): lane l holds states l + 64*s for the
 // slots s < NSL (NSL = 2^(K-1)/64 for K > 7, else 1).  The branch metrics of
-// a block of 64 stages are tabulated in LDS, one stage per lane, for every
-// beta-bit branch output pattern.  Path metrics are exchanged through LDS.
-// Decisions of 64 states are packed by a wave ballot into one 64-bit word
-// per stage and slot (bit j = 1 when state j kept its higher-index previous
-// state), collected 64 stages at a time across the lanes and written with one
-// coalesced store.
+// a block of 64 stages (63 for radix 8) are tabulated in LDS, one stage per
+// lane, for every beta-bit branch output pattern.  Path metrics are exchanged
+// through LDS.  Decisions of 64 states are packed by a wave ballot into one
+// 64-bit word per stage and slot (radix 2: bit j = 1 when state j kept its
+// higher-index previous state), collected one block at a time across the
+// lanes and written with one coalesced store.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -85,7 +87,7 @@ __device__ __forceinline__ void fill_bm_table(const DevCode& c, const typename A
   }
 }
 
-// Final state and metric of an item (shared by both forward kernels).
+// Final state and metric of an item (shared by the generic forward kernels).
 template <int DT, int NSL>
 __device__ __forceinline__ void finish_item(const Item& it, int NS, const typename Arith<DT>::T* pm,
                                             const bool* act, typename Arith<DT>::T* xpm,
@@ -324,72 +326,149 @@ __global__ __launch_bounds__(64) void k_fwd_r4(const DevCode* __restrict__ codes
 }
 
 // ---------------------------------------------------------------------------
-// Traceback (Algorithm 2), one lane per item.
+// Radix-8 forward procedure (exact integers): the radix-2^rho form of §VIII
+// with rho = 3, three stages per iteration.  Right state j of dragonfly
+// f = j mod 2^(K-4) takes the best of the eight left states 8f+y.  With
+// u1, u2, u3 = bits K-4, K-3, K-2 of j (the inputs of the three stages), the
+// super-branch i -> m1 -> m2 -> j has middle states
+// m1 = u1 << (K-2) | (i >> 1) and m2 = u2 << (K-2) | (m1 >> 1), so m1
+// depends on y >> 1 and m2 on y >> 2 only.  The second stage's branch metric
+// is therefore common to y = 2k, 2k+1 and the third stage's to
+// y = 4l .. 4l+3: each is added after the max of its group (a tree of
+// 8 + 4 + 2 adds and 7 compare-selects).  Every max keeps the lower group on
+// ties, which picks the smallest y among the best candidates: the path
+// three radix-2 steps with their lower-predecessor rule choose.
+// Iterations start at stage 0 in blocks of 63 stages; the S mod 3 last
+// stages of a frame are radix-2 stages.  Decision words: for the stages
+// (t, t+1, t+2) of one iteration, word t + b holds bit b of y.
 // ---------------------------------------------------------------------------
-struct BitSink {
-  uint32_t word = 0;
-  // Emit the decoded bit of stage t (called with t decreasing).
-  __device__ __forceinline__ void put(const Item& it, int t, int u, uint32_t* bits) {
-    const int k = t - it.out_begin;
-    if (k >= 0 && k < it.n_out) {
-      word |= (uint32_t)u << (k & 31);
-      if ((k & 31) == 0) {
-        bits[(it.bit_off + k) >> 5] = word;
-        word = 0;
+constexpr int kBlk8 = 63;  // stages per staged block (a multiple of 3)
+
+template <int NSL>
+__global__ __launch_bounds__(64) void k_fwd_r8(const DevCode* __restrict__ codes,
+                                               const Item* __restrict__ items,
+                                               const void* __restrict__ llr_v,
+                                               uint64_t* __restrict__ surv, void* metric,
+                                               int32_t* end_out, int32_t* item_end) {
+  using T = int;
+  const int8_t* llr = (const int8_t*)llr_v;
+  const Item it = items[blockIdx.x];
+  const DevCode c = codes[it.code];
+  const int K = c.K, NS = 1 << (K - 1), half = NS >> 1, eighth = NS >> 3;
+  const int lane = threadIdx.x;
+  __shared__ __attribute__((aligned(16))) T xpm[kMaxStates];
+  __shared__ T bmt[kBlk][16];
+
+  int iLo[NSL], pLo[NSL], pHi[NSL], base[NSL];
+  uint8_t q1[NSL][8], q2[NSL][4], q3[NSL][2];
+  bool act[NSL];
+  T pm[NSL];
+  uint32_t svlo[NSL], svhi[NSL];
+#pragma unroll
+  for (int s = 0; s < NSL; ++s) {
+    const int j = lane + 64 * s;
+    act[s] = j < NS;
+    const int jj = act[s] ? j : 0;
+    const int u = jj >> (K - 2), f2 = jj & (half - 1);
+    iLo[s] = 2 * f2;
+    pLo[s] = branch_out(c, 2 * f2, u);
+    pHi[s] = branch_out(c, 2 * f2 + 1, u);
+    const int f = jj & (eighth - 1);
+    const int u1 = (jj >> (K - 4)) & 1, u2 = (jj >> (K - 3)) & 1, u3 = jj >> (K - 2);
+    base[s] = 8 * f;
+#pragma unroll
+    for (int y = 0; y < 8; ++y) q1[s][y] = (uint8_t)branch_out(c, 8 * f + y, u1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q2[s][k] = (uint8_t)branch_out(c, (u1 << (K - 2)) | (4 * f + k), u2);
+#pragma unroll
+    for (int l = 0; l < 2; ++l)
+      q3[s][l] = (uint8_t)branch_out(c, (u2 << (K - 2)) | (u1 << (K - 3)) | (2 * f + l), u3);
+    pm[s] = (it.start_known && j != 0) ? Arith<1>::unreachable() : 0;
+    svlo[s] = svhi[s] = 0;
+  }
+  int64_t offset = 0;
+  const int S = it.n_stages;
+  for (int t0 = 0; t0 < S; t0 += kBlk8) {
+    const int nst = min(kBlk8, S - t0);
+    fill_bm_table<1>(c, llr, it.llr_off, t0, nst, bmt);
+    if (t0 > 0) {
+      const T ref = __builtin_amdgcn_readfirstlane(pm[0]);
+#pragma unroll
+      for (int s = 0; s < NSL; ++s) pm[s] -= ref;
+      offset += ref;
+    }
+    __syncthreads();
+    const int ntri = nst - nst % 3;
+    for (int tt = 0; tt < ntri; tt += 3) {
+#pragma unroll
+      for (int s = 0; s < NSL; ++s)
+        if (act[s]) xpm[lane + 64 * s] = pm[s];
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < NSL; ++s) {
+        const int4 lo = *(const int4*)&xpm[base[s]];
+        const int4 hi = *(const int4*)&xpm[base[s] + 4];
+        const T pl[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+        T a[4];
+        int ya[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const T c0 = pl[2 * k] + bmt[tt][q1[s][2 * k]];
+          const T c1 = pl[2 * k + 1] + bmt[tt][q1[s][2 * k + 1]];
+          const bool h = c1 > c0;
+          a[k] = (h ? c1 : c0) + bmt[tt + 1][q2[s][k]];
+          ya[k] = 2 * k + (h ? 1 : 0);
+        }
+        T b[2];
+        int yb[2];
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+          const bool h = a[2 * l + 1] > a[2 * l];
+          b[l] = (h ? a[2 * l + 1] : a[2 * l]) + bmt[tt + 2][q3[s][l]];
+          yb[l] = h ? ya[2 * l + 1] : ya[2 * l];
+        }
+        const bool h = b[1] > b[0];
+        pm[s] = h ? b[1] : b[0];
+        const int y = h ? yb[1] : yb[0];
+#pragma unroll
+        for (int bit = 0; bit < 3; ++bit) {
+          const uint64_t m = __ballot(act[s] && ((y >> bit) & 1));
+          if (lane == tt + bit) {
+            svlo[s] = (uint32_t)m;
+            svhi[s] = (uint32_t)(m >> 32);
+          }
+        }
       }
+      __syncthreads();
+    }
+    // the S mod 3 last stages of the frame: radix-2 stages
+    for (int tt = ntri; tt < nst; ++tt) {
+#pragma unroll
+      for (int s = 0; s < NSL; ++s)
+        if (act[s]) xpm[lane + 64 * s] = pm[s];
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < NSL; ++s) {
+        const T a = xpm[iLo[s]], b = xpm[iLo[s] + 1];
+        const T cLo = a + bmt[tt][pLo[s]];
+        const T cHi = b + bmt[tt][pHi[s]];
+        const bool d = act[s] && (cHi > cLo);
+        pm[s] = d ? cHi : cLo;
+        const uint64_t m = __ballot(d);
+        if (lane == tt) {
+          svlo[s] = (uint32_t)m;
+          svhi[s] = (uint32_t)(m >> 32);
+        }
+      }
+      __syncthreads();
+    }
+    if (lane < nst) {
+      uint64_t* dst = surv + it.surv_off + (int64_t)(t0 + lane) * NSL;
+#pragma unroll
+      for (int s = 0; s < NSL; ++s) dst[s] = ((uint64_t)svhi[s] << 32) | svlo[s];
     }
   }
-};
-
-__global__ __launch_bounds__(64) void k_tb_r2(const DevCode* __restrict__ codes,
-                                              const Item* __restrict__ items, int n_items,
-                                              const uint64_t* __restrict__ surv,
-                                              const int32_t* __restrict__ item_end,
-                                              uint32_t* __restrict__ bits) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n_items) return;
-  const Item it = items[idx];
-  const DevCode c = codes[it.code];
-  const int K = c.K, NS = 1 << (K - 1), W = words_per_stage(K);
-  const uint64_t* sv = surv + it.surv_off;
-  int j = item_end[it.slot];
-  BitSink sink;
-  for (int t = it.n_stages - 1; t >= 0; --t) {
-    const uint64_t w = sv[(int64_t)t * W + (j >> 6)];
-    const int d = (int)((w >> (j & 63)) & 1);
-    sink.put(it, t, j >> (K - 2), bits);  // alpha_in of the branch into j
-    j = ((j << 1) | d) & (NS - 1);
-  }
-}
-
-__global__ __launch_bounds__(64) void k_tb_r4(const DevCode* __restrict__ codes,
-                                              const Item* __restrict__ items, int n_items,
-                                              const uint64_t* __restrict__ surv,
-                                              const int32_t* __restrict__ item_end,
-                                              uint32_t* __restrict__ bits) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n_items) return;
-  const Item it = items[idx];
-  const DevCode c = codes[it.code];
-  const int K = c.K, NS = 1 << (K - 1), W = words_per_stage(K);
-  const uint64_t* sv = surv + it.surv_off;
-  const int S = it.n_stages;
-  int j = item_end[it.slot];
-  BitSink sink;
-  if (S & 1) {
-    const int t = S - 1;
-    const int d = (int)((sv[(int64_t)t * W + (j >> 6)] >> (j & 63)) & 1);
-    sink.put(it, t, j >> (K - 2), bits);
-    j = ((j << 1) | d) & (NS - 1);
-  }
-  for (int t = (S & ~1) - 2; t >= 0; t -= 2) {
-    const int wi = j >> 6, sh = j & 63;
-    const int y = (int)((sv[(int64_t)t * W + wi] >> sh) & 1) |
-                  ((int)((sv[(int64_t)(t + 1) * W + wi] >> sh) & 1) << 1);
-    sink.put(it, t + 1, j >> (K - 2), bits);
-    sink.put(it, t, (j >> (K - 3)) & 1, bits);
-    j = 4 * (j & ((NS >> 2) - 1)) + y;
-  }
+  finish_item<1, NSL>(it, NS, pm, act, xpm, offset, metric, end_out, item_end);
 }
 
 // ---------------------------------------------------------------------------
@@ -481,11 +560,19 @@ hipError_t launch_fwd(int radix, int nsl, int dt, const DevCode* codes, const It
   dim3 g(n_items), b(64);
 #define MV_FWD2(N, I) hipLaunchKernelGGL((k_fwd_r2<N, I>), g, b, 0, st, codes, items, llr, surv, metric, end_out, item_end)
 #define MV_FWD4(N) hipLaunchKernelGGL((k_fwd_r4<N>), g, b, 0, st, codes, items, llr, surv, metric, end_out, item_end)
+#define MV_FWD8(N) hipLaunchKernelGGL((k_fwd_r8<N>), g, b, 0, st, codes, items, llr, surv, metric, end_out, item_end)
   if (radix == 4) {
     switch (nsl) {
       case 1: MV_FWD4(1); break;
       case 2: MV_FWD4(2); break;
       case 4: MV_FWD4(4); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else if (radix == 8) {
+    switch (nsl) {
+      case 1: MV_FWD8(1); break;
+      case 2: MV_FWD8(2); break;
+      case 4: MV_FWD8(4); break;
       default: return hipErrorInvalidValue;
     }
   } else {
@@ -505,18 +592,7 @@ hipError_t launch_fwd(int radix, int nsl, int dt, const DevCode* codes, const It
   }
 #undef MV_FWD2
 #undef MV_FWD4
-  return hipGetLastError();
-}
-
-hipError_t launch_tb(int radix, const DevCode* codes, const Item* items, int n_items,
-                     const uint64_t* surv, const int32_t* item_end, uint32_t* bits,
-                     hipStream_t st) {
-  if (n_items <= 0) return hipSuccess;
-  dim3 g((n_items + 63) / 64), b(64);
-  if (radix == 4)
-    hipLaunchKernelGGL(k_tb_r4, g, b, 0, st, codes, items, n_items, surv, item_end, bits);
-  else
-    hipLaunchKernelGGL(k_tb_r2, g, b, 0, st, codes, items, n_items, surv, item_end, bits);
+#undef MV_FWD8
   return hipGetLastError();
 }
 

@@ -30,6 +30,8 @@ namespace mivit {
 enum : int {
   kLayoutNatR2 = 0,  // per stage, ceil(NS/64) uint64 words, bit j = decision of state j
   kLayoutNatR4 = 1,  // same words; stage pairs (t, t+1) from 0 hold bits 0 and 1 of y
+  kLayoutNatR8 = 5,  // same words; stage triples (t, t+1, t+2) from 0 hold bits 0..2 of y,
+                     // the S mod 3 last stages radix-2 decisions
   kLayoutRotR2 = 2,  // per 32 stages, NS uint32 words; rotating state-to-word map
   kLayoutRotByte = 4,  // per 8 stages, NS bytes: byte p = decisions at position p (stage
                        // 8g + i at bit 7 - i); the state j after stage t is at position
@@ -49,6 +51,9 @@ struct TbGeom {
     } else if (LAYOUT == kLayoutRotByte) {
       SB = 2048 / NS;  // 64 words of NS / 4 words per 8 stages
       WB = 64;
+    } else if (LAYOUT == kLayoutNatR8) {
+      SB = (32 / W) / 3 * 3;  // whole triples per block: 30, 15 or 6 stages
+      WB = SB * 2 * W;
     } else {
       SB = 32 / W;
       WB = 64;
@@ -92,6 +97,8 @@ __device__ __forceinline__ uint32_t word_at(const uint32_t* buf_k, int w, int la
 // entering stage t.  In the natural radix-4 layout the decisions of a stage
 // pair (2k, 2k+1) only name the state two stages back, so states are known
 // (and compared between segments) at pair-aligned times: even times and S.
+// In the radix-8 layout they are the multiples of 3 and the times of the
+// radix-2 stages at the end.
 struct Chase {
   int top, a, b;  // from time top down to time a; bits of [a, b) are emitted
   int j;          // current state
@@ -147,6 +154,33 @@ __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_
           if (t - 1 == c.yb) c.y = j;
           if (t - 1 == c.xa) c.x = j;
         }
+      } else if (LAYOUT == kLayoutNatR8) {
+        // the S mod 3 last stages were radix-2 stages
+        for (; t >= S - S % 3 && t >= B * SB && t >= c.a; --t) {
+          const int w = (t % SB) * 2 * g.W + (j >> 5);
+          const int d = (word_at(cur, w, lane) >> (j & 31)) & 1;
+          if (t < c.b) em.put(t - ob, j >> (g.KM1 - 1), bits, bit_off);
+          j = ((j << 1) | d) & (g.NS - 1);
+          if (t == c.yb) c.y = j;
+          if (t == c.xa) c.x = j;
+        }
+        // triples (t-2, t-1, t), t = 2 mod 3; triples never straddle a block
+        for (; t >= B * SB + 2 && t >= c.a; t -= 3) {
+          const int sh = j & 31;
+          const int w2 = (t % SB) * 2 * g.W + (j >> 5);
+          const int w1 = w2 - 2 * g.W, w0 = w1 - 2 * g.W;
+          const int yy = ((word_at(cur, w0, lane) >> sh) & 1) |
+                         (((word_at(cur, w1, lane) >> sh) & 1) << 1) |
+                         (((word_at(cur, w2, lane) >> sh) & 1) << 2);
+          if (t < c.b) em.put(t - ob, j >> (g.KM1 - 1), bits, bit_off);
+          if (t - 1 >= c.a && t - 1 < c.b)
+            em.put(t - 1 - ob, (j >> (g.KM1 - 2)) & 1, bits, bit_off);
+          if (t - 2 >= c.a && t - 2 < c.b)
+            em.put(t - 2 - ob, (j >> (g.KM1 - 3)) & 1, bits, bit_off);
+          j = 8 * (j & ((g.NS >> 3) - 1)) + yy;
+          if (t - 2 == c.yb) c.y = j;
+          if (t - 2 == c.xa) c.x = j;
+        }
       } else {
         const int lo = max(c.a, B * SB);
         for (; t >= lo; --t) {
@@ -187,9 +221,14 @@ __global__ __launch_bounds__(64) void k_tb_seg(const DevCode* __restrict__ codes
   const int lane = threadIdx.x;
   const uint32_t* sv = (const uint32_t*)(surv + it.surv_off);
   const int S = it.n_stages, ob = it.out_begin, n = it.n_out;
-  // pair-aligned time at or above t (every time for radix 2)
-  const bool pairs = LAYOUT == kLayoutNatR4;
-  auto align = [&](int t) { return (pairs && (t & 1) && t < S) ? t + 1 : t; };
+  // the next time at or above t where states are known (every time for
+  // radix 2; even times and S for radix 4; multiples of 3 and the times from
+  // S - S mod 3 on for radix 8)
+  auto align = [&](int t) {
+    if (LAYOUT == kLayoutNatR4) return ((t & 1) && t < S) ? t + 1 : t;
+    if (LAYOUT == kLayoutNatR8) return (t % 3 && t < S - S % 3) ? t + 3 - t % 3 : t;
+    return t;
+  };
   // segment geometry: G segments of L stages, L a multiple of 32
   int G = min(64, (n + 31) / 32);
   const int L = (((n + G - 1) / G) + 31) & ~31;
@@ -236,6 +275,10 @@ hipError_t launch_tb_seg(int layout, const DevCode* codes, const Item* items, in
       break;
     case kLayoutNatR4:
       hipLaunchKernelGGL(k_tb_seg<kLayoutNatR4>, grid, block, 0, st, codes, items, surv,
+                         item_end, bits, warm);
+      break;
+    case kLayoutNatR8:
+      hipLaunchKernelGGL(k_tb_seg<kLayoutNatR8>, grid, block, 0, st, codes, items, surv,
                          item_end, bits, warm);
       break;
     case kLayoutRotR2:

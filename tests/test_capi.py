@@ -105,7 +105,8 @@ def test_overlapping_outputs():
 
 
 @pytest.mark.parametrize("opts", [
-    dict(dtype=3), dict(dtype=-1), dict(radix=3), dict(radix=4, dtype=0), dict(radix=4, dtype=2),
+    dict(dtype=3), dict(dtype=-1), dict(radix=3), dict(radix=16), dict(radix=4, dtype=0),
+    dict(radix=4, dtype=2), dict(radix=8, dtype=0), dict(radix=8, dtype=2),
     dict(chunk=-1), dict(chunk=100),
     dict(overlap=-1), dict(variant=3), dict(flags=8), dict(flags=1 << 31),
 ])
@@ -117,6 +118,13 @@ def test_bad_opts(opts):
 def test_f16_other_variants_unsupported(variant):
     """float16 soft values run the default exchange scheme only."""
     assert _plan_status([K7], _frame(), dtype=_capi.MIVIT_F16, variant=variant) == \
+        _capi.MIVIT_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("code,variant", [(_code(3, [7, 5]), 0), (K7, 1), (K7, 2)])
+def test_radix8_unsupported(code, variant):
+    """Radix 8 needs at least 8 states and runs one kernel (variant 0)."""
+    assert _plan_status([code], _frame(), dtype=_capi.MIVIT_I8, radix=8, variant=variant) == \
         _capi.MIVIT_EUNSUPPORTED
 
 

@@ -4,8 +4,8 @@ float32 frames: decoded bits and metrics identical to the single-precision
 oracle (the decisions are taken in the same precision); bits equal to the
 double-precision oracle on every frame whose runner-up gap exceeds the float32
 error bound; metric within 1e-5 relative of double precision.
-int8 frames: bits and metrics identical to the exact-integer oracle, radix 2
-and radix 4, including tie-heavy inputs.
+int8 frames: bits and metrics identical to the exact-integer oracle, radix 2,
+4 and 8, including tie-heavy inputs.
 """
 import numpy as np
 import pytest
@@ -99,9 +99,11 @@ def int8_batch(code, F, n, eb, seed, ties=False):
     return b, q
 
 
-@pytest.mark.parametrize("radix", [2, 4])
+@pytest.mark.parametrize("radix", [2, 4, 8])
 @pytest.mark.parametrize("code", CODES, ids=cid)
 def test_int8_exact(code, radix):
+    if radix == 8 and code.K < 4:
+        pytest.skip("radix 8 needs at least 8 states")
     for n, F, eb, ties in [(0, 2, 2.0, False), (1, 3, 2.0, True), (2, 3, 1.0, True),
                            (61, 5, 1.0, False), (130, 4, 2.0, True), (777, 3, 0.0, False)]:
         b, q = int8_batch(code, F, n, eb, 2000 + n + code.K, ties)
@@ -123,7 +125,7 @@ def _plan_decode(code, frames, llr_np, dtype, radix=0, chunk=0, overlap=0):
 
 
 @pytest.mark.parametrize("code", [CODE_K5, CODE_K7, CODE_K9], ids=cid)
-@pytest.mark.parametrize("dtype,radix", [("f32", 2), ("f16", 2), ("i8", 2), ("i8", 4)])
+@pytest.mark.parametrize("dtype,radix", [("f32", 2), ("f16", 2), ("i8", 2), ("i8", 4), ("i8", 8)])
 def test_free_end_and_unknown_start(code, dtype, radix):
     """Frames with a best-state end and with an unknown start (all-zero
     initial metrics), mixed lengths in one plan."""
@@ -175,7 +177,7 @@ def test_chunked_stream(dtype):
             llr = llr.astype(np.float16)
     t = torch.from_numpy(llr).to(DEV)
     ref = llr.astype(np.float32) if dtype == "f16" else llr
-    for radix in ((2, 4) if dtype == "i8" else (2,)):
+    for radix in ((2, 4, 8) if dtype == "i8" else (2,)):
         words = mv.decode_stream(t, CODE_K7, n, 2048, 64, radix)
         torch.cuda.synchronize()
         bits = mv.unpack_bits(words.cpu().numpy(), n)
@@ -185,9 +187,10 @@ def test_chunked_stream(dtype):
 
 
 @pytest.mark.parametrize("code", [CODE_K5, CODE_K7], ids=cid)
-def test_int8_radix4_extremes(code):
+def test_int8_extremes(code):
     """Saturated soft values (+-127, -128 and runs of equal signs) over long
-    frames: the widest metric spread and many range-control steps."""
+    frames: the widest metric spread and many range-control steps (radix 4
+    packed and generic, radix 8)."""
     rng = np.random.default_rng(77 + code.K)
     for n, F in [(5000, 3), (4093, 6), (255, 9)]:
         S = n + code.K - 1
@@ -195,10 +198,10 @@ def test_int8_radix4_extremes(code):
         vals = np.array([127, -127, -128, 0], np.int16)[pick]
         runs = rng.integers(0, 2, size=(F, 1)) * rng.integers(-128, 128, size=(F, S * code.beta))
         q = np.where(rng.random((F, S * code.beta)) < 0.3, runs, vals).astype(np.int8)
-        for variant in (0, 1):
-            print("extremes", cid(code), n, F, variant, flush=True)
+        for radix, variant in ((4, 0), (4, 1), (8, 0)):
+            print("extremes", cid(code), n, F, radix, variant, flush=True)
             fr = mv.uniform_frames(code, F, n, True)
-            plan = mv.Plan([code], fr, "i8", 4, variant=variant)
+            plan = mv.Plan([code], fr, "i8", radix, variant=variant)
             words, metric, _ = plan.decode(torch.from_numpy(q).to(DEV))
             torch.cuda.synchronize()
             nw = (n + 31) // 32
@@ -209,21 +212,22 @@ def test_int8_radix4_extremes(code):
 
 
 @pytest.mark.parametrize("code", [CODE_K5, CODE_K7], ids=cid)
-def test_radix4_packed_vs_generic_windows(code):
+def test_int8_windows(code):
     """Chunked windows (unknown start, best end, emitted cores that differ
     between equal-length windows) through the packed and the generic
-    radix-4 kernels, odd stage counts included; both equal the oracle."""
+    radix-4 kernels and the radix-8 kernel, stage counts of every residue
+    included; all equal the oracle."""
     from workload import int8_scale_for
     for n, chunk, ov in [(9001, 512, 64), (3001, 256, 33), (777, 2048, 64)]:
         msg, llr = make_stream(code, n, 2.0, seed=31 + n)
         q = oracle.quantize_i8(llr, int8_scale_for(2.0, 2))
         t = torch.from_numpy(q).to(DEV)
         ob, _, _ = oracle.decode_chunked(code, q, n, chunk, ov, oracle.I64)
-        for variant in (0, 1):
-            print("windows", cid(code), n, chunk, ov, variant, flush=True)
+        for radix, variant in ((4, 0), (4, 1), (8, 0)):
+            print("windows", cid(code), n, chunk, ov, radix, variant, flush=True)
             fr = np.zeros(1, mv.FRAME_DTYPE)
             fr[0] = (0, 0, n, 0, n, 0, mv.MIVIT_START_KNOWN)
-            plan = mv.Plan([code], fr, "i8", 4, chunk, ov, variant=variant)
+            plan = mv.Plan([code], fr, "i8", radix, chunk, ov, variant=variant)
             words, _, _ = plan.decode(t)
             torch.cuda.synchronize()
             bits = mv.unpack_bits(words.cpu().numpy(), n)
@@ -453,13 +457,15 @@ def _check_mixed(codes, plan, fr, ofr, llr_np, dtype, n_bits, words=None):
 
 
 @pytest.mark.parametrize("dtype", ["i8", "f32", "f16"])
-@pytest.mark.parametrize("mode", ["default", "persistent", "autotune"])
+@pytest.mark.parametrize("mode", ["default", "persistent", "autotune", "radix8"])
 def test_mixed_codes_batch(dtype, mode):
     """Uneven frames of three codes in one plan: one part per code, run
-    concurrently; persistent work-queue and autotuned plans give the same
-    bits and metrics as the oracle."""
+    concurrently; persistent work-queue, autotuned and (int8) radix-8 plans
+    give the same bits and metrics as the oracle."""
+    if mode == "radix8" and dtype != "i8":
+        pytest.skip("radix 8 takes int8 soft values")
     codes, fr, ofr, llr, n_bits = _mixed(dtype)
-    radix = 4 if (dtype == "i8" and mode != "autotune") else 0
+    radix = 8 if mode == "radix8" else 4 if (dtype == "i8" and mode != "autotune") else 0
     print("mixed", dtype, mode, flush=True)
     plan = mv.Plan(codes, fr, dtype, radix, persistent=(mode == "persistent"),
                    autotune=(mode == "autotune"))
