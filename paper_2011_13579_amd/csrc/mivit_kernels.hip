@@ -332,15 +332,17 @@ __global__ __launch_bounds__(64) void k_fwd_r4(const DevCode* __restrict__ codes
 // u1, u2, u3 = bits K-4, K-3, K-2 of j (the inputs of the three stages), the
 // super-branch i -> m1 -> m2 -> j has middle states
 // m1 = u1 << (K-2) | (i >> 1) and m2 = u2 << (K-2) | (m1 >> 1), so m1
-// depends on y >> 1 and m2 on y >> 2 only.  The second stage's branch metric
-// is therefore common to y = 2k, 2k+1 and the third stage's to
-// y = 4l .. 4l+3: each is added after the max of its group (a tree of
-// 8 + 4 + 2 adds and 7 compare-selects).  Every max keeps the lower group on
-// ties, which picks the smallest y among the best candidates: the path
-// three radix-2 steps with their lower-predecessor rule choose.
-// Iterations start at stage 0 in blocks of 63 stages; the S mod 3 last
-// stages of a frame are radix-2 stages.  Decision words: for the stages
-// (t, t+1, t+2) of one iteration, word t + b holds bit b of y.
+// depends on y >> 1 and m2 on y >> 2 only.  Ties go to the smallest y: the
+// path three radix-2 steps with their lower-predecessor rule choose.
+//
+// Metrics are held as 8*PM, and each candidate carries the tag 7-y in its
+// three low bits: one signed max over the eight tagged candidates yields the
+// best metric (tag cleared) and, on equal metrics, the smallest y.  The
+// branch-metric sums of the eight super-branches are formed before the path
+// metrics arrive.  Iterations start at stage 0 in blocks of 63 stages; the
+// S mod 3 last stages of a frame are radix-2 stages.  Decision words: for the
+// stages (t, t+1, t+2) of one iteration, word t + b holds bit b of y; lane 0
+// parks them in LDS and the block's words are stored together.
 // ---------------------------------------------------------------------------
 constexpr int kBlk8 = 63;  // stages per staged block (a multiple of 3)
 
@@ -358,16 +360,18 @@ __global__ __launch_bounds__(64) void k_fwd_r8(const DevCode* __restrict__ codes
   const int lane = threadIdx.x;
   __shared__ __attribute__((aligned(16))) T xpm[kMaxStates];
   __shared__ T bmt[kBlk][16];
+  __shared__ uint64_t svb[kBlk8][NSL];
 
   int iLo[NSL], pLo[NSL], pHi[NSL], base[NSL];
   uint8_t q1[NSL][8], q2[NSL][4], q3[NSL][2];
   bool act[NSL];
-  T pm[NSL];
-  uint32_t svlo[NSL], svhi[NSL];
+  uint64_t amask[NSL];  // lanes holding states
+  T pm[NSL];            // 8 * path metric
 #pragma unroll
   for (int s = 0; s < NSL; ++s) {
     const int j = lane + 64 * s;
     act[s] = j < NS;
+    amask[s] = __ballot(act[s]);
     const int jj = act[s] ? j : 0;
     const int u = jj >> (K - 2), f2 = jj & (half - 1);
     iLo[s] = 2 * f2;
@@ -383,14 +387,17 @@ __global__ __launch_bounds__(64) void k_fwd_r8(const DevCode* __restrict__ codes
 #pragma unroll
     for (int l = 0; l < 2; ++l)
       q3[s][l] = (uint8_t)branch_out(c, (u2 << (K - 2)) | (u1 << (K - 3)) | (2 * f + l), u3);
+    // the unreachable stand-in is a multiple of 8 and stays far below every
+    // reachable 8 * PM
     pm[s] = (it.start_known && j != 0) ? Arith<1>::unreachable() : 0;
-    svlo[s] = svhi[s] = 0;
   }
-  int64_t offset = 0;
+  int64_t offset = 0;  // 8 * total subtracted by renormalisation
   const int S = it.n_stages;
   for (int t0 = 0; t0 < S; t0 += kBlk8) {
     const int nst = min(kBlk8, S - t0);
     fill_bm_table<1>(c, llr, it.llr_off, t0, nst, bmt);
+    if (lane < nst)
+      for (int p = 0; p < (1 << c.beta); ++p) bmt[lane][p] *= 8;
     if (t0 > 0) {
       const T ref = __builtin_amdgcn_readfirstlane(pm[0]);
 #pragma unroll
@@ -399,47 +406,59 @@ __global__ __launch_bounds__(64) void k_fwd_r8(const DevCode* __restrict__ codes
     }
     __syncthreads();
     const int ntri = nst - nst % 3;
-    for (int tt = 0; tt < ntri; tt += 3) {
+    // 8 * (branch metrics of the three stages) + tag, per super-branch;
+    // loaded one iteration ahead, next to the path-metric exchange
+    T sb[NSL][8];
+    auto load_sb = [&](T (*dst)[8], const int tt) __attribute__((always_inline)) {
+#pragma unroll
+      for (int s = 0; s < NSL; ++s)
+#pragma unroll
+        for (int y = 0; y < 8; ++y)
+          dst[s][y] = bmt[tt][q1[s][y]] + bmt[tt + 1][q2[s][y >> 1]] +
+                      bmt[tt + 2][q3[s][y >> 2]] + (7 - y);
+    };
+    auto iteration = [&](const int tt) __attribute__((always_inline)) {
 #pragma unroll
       for (int s = 0; s < NSL; ++s)
         if (act[s]) xpm[lane + 64 * s] = pm[s];
       __syncthreads();
+      int4 lo[NSL], hi[NSL];
 #pragma unroll
       for (int s = 0; s < NSL; ++s) {
-        const int4 lo = *(const int4*)&xpm[base[s]];
-        const int4 hi = *(const int4*)&xpm[base[s] + 4];
-        const T pl[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-        T a[4];
-        int ya[4];
+        lo[s] = *(const int4*)&xpm[base[s]];
+        hi[s] = *(const int4*)&xpm[base[s] + 4];
+      }
+      T nx[NSL][8];
+      if (tt + 3 < ntri) load_sb(nx, tt + 3);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const T c0 = pl[2 * k] + bmt[tt][q1[s][2 * k]];
-          const T c1 = pl[2 * k + 1] + bmt[tt][q1[s][2 * k + 1]];
-          const bool h = c1 > c0;
-          a[k] = (h ? c1 : c0) + bmt[tt + 1][q2[s][k]];
-          ya[k] = 2 * k + (h ? 1 : 0);
-        }
-        T b[2];
-        int yb[2];
-#pragma unroll
-        for (int l = 0; l < 2; ++l) {
-          const bool h = a[2 * l + 1] > a[2 * l];
-          b[l] = (h ? a[2 * l + 1] : a[2 * l]) + bmt[tt + 2][q3[s][l]];
-          yb[l] = h ? ya[2 * l + 1] : ya[2 * l];
-        }
-        const bool h = b[1] > b[0];
-        pm[s] = h ? b[1] : b[0];
-        const int y = h ? yb[1] : yb[0];
+      for (int s = 0; s < NSL; ++s) {
+        const T m0 = max(max(lo[s].x + sb[s][0], lo[s].y + sb[s][1]), lo[s].z + sb[s][2]);
+        const T m1 = max(max(lo[s].w + sb[s][3], hi[s].x + sb[s][4]), hi[s].y + sb[s][5]);
+        const T m2 = max(hi[s].z + sb[s][6], hi[s].w + sb[s][7]);
+        const T best = max(max(m0, m1), m2);
+        pm[s] = best & ~7;
+        // bit b of y = 7 - tag is the complement of bit b of the tag
 #pragma unroll
         for (int bit = 0; bit < 3; ++bit) {
-          const uint64_t m = __ballot(act[s] && ((y >> bit) & 1));
-          if (lane == tt + bit) {
-            svlo[s] = (uint32_t)m;
-            svhi[s] = (uint32_t)(m >> 32);
-          }
+          const uint64_t m = __ballot(((best >> bit) & 1) == 0) & amask[s];
+          if (lane == 0) svb[tt + bit][s] = m;
         }
       }
+      if (tt + 3 < ntri) {
+#pragma unroll
+        for (int s = 0; s < NSL; ++s)
+#pragma unroll
+          for (int y = 0; y < 8; ++y) sb[s][y] = nx[s][y];
+      }
       __syncthreads();
+    };
+    if (ntri > 0) load_sb(sb, 0);
+    if (ntri == kBlk8) {
+      // whole blocks unrolled: the table offsets become immediates
+#pragma unroll
+      for (int tt = 0; tt < kBlk8; tt += 3) iteration(tt);
+    } else {
+      for (int tt = 0; tt < ntri; tt += 3) iteration(tt);
     }
     // the S mod 3 last stages of the frame: radix-2 stages
     for (int tt = ntri; tt < nst; ++tt) {
@@ -455,20 +474,20 @@ __global__ __launch_bounds__(64) void k_fwd_r8(const DevCode* __restrict__ codes
         const bool d = act[s] && (cHi > cLo);
         pm[s] = d ? cHi : cLo;
         const uint64_t m = __ballot(d);
-        if (lane == tt) {
-          svlo[s] = (uint32_t)m;
-          svhi[s] = (uint32_t)(m >> 32);
-        }
+        if (lane == 0) svb[tt][s] = m;
       }
       __syncthreads();
     }
     if (lane < nst) {
       uint64_t* dst = surv + it.surv_off + (int64_t)(t0 + lane) * NSL;
 #pragma unroll
-      for (int s = 0; s < NSL; ++s) dst[s] = ((uint64_t)svhi[s] << 32) | svlo[s];
+      for (int s = 0; s < NSL; ++s) dst[s] = svb[lane][s];
     }
+    __syncthreads();
   }
-  finish_item<1, NSL>(it, NS, pm, act, xpm, offset, metric, end_out, item_end);
+#pragma unroll
+  for (int s = 0; s < NSL; ++s) pm[s] >>= 3;  // exact: multiples of 8
+  finish_item<1, NSL>(it, NS, pm, act, xpm, offset >> 3, metric, end_out, item_end);
 }
 
 // ---------------------------------------------------------------------------
