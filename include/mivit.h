@@ -239,6 +239,48 @@ mivit_status mivit_pipe_run(mivit_pipe* pipe, const void* host_llr, uint32_t* ho
                             void* host_metric, int64_t n_batches);
 mivit_status mivit_pipe_destroy(mivit_pipe* pipe);
 
+/* Continuous stream across calls (the frames with overlap of §III for one
+ * stream whose soft values arrive in pieces): the stream is cut into windows
+ * exactly as a plan with the same chunk and overlap cuts it as one frame
+ * (cores of opts->chunk stages, opts->overlap stages on each side, a window
+ * at the stream's start with a known start state when flags has
+ * MIVIT_START_KNOWN, the last window ending in state 0 when flags has
+ * MIVIT_END_ZERO).  Each window is decoded once its right overlap has
+ * arrived and its core bits are emitted in stream order, one bit per stage,
+ * so the bits of all calls, concatenated, equal that plan's output.  The
+ * soft values not yet consumed (fewer than chunk + 2*overlap stages) stay in
+ * a device buffer between calls.
+ *
+ * mivit_stream_create: code and opts as for mivit_plan_create (host
+ *   pointers, copied), with opts->chunk > 0 a multiple of 32 and
+ *   opts->overlap >= 0; flags: MIVIT_START_KNOWN | MIVIT_END_ZERO;
+ *   max_push_stages > 0 bounds one push.  Reserves two device buffers of
+ *   chunk + 2*overlap + max_push_stages stages on the current device.
+ *   Errors: MIVIT_EINVAL, those of mivit_plan_create, MIVIT_ENOMEM.
+ * mivit_stream_push: appends n_stages stages (0 <= n_stages <=
+ *   max_push_stages) of soft values, device memory of the stream's dtype,
+ *   beta values per stage; writes the bits of every window now complete to
+ *   the device words at bits (from bit 0; at most max_push_stages + chunk
+ *   + 2*overlap bits, always a multiple of chunk) and their number to the
+ *   host int64 *n_bits.  Asynchronous on 'stream'; llr may be reused once
+ *   the stream has passed this call.  Window plans (one per distinct run of
+ *   windows, up to 8 kept) are created on first use.
+ * mivit_stream_finish: the stream has ended; writes the bits of the
+ *   remaining windows (at most chunk + 2*overlap) to bits and their number
+ *   to *n_bits, and waits for the device.  No push may follow.
+ * mivit_stream_destroy: waits for the device and frees the stream.
+ * Calls on one stream object must be made one at a time, on one HIP stream
+ * (or with the caller ordering them).  After an error, destroy the stream. */
+typedef struct mivit_stream mivit_stream;
+mivit_status mivit_stream_create(mivit_stream** stream_obj, const mivit_code* code,
+                                 const mivit_opts* opts, uint32_t flags,
+                                 int64_t max_push_stages);
+mivit_status mivit_stream_push(mivit_stream* stream_obj, const void* llr, int64_t n_stages,
+                               uint32_t* bits, int64_t* n_bits, void* stream);
+mivit_status mivit_stream_finish(mivit_stream* stream_obj, uint32_t* bits, int64_t* n_bits,
+                                 void* stream);
+mivit_status mivit_stream_destroy(mivit_stream* stream_obj);
+
 /* int8 quantiser for soft values (the paper uses float inputs; this is the
  * library's choice): q[k] = saturate_127(round_half_even(fl32(llr[k] *
  * scale))); the product is rounded to float32 first.  llr: device float32

@@ -11,6 +11,7 @@ Entry points
   decode_stream(llr, code, n_info, chunk, overlap)   one long stream, chunked
   quantize_i8(llr, scale)                            float32 -> int8 soft values
   Pipeline(plan, depth).run(host_llr, host_bits)     batches from host memory
+  StreamDecoder(code, dtype, chunk, overlap, ...)    one stream pushed in pieces
   ViterbiDecode.apply(llr, code, n_info)             autograd on the best metric
 """
 from __future__ import annotations
@@ -25,7 +26,7 @@ from . import _capi
 from ._capi import (FRAME_DTYPE, MIVIT_END_ZERO, MIVIT_F16, MIVIT_F32, MIVIT_I8, MIVIT_START_KNOWN,
                     MivitError)
 
-__all__ = ["Code", "Plan", "Pipeline", "decode", "decode_stream", "quantize_i8", "ViterbiDecode",
+__all__ = ["Code", "Plan", "Pipeline", "StreamDecoder", "decode", "decode_stream", "quantize_i8", "ViterbiDecode",
            "unpack_bits", "FRAME_DTYPE", "MivitError", "version"]
 
 
@@ -256,6 +257,88 @@ class Pipeline:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.mivit_pipe_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class StreamDecoder:
+    """One continuous stream whose soft values arrive in pieces
+    (mivit_stream_*): cut into windows of ``chunk`` core stages with
+    ``overlap`` stages on each side exactly as decode_stream cuts it, each
+    window decoded once its right overlap has arrived.  push() and finish()
+    return the bit words of the windows completed by that call (one bit per
+    stage, stream order) and their number of bits; concatenated, they equal
+    the one-shot chunked decode of the whole stream."""
+
+    def __init__(self, code, dtype: str = "i8", chunk: int = 2048, overlap: int = 64,
+                 max_push_stages: int = 1 << 20, radix: int = 0, variant: int = 0,
+                 start_known: bool = True, end_zero: bool = False):
+        self._lib = _capi.load()
+        self.code = _as_code(code)
+        self.dtype = {"f32": MIVIT_F32, "i8": MIVIT_I8, "f16": MIVIT_F16}[dtype]
+        self.chunk, self.overlap = int(chunk), int(overlap)
+        self.max_push_stages = int(max_push_stages)
+        opts = _capi.Opts()
+        opts.dtype, opts.radix, opts.chunk, opts.overlap = self.dtype, int(radix), self.chunk, \
+            self.overlap
+        opts.variant = int(variant)
+        flags = (MIVIT_START_KNOWN if start_known else 0) | (MIVIT_END_ZERO if end_zero else 0)
+        h = ctypes.c_void_p()
+        _capi.check(self._lib.mivit_stream_create(ctypes.byref(h), ctypes.byref(self.code.c_struct()),
+                                                  ctypes.byref(opts), flags, self.max_push_stages),
+                    "mivit_stream_create")
+        self._h = h
+        self._words = None  # output words, sized for one call
+
+    def _out(self, device):
+        torch = _torch()
+        n = (self.max_push_stages + self.chunk + 2 * self.overlap + 31) // 32
+        if self._words is None or self._words.device != device:
+            self._words = torch.empty(n, dtype=torch.int32, device=device)
+        return self._words
+
+    def push(self, llr, stream=None):
+        """llr: device tensor of whole stages (beta soft values each) of the
+        stream's dtype.  Returns (bit words int32, number of bits); the words
+        are a view of a buffer the next call overwrites."""
+        torch = _torch()
+        want = {MIVIT_F32: torch.float32, MIVIT_I8: torch.int8, MIVIT_F16: torch.float16}
+        beta = self.code.beta
+        if llr.dtype != want[self.dtype] or not llr.is_cuda or llr.numel() % beta:
+            raise ValueError("soft values must be a device tensor of dtype %s holding whole "
+                             "stages of %d values" % (want[self.dtype], beta))
+        llr = llr.contiguous()
+        n_st = llr.numel() // beta
+        if n_st > self.max_push_stages:
+            raise ValueError("push of %d stages exceeds max_push_stages=%d"
+                             % (n_st, self.max_push_stages))
+        words = self._out(llr.device)
+        nb = ctypes.c_int64()
+        _capi.check(self._lib.mivit_stream_push(self._h, _dptr(llr), n_st, _dptr(words),
+                                                ctypes.byref(nb), _stream_handle(stream)),
+                    "mivit_stream_push")
+        return words[: (nb.value + 31) // 32], nb.value
+
+    def finish(self, device=None, stream=None):
+        """End of the stream: the remaining windows' bit words and bit count."""
+        torch = _torch()
+        words = self._out(torch.device(device) if device is not None else
+                          (self._words.device if self._words is not None else
+                           torch.device("cuda", torch.cuda.current_device())))
+        nb = ctypes.c_int64()
+        _capi.check(self._lib.mivit_stream_finish(self._h, _dptr(words), ctypes.byref(nb),
+                                                  _stream_handle(stream)),
+                    "mivit_stream_finish")
+        return words[: (nb.value + 31) // 32], nb.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.mivit_stream_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

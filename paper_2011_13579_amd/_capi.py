@@ -18,6 +18,7 @@ EXPORTS = (
     "mivit_plan_create", "mivit_decode", "mivit_forward", "mivit_traceback", "mivit_decode_grad", "mivit_plan_destroy",
     "mivit_plan_get_info", "mivit_plan_describe", "mivit_quantize_i8", "mivit_strerror",
     "mivit_version", "mivit_pipe_create", "mivit_pipe_run", "mivit_pipe_destroy",
+    "mivit_stream_create", "mivit_stream_push", "mivit_stream_finish", "mivit_stream_destroy",
 )
 MIVIT_PLAN_GRAPH, MIVIT_PLAN_AUTOTUNE, MIVIT_PLAN_PERSISTENT = 1, 2, 4
 
@@ -113,6 +114,15 @@ def load(path: str = LIB_PATH):
     lib.mivit_pipe_run.argtypes = [vp, vp, vp, vp, i64]
     lib.mivit_pipe_destroy.restype = ctypes.c_int
     lib.mivit_pipe_destroy.argtypes = [vp]
+    lib.mivit_stream_create.restype = ctypes.c_int
+    lib.mivit_stream_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Code),
+                                        ctypes.POINTER(Opts), ctypes.c_uint32, i64]
+    lib.mivit_stream_push.restype = ctypes.c_int
+    lib.mivit_stream_push.argtypes = [vp, vp, i64, vp, ctypes.POINTER(i64), vp]
+    lib.mivit_stream_finish.restype = ctypes.c_int
+    lib.mivit_stream_finish.argtypes = [vp, vp, ctypes.POINTER(i64), vp]
+    lib.mivit_stream_destroy.restype = ctypes.c_int
+    lib.mivit_stream_destroy.argtypes = [vp]
     _lib = lib
     return lib
 

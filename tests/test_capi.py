@@ -167,6 +167,31 @@ def test_pipe_null_arguments():
     assert lib.mivit_pipe_destroy(None) == _capi.MIVIT_EINVAL
 
 
+def test_stream_invalid_arguments():
+    """Stream objects: argument checks that need no device."""
+    lib = _capi.load()
+    h = ctypes.c_void_p()
+    o = _capi.Opts()
+    o.dtype, o.chunk, o.overlap = _capi.MIVIT_I8, 2048, 64
+    assert lib.mivit_stream_create(None, ctypes.byref(K7), ctypes.byref(o), 1, 1024) == \
+        _capi.MIVIT_EINVAL
+    assert lib.mivit_stream_create(ctypes.byref(h), None, ctypes.byref(o), 1, 1024) == \
+        _capi.MIVIT_EINVAL
+    assert lib.mivit_stream_create(ctypes.byref(h), ctypes.byref(K7), None, 1, 1024) == \
+        _capi.MIVIT_EINVAL
+    for chunk, overlap, flags, maxp in [(0, 64, 1, 1024), (100, 64, 1, 1024), (2048, -1, 1, 1024),
+                                        (2048, 64, 8, 1024), (2048, 64, 1, 0),
+                                        (2048, 1 << 30, 1, 1024)]:
+        o.chunk, o.overlap = chunk, overlap
+        assert lib.mivit_stream_create(ctypes.byref(h), ctypes.byref(K7), ctypes.byref(o), flags,
+                                       maxp) == _capi.MIVIT_EINVAL
+        assert not h.value
+    nb = ctypes.c_int64()
+    assert lib.mivit_stream_push(None, None, 0, None, ctypes.byref(nb), None) == _capi.MIVIT_EINVAL
+    assert lib.mivit_stream_finish(None, None, ctypes.byref(nb), None) == _capi.MIVIT_EINVAL
+    assert lib.mivit_stream_destroy(None) == _capi.MIVIT_EINVAL
+
+
 def test_null_and_misc():
     lib = _capi.load()
     assert lib.mivit_plan_create(None, None, 0, None, 0, None) == _capi.MIVIT_EINVAL

@@ -692,6 +692,57 @@ def test_binding_rejects_bad_tensors():
     assert w is bits
 
 
+@pytest.mark.parametrize("dtype,chunk,overlap,end_zero,radix", [
+    ("i8", 2048, 64, False, 4), ("i8", 256, 33, True, 0), ("f32", 64, 100, False, 0),
+    ("f16", 96, 40, True, 0)])
+def test_stream_pushes_match_oracle(dtype, chunk, overlap, end_zero, radix):
+    """A stream pushed in pieces of seeded sizes (empty, one stage, less than
+    a chunk, several chunks) gives, concatenated, the oracle's bits for the
+    same windows; every push emits whole chunks."""
+    from workload import int8_scale_for
+    code = CODE_K7
+    n = 20017
+    msg, llr = make_stream(code, n, 3.0, seed=41 + chunk)
+    if dtype == "i8":
+        llr = oracle.quantize_i8(llr, int8_scale_for(3.0, 2))
+        mode = oracle.I64
+    else:
+        mode = oracle.F32
+        if dtype == "f16":
+            llr = llr.astype(np.float16)
+    ref = llr.astype(np.float32) if dtype == "f16" else llr
+    ofr = oracle.chunked_frames(code, n, chunk, overlap)
+    if end_zero:
+        ofr[-1]["end_state"] = 0
+    ob, _, _, _ = oracle.decode_frames([code], ofr, ref, mode, n)
+    rng = np.random.default_rng(7 + chunk)
+    maxp = 3000
+    choices = [0, 1, 5, 31, chunk - 1, chunk, chunk + 1, 2 * chunk + 7, maxp]
+    sizes, left = [], n
+    while left > 0:
+        k = int(rng.choice(choices)) if rng.random() < 0.6 else int(rng.integers(0, maxp + 1))
+        k = min(k, maxp, left)
+        sizes.append(k)
+        left -= k
+    print("stream pushes", dtype, chunk, overlap, end_zero, radix, len(sizes), flush=True)
+    t = torch.from_numpy(np.ascontiguousarray(llr)).to(DEV)
+    dec = mv.StreamDecoder(code, dtype, chunk, overlap, max_push_stages=maxp, radix=radix,
+                           end_zero=end_zero)
+    out, pos = [], 0
+    for k in sizes:
+        words, nb = dec.push(t[pos * code.beta:(pos + k) * code.beta])
+        assert nb % chunk == 0
+        out.append(mv.unpack_bits(words.cpu().numpy(), nb))
+        pos += k
+    words, nb = dec.finish()
+    out.append(mv.unpack_bits(words.cpu().numpy(), nb))
+    dec.close()
+    bits = np.concatenate(out)
+    assert bits.size == n
+    np.testing.assert_array_equal(bits, ob)
+    assert (bits[: n - 200] != msg[: n - 200]).sum() < 100
+
+
 @pytest.mark.parametrize("depth", [2, 3])
 def test_pipeline_matches_decode(depth):
     """Batches decoded by the host pipeline (copy in, decode, copy out on
