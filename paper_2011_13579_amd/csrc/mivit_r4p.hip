@@ -258,7 +258,7 @@ __device__ __forceinline__ void block(Fwd<ND>& F, int it0) {
       const uint32_t b = (uint32_t)__builtin_amdgcn_sdot4((int)F.w1, F.sgn[e], kBias, false);
       t[e] = a | (b << 16);
     }
-    uint4* dst = (uint4*)(F.tbl + F.ib * 16 + (F.r >> 4) * PPL);
+    uint4* dst = (uint4*)(F.tbl + F.ib * 16 + (F.r % (16 / PPL)) * PPL);
 #pragma unroll
     for (int e = 0; e < PPL / 4; ++e) dst[e] = make_uint4(t[4 * e], t[4 * e + 1], t[4 * e + 2], t[4 * e + 3]);
   }
@@ -359,7 +359,9 @@ __device__ __forceinline__ void fwd_r4p_wave(const DevCode* __restrict__ codes,
   F.tbl = &tbl_w[m][0];
   F.r = r;
   F.n_it = n_it;
-  F.ib = r & 15;
+  // lanes 4k .. 4k+3 (K = 7) fill row k, so one 16-byte store per lane
+  // covers the table contiguously (no LDS bank conflicts)
+  F.ib = r / (16 / PPL);
   F.store = va;
   F.sv = (uint32_t*)(surv + ita.surv_off);
   F.l0 = llr + ita.llr_off + 2 * lead;
@@ -368,7 +370,7 @@ __device__ __forceinline__ void fwd_r4p_wave(const DevCode* __restrict__ codes,
   F.acc = 0;
 #pragma unroll
   for (int e = 0; e < PPL; ++e) {
-    const int p = (r >> 4) * PPL + e;
+    const int p = (r % (16 / PPL)) * PPL + e;
     uint32_t s = 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) s |= (((p >> b) & 1) ? 0xFCu : 0x04u) << (8 * b);
