@@ -7,11 +7,14 @@
 // previous states (Eq. (radix2:S): 2f and 2f+1) of the state at position p
 // sit at the positions p with bit q cleared and set, and the new state stays
 // at p.  For q < 6 that is an exchange between lanes, done for each of the R
-// registers (DPP quad permutations for bits 0 and 1, ds_swizzle for bits 2
-// and 3, v_permlane16/32_swap for bits 4 and 5); for q >= 6 the two previous
-// states are two registers of the same lane and nothing moves.  The R
-// registers are independent dependency chains, which keeps a lone wavefront
-// busy.
+// registers: DPP quad permutations fetch both previous metrics for bits 0
+// and 1, v_permlane16/32_swap for bits 4 and 5.  For bits 2 and 3, float
+// metrics stay in the VALU: a lane keeps its own previous state's metric and
+// fetches its partner's (lane ^ 4: row half-mirror then quad reverse; lane ^
+// 8: row rotate by 8); integer metrics fetch both through ds_swizzle, which
+// measured faster for them.  For q >= 6 the two previous states are two
+// registers of the same lane and nothing moves.  The R registers are independent dependency
+// chains, which keeps a lone wavefront busy.
 //
 // Branch metrics: Eq. (BM) for the even previous state on the new state's
 // input; by the corollary of §IV the odd previous state's branch has the
@@ -104,6 +107,26 @@ __device__ __forceinline__ void pair_fetch(typename Ty<DT>::T x, typename Ty<DT>
   o = Ty<DT>::from(oi);
 }
 
+// Stages at lane bits 2 and 3 in own/partner form (float metrics).
+template <int DT, int Q>
+constexpr bool own_partner() {
+  return (Q == 2 || Q == 3) && !Ty<DT>::kInt;
+}
+
+// Metric of the partner lane (lane ^ 2^Q) for Q = 2, 3.
+template <int Q, int DT>
+__device__ __forceinline__ typename Ty<DT>::T partner_fetch(typename Ty<DT>::T x) {
+  const int xi = Ty<DT>::bits(x);
+  int pi;
+  if constexpr (Q == 2) {
+    const int hm = __builtin_amdgcn_mov_dpp(xi, 0x141, 0xF, 0xF, true);  // row_half_mirror: ^7
+    pi = __builtin_amdgcn_mov_dpp(hm, 0x1B, 0xF, 0xF, true);            // quad_perm [3,2,1,0]: ^3
+  } else {
+    pi = __builtin_amdgcn_mov_dpp(xi, 0x128, 0xF, 0xF, true);  // row_ror:8
+  }
+  return Ty<DT>::from(pi);
+}
+
 template <int DT, int R>
 struct Wave {
   using T = typename Ty<DT>::T;
@@ -122,13 +145,28 @@ __device__ __forceinline__ T acs(T e, T o, T m, bool& d) {
   return d ? co : ce;
 }
 
-// One stage at phase Q; bm[r] the branch metric of position 64r + lane.
+// One stage at phase Q; bm[r] the branch metric of position 64r + lane: of
+// its even previous state, or in own/partner form of its own previous state
+// (the state at position 64r + lane before the stage).  Own/partner form: the
+// candidates are own + bm and partner - bm in every lane (by the corollary
+// the other previous state's branch has the opposite value); the odd
+// previous state won when partner > own where the lane's bit Q is 0 and
+// own > partner where it is 1, strictly, so a tie keeps the even state.
 template <int KM1, int DT, int R, int Q>
 __device__ __forceinline__ void stage(Wave<DT, R>& W, const typename Ty<DT>::T (&bm)[R]) {
   using T = typename Ty<DT>::T;
   T nv[R];
   bool d[R];
-  if constexpr (Q < 6) {
+  if constexpr (own_partner<DT, Q>()) {
+    const bool own_odd = ((threadIdx.x >> Q) & 1) != 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const T cp = partner_fetch<Q, DT>(W.pm[r]) - bm[r];
+      const T co = W.pm[r] + bm[r];
+      nv[r] = cp > co ? cp : co;
+      d[r] = own_odd ? (co > cp) : (cp > co);
+    }
+  } else if constexpr (Q < 6) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       T e, o;
@@ -305,8 +343,13 @@ __global__ __launch_bounds__(64 * wide::kWideWaves) void k_fwd_wide(
   for (int q = 0; q < KM1; ++q) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
+      // the new state at position p = 64r + lane, and the previous state
+      // whose branch the stage's metric table entry gives: the even one, or
+      // in own/partner form the one at p (odd when bit q of p is set)
       const int j = rotr(64 * r + lane, (q + 1) % KM1, KM1);
-      pat[q][r] = branch_out(c, (j << 1) & (NS - 1), j >> (KM1 - 1));
+      const bool op = (q == 2 || q == 3) && !Ty<DT>::kInt;
+      const int own = op ? ((lane >> q) & 1) : 0;
+      pat[q][r] = branch_out(c, ((j << 1) | own) & (NS - 1), j >> (KM1 - 1));
     }
   }
   Wave<DT, R> W;
