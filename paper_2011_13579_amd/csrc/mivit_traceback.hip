@@ -120,6 +120,9 @@ __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_
   const int B0 = go ? (c.top - 1) / SB : 0;
   const int nb = go ? B0 - c.a / SB + 1 : 0;
   int t = c.top - 1;  // next stage to step over
+  // rotating layouts: rotation (t + 1) mod (K-1) of the state's position,
+  // stepped down with t (no division in the chase)
+  int rot = (go && (LAYOUT == kLayoutRotR2 || LAYOUT == kLayoutRotByte)) ? c.top % g.KM1 : 0;
   if (nb > 0) fetch_block(sv + (int64_t)B0 * WB, lds);
   for (int r = 0;; ++r) {
     if (__ballot(r < nb) == 0) break;
@@ -129,11 +132,12 @@ __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_
     if (r + 1 < nb) fetch_block(sv + (int64_t)(B0 - r - 1) * WB, nxt);
     if (r < nb) {
       const int B = B0 - r;
+      const int t0 = B * SB;  // first stage of the block: t - t0 = t mod SB
       int j = c.j;
       if (LAYOUT == kLayoutNatR4) {
-        if ((S & 1) && t == S - 1 && t >= B * SB) {
+        if ((S & 1) && t == S - 1 && t >= t0) {
           // odd stage count: the last stage was a radix-2 stage
-          const int w = (t % SB) * 2 * g.W + (j >> 5);
+          const int w = (t - t0) * 2 * g.W + (j >> 5);
           const int d = (word_at(cur, w, lane) >> (j & 31)) & 1;
           if (t >= c.a && t < c.b) em.put(t - ob, j >> (g.KM1 - 1), bits, bit_off);
           j = ((j << 1) | d) & (g.NS - 1);
@@ -142,9 +146,9 @@ __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_
           --t;
         }
         // pairs (t-1, t), t odd; pairs never straddle a block
-        for (; t > B * SB && t >= c.a; t -= 2) {
-          const int w0 = ((t - 1) % SB) * 2 * g.W + (j >> 5);
-          const int w1 = (t % SB) * 2 * g.W + (j >> 5);
+        for (; t > t0 && t >= c.a; t -= 2) {
+          const int w0 = (t - 1 - t0) * 2 * g.W + (j >> 5);
+          const int w1 = (t - t0) * 2 * g.W + (j >> 5);
           const int yy = ((word_at(cur, w0, lane) >> (j & 31)) & 1) |
                          (((word_at(cur, w1, lane) >> (j & 31)) & 1) << 1);
           if (t < c.b) em.put(t - ob, j >> (g.KM1 - 1), bits, bit_off);
@@ -156,8 +160,8 @@ __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_
         }
       } else if (LAYOUT == kLayoutNatR8) {
         // the S mod 3 last stages were radix-2 stages
-        for (; t >= S - S % 3 && t >= B * SB && t >= c.a; --t) {
-          const int w = (t % SB) * 2 * g.W + (j >> 5);
+        for (; t >= S - S % 3 && t >= t0 && t >= c.a; --t) {
+          const int w = (t - t0) * 2 * g.W + (j >> 5);
           const int d = (word_at(cur, w, lane) >> (j & 31)) & 1;
           if (t < c.b) em.put(t - ob, j >> (g.KM1 - 1), bits, bit_off);
           j = ((j << 1) | d) & (g.NS - 1);
@@ -165,9 +169,9 @@ __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_
           if (t == c.xa) c.x = j;
         }
         // triples (t-2, t-1, t), t = 2 mod 3; triples never straddle a block
-        for (; t >= B * SB + 2 && t >= c.a; t -= 3) {
+        for (; t >= t0 + 2 && t >= c.a; t -= 3) {
           const int sh = j & 31;
-          const int w2 = (t % SB) * 2 * g.W + (j >> 5);
+          const int w2 = (t - t0) * 2 * g.W + (j >> 5);
           const int w1 = w2 - 2 * g.W, w0 = w1 - 2 * g.W;
           const int yy = ((word_at(cur, w0, lane) >> sh) & 1) |
                          (((word_at(cur, w1, lane) >> sh) & 1) << 1) |
@@ -182,24 +186,25 @@ __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_
           if (t - 2 == c.xa) c.x = j;
         }
       } else {
-        const int lo = max(c.a, B * SB);
+        const int lo = max(c.a, t0);
         for (; t >= lo; --t) {
           int d;
           if (LAYOUT == kLayoutRotR2) {
-            const int w = rotl_bits(j, (t + 1) % g.KM1, g.KM1);
+            const int w = rotl_bits(j, rot, g.KM1);
             d = (word_at(cur, w, lane) >> (31 - (t & 31))) & 1;
           } else if (LAYOUT == kLayoutRotByte) {
-            const int p = rotl_bits(j, (t + 1) % g.KM1, g.KM1);
-            const int w = ((t % SB) >> 3) * (g.NS >> 2) + (p >> 2);
+            const int p = rotl_bits(j, rot, g.KM1);
+            const int w = ((t - t0) >> 3) * (g.NS >> 2) + (p >> 2);
             d = (word_at(cur, w, lane) >> (8 * (p & 3) + 7 - (t & 7))) & 1;
           } else {
-            const int w = (t % SB) * 2 * g.W + (j >> 5);
+            const int w = (t - t0) * 2 * g.W + (j >> 5);
             d = (word_at(cur, w, lane) >> (j & 31)) & 1;
           }
           if (t < c.b) em.put(t - ob, j >> (g.KM1 - 1), bits, bit_off);
           j = ((j << 1) | d) & (g.NS - 1);
           if (t == c.yb) c.y = j;
           if (t == c.xa) c.x = j;
+          rot = rot == 0 ? g.KM1 - 1 : rot - 1;
         }
       }
       c.j = j;
