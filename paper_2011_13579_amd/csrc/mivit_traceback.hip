@@ -61,6 +61,13 @@ struct TbGeom {
   }
 };
 
+// Rotating radix-2 layout: the chase holds the state as the byte offset, in
+// a staged buffer, of the word of its position p: (p >> 2) * 1024 +
+// (p & 3) * 4 (plus the lane's 16-byte slot).  Position bit q is offset bit
+// pos_bit(q).
+__device__ __forceinline__ int pos_off(int p) { return ((p >> 2) << 10) | ((p & 3) << 2); }
+__device__ __forceinline__ int pos_bit(int q) { return q < 2 ? q + 2 : q + 8; }
+
 __device__ __forceinline__ int rotl_bits(int x, int r, int n) {
   // rotate the n-bit value x left by r (0 <= r < n)
   return ((x << r) | (x >> (n - r))) & ((1 << n) - 1);
@@ -94,7 +101,9 @@ __device__ __forceinline__ uint32_t word_at(const uint32_t* buf_k, int w, int la
 }
 
 // Per-lane chase state.  Times are stage boundaries: time t is the state
-// entering stage t.  In the natural radix-4 layout the decisions of a stage
+// entering stage t.  In the rotating radix-2 layout the states j, x, y are
+// held as position offsets (pos_off of the state's position at that time),
+// which compare like states at one time.  In the natural radix-4 layout the decisions of a stage
 // pair (2k, 2k+1) only name the state two stages back, so states are known
 // (and compared between segments) at pair-aligned times: even times and S.
 // In the radix-8 layout they are the multiples of 3 and the times of the
@@ -185,14 +194,28 @@ __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_
           if (t - 2 == c.yb) c.y = j;
           if (t - 2 == c.xa) c.x = j;
         }
+      } else if (LAYOUT == kLayoutRotR2) {
+        // j: position offset at time t + 1.  Stepping over stage t replaces
+        // position bit t mod (K-1) by the decision (the predecessor's
+        // position); that bit held the stage's decoded input bit.
+        const char* cl = (const char*)cur + lane * 16;
+        const int lo = max(c.a, t0);
+        for (; t >= lo; --t) {
+          const int q = rot == 0 ? g.KM1 - 1 : rot - 1;  // t mod (K-1)
+          const int a = pos_bit(q);
+          const uint32_t word = *(const uint32_t*)(cl + j);
+          const int d = (int)((word >> (31 - (t & 31))) & 1u);
+          if (t < c.b) em.put(t - ob, (j >> a) & 1, bits, bit_off);
+          j = (j & ~(1 << a)) | (d << a);
+          if (t == c.yb) c.y = j;
+          if (t == c.xa) c.x = j;
+          rot = q;
+        }
       } else {
         const int lo = max(c.a, t0);
         for (; t >= lo; --t) {
           int d;
-          if (LAYOUT == kLayoutRotR2) {
-            const int w = rotl_bits(j, rot, g.KM1);
-            d = (word_at(cur, w, lane) >> (31 - (t & 31))) & 1;
-          } else if (LAYOUT == kLayoutRotByte) {
+          if (LAYOUT == kLayoutRotByte) {
             const int p = rotl_bits(j, rot, g.KM1);
             const int w = ((t - t0) >> 3) * (g.NS >> 2) + (p >> 2);
             d = (word_at(cur, w, lane) >> (8 * (p & 3) + 7 - (t & 7))) & 1;
@@ -247,12 +270,15 @@ __global__ __launch_bounds__(64) void k_tb_seg(const DevCode* __restrict__ codes
   c.top = active ? ((lane == G - 1) ? S : min(S, align(c.b + warm))) : c.a;
   const bool exact = active && c.top == S;
   c.j = exact ? item_end[it.slot] : 0;
+  if (LAYOUT == kLayoutRotR2 && exact) c.j = pos_off(rotl_bits(c.j, S % g.KM1, g.KM1));
+  // mask of the state bits (of the offset bits for the rotating radix-2 layout)
+  const int state_mask = LAYOUT == kLayoutRotR2 ? pos_off(g.NS - 1) : g.NS - 1;
   c.x = c.y = -1;
   chase_all<LAYOUT>(g, sv, lds, c, active && c.top > c.a, ob, S, bits, it.bit_off);
   // repair rounds: lane g is right when its state at yb equals lane g+1's
   // state at its xa (the same time)
   for (int round = 0; round <= G; ++round) {
-    const int x_up = __shfl_down(c.x, 1) & (g.NS - 1);
+    const int x_up = __shfl_down(c.x, 1) & state_mask;
     const bool bad = active && !exact && lane < G - 1 && c.y != x_up;
     if (__ballot(bad) == 0) break;
     // lanes that agree with their neighbour stay idle this round
