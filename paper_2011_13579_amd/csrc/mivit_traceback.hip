@@ -101,9 +101,9 @@ __device__ __forceinline__ uint32_t word_at(const uint32_t* buf_k, int w, int la
 }
 
 // Per-lane chase state.  Times are stage boundaries: time t is the state
-// entering stage t.  In the rotating radix-2 layout the states j, x, y are
-// held as position offsets (pos_off of the state's position at that time),
-// which compare like states at one time.  In the natural radix-4 layout the decisions of a stage
+// entering stage t.  In the rotating layouts the states j, x, y are held as
+// the state's position at that time (radix 2: as its offset, pos_off), which
+// compare like states at one time.  In the natural radix-4 layout the decisions of a stage
 // pair (2k, 2k+1) only name the state two stages back, so states are known
 // (and compared between segments) at pair-aligned times: even times and S.
 // In the radix-8 layout they are the multiples of 3 and the times of the
@@ -129,8 +129,8 @@ __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_
   const int B0 = go ? (c.top - 1) / SB : 0;
   const int nb = go ? B0 - c.a / SB + 1 : 0;
   int t = c.top - 1;  // next stage to step over
-  // rotating layouts: rotation (t + 1) mod (K-1) of the state's position,
-  // stepped down with t (no division in the chase)
+  // rotating layouts: rotation (t + 1) mod (K-1) of the positions, stepped
+  // down with t (no division in the chase)
   int rot = (go && (LAYOUT == kLayoutRotR2 || LAYOUT == kLayoutRotByte)) ? c.top % g.KM1 : 0;
   if (nb > 0) fetch_block(sv + (int64_t)B0 * WB, lds);
   for (int r = 0;; ++r) {
@@ -211,23 +211,29 @@ __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_
           if (t == c.xa) c.x = j;
           rot = q;
         }
+      } else if (LAYOUT == kLayoutRotByte) {
+        // j: position at time t + 1 (as for the rotating radix-2 layout,
+        // a step replaces position bit t mod (K-1) by the decision)
+        const int lo = max(c.a, t0);
+        for (; t >= lo; --t) {
+          const int q = rot == 0 ? g.KM1 - 1 : rot - 1;  // t mod (K-1)
+          const int w = ((t - t0) >> 3) * (g.NS >> 2) + (j >> 2);
+          const int d = (word_at(cur, w, lane) >> (8 * (j & 3) + 7 - (t & 7))) & 1;
+          if (t < c.b) em.put(t - ob, (j >> q) & 1, bits, bit_off);
+          j = (j & ~(1 << q)) | (d << q);
+          if (t == c.yb) c.y = j;
+          if (t == c.xa) c.x = j;
+          rot = q;
+        }
       } else {
         const int lo = max(c.a, t0);
         for (; t >= lo; --t) {
-          int d;
-          if (LAYOUT == kLayoutRotByte) {
-            const int p = rotl_bits(j, rot, g.KM1);
-            const int w = ((t - t0) >> 3) * (g.NS >> 2) + (p >> 2);
-            d = (word_at(cur, w, lane) >> (8 * (p & 3) + 7 - (t & 7))) & 1;
-          } else {
-            const int w = (t - t0) * 2 * g.W + (j >> 5);
-            d = (word_at(cur, w, lane) >> (j & 31)) & 1;
-          }
+          const int w = (t - t0) * 2 * g.W + (j >> 5);
+          const int d = (word_at(cur, w, lane) >> (j & 31)) & 1;
           if (t < c.b) em.put(t - ob, j >> (g.KM1 - 1), bits, bit_off);
           j = ((j << 1) | d) & (g.NS - 1);
           if (t == c.yb) c.y = j;
           if (t == c.xa) c.x = j;
-          rot = rot == 0 ? g.KM1 - 1 : rot - 1;
         }
       }
       c.j = j;
@@ -270,6 +276,8 @@ __global__ __launch_bounds__(64) void k_tb_seg(const DevCode* __restrict__ codes
   c.top = active ? ((lane == G - 1) ? S : min(S, align(c.b + warm))) : c.a;
   const bool exact = active && c.top == S;
   c.j = exact ? item_end[it.slot] : 0;
+  // rotating layouts chase positions: the state's at time S
+  if (LAYOUT == kLayoutRotByte && exact) c.j = rotl_bits(c.j, S % g.KM1, g.KM1);
   if (LAYOUT == kLayoutRotR2 && exact) c.j = pos_off(rotl_bits(c.j, S % g.KM1, g.KM1));
   // mask of the state bits (of the offset bits for the rotating radix-2 layout)
   const int state_mask = LAYOUT == kLayoutRotR2 ? pos_off(g.NS - 1) : g.NS - 1;
