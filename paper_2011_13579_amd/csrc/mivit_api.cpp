@@ -825,11 +825,15 @@ mivit_status mivit_plan_describe(const mivit_plan* p, char* buf, int32_t len) {
   for (const Part& q : p->parts) {
     char line[256];
     for (const PlanGroup& g : q.groups) {
+      // the rotating kernels run a wave table; the others one wavefront per item
+      const bool table = g.kern == kKernRot2 || g.kern == kKernRot4P;
       std::snprintf(line, sizeof line,
                     "%scode %d: K=%d beta=%d, %s forward, variant %d, %s, %d items, %d wavefronts",
                     s.empty() ? "" : "; ", q.code, g.K, g.beta, kern_name(g.kern), q.ch.variant,
-                    g.counter >= 0 ? "persistent work queue" : "one wavefront per table entry",
-                    g.count, g.n_waves);
+                    g.counter >= 0 ? "persistent work queue"
+                    : table        ? "one wavefront per table entry"
+                                   : "one wavefront per item",
+                    g.count, table ? g.n_waves : g.count);
       s += line;
     }
   }

@@ -472,6 +472,8 @@ def test_mixed_codes_batch(dtype, mode):
     desc = plan.describe()
     print(desc, flush=True)
     assert desc.count("code ") == 3
+    # the K=9 rate-1/3 part never runs a rotating wave table
+    assert "K=9 beta=3" in desc and "one wavefront per item" in desc
     if mode == "persistent":
         assert "persistent work queue" in desc
     _check_mixed(codes, plan, fr, ofr, llr, dtype, n_bits)
