@@ -105,18 +105,21 @@ def time_variant(torch, mv, plan, llr, steps, warmup):
         plan.forward(llr, metric, end)
         plan.traceback(bits)
     torch.cuda.synchronize()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    # events on the launch stream: a[k] before step k's forward, b[k] between
+    # its forward and traceback; a[steps] closes the last step
+    a = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    b = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     t0 = time.perf_counter()
     for k in range(steps):
-        ev[k][0].record(st)
+        a[k].record(st)
         plan.forward(llr, metric, end)
-        ev[k][1].record(st)
+        b[k].record(st)
         plan.traceback(bits)
-        ev[k][2].record(st)
+    a[steps].record(st)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
-    fwd = float(np.mean([ev[k][0].elapsed_time(ev[k][1]) for k in range(steps)]))
-    tb = float(np.mean([ev[k][1].elapsed_time(ev[k][2]) for k in range(steps)]))
+    fwd = float(np.mean([a[k].elapsed_time(b[k]) for k in range(steps)]))
+    tb = float(np.mean([b[k].elapsed_time(a[k + 1]) for k in range(steps)]))
     return wall * 1e3, fwd, tb, bits, metric
 
 
