@@ -123,10 +123,11 @@ def time_variant(torch, mv, plan, llr, steps, warmup):
     return wall * 1e3, fwd, tb, bits, metric
 
 
-def cpu_baseline(code, llr_i8_np):
+def cpu_baseline(code, llr_i8_np, gpu_bits):
     """The CPU oracle (exact-integer radix-2, C, -O2, one thread per core over
     frames) on the same int8 soft values: the whole batch, median of 5 runs;
-    plus one thread on the first 128 frames."""
+    plus one thread on the first 128 frames.  Its decoded bits are compared
+    with the headline variant's bits of the same batch."""
     import oracle
     threads = oracle.default_threads()
     n = llr_i8_np.shape[0]
@@ -134,17 +135,22 @@ def cpu_baseline(code, llr_i8_np):
     times = []
     for _ in range(5):
         t0 = time.perf_counter()
-        oracle.decode_uniform(code, llr_i8_np, N_INFO, True, oracle.I64, n_threads=threads)
+        ob, _, _ = oracle.decode_uniform(code, llr_i8_np, N_INFO, True, oracle.I64,
+                                         n_threads=threads)
         times.append(time.perf_counter() - t0)
     dt = float(np.median(times))
     t0 = time.perf_counter()
     oracle.decode_uniform(code, llr_i8_np[:128], N_INFO, True, oracle.I64, n_threads=1)
     dt1 = time.perf_counter() - t0
-    return {"value": round(n * N_INFO / dt / 1e9, 6), "unit": "Gbit/s", "cores": threads,
-            "kind": "oracle",
-            "sample": "the whole batch (%d frames x %d bits), exact-integer radix-2 oracle, "
-                      "median of 5 runs (%.2f s each)" % (n, N_INFO, dt),
-            "single_thread_gbit_s": round(128 * N_INFO / dt1 / 1e9, 6)}
+    out = {"value": round(n * N_INFO / dt / 1e9, 6), "unit": "Gbit/s", "cores": threads,
+           "kind": "oracle",
+           "sample": "the whole batch (%d frames x %d bits), exact-integer radix-2 oracle, "
+                     "median of 5 runs (%.2f s each)" % (n, N_INFO, dt),
+           "single_thread_gbit_s": round(128 * N_INFO / dt1 / 1e9, 6)}
+    if gpu_bits is not None:
+        out["mismatches"] = int((ob != gpu_bits).sum())
+        out["mismatched_frames"] = int((ob != gpu_bits).any(axis=1).sum())
+    return out
 
 
 def ber_sweep(torch, mv, code, frames_plan_i8, frames_plan_f32, frames_plan_f16=None):
@@ -362,6 +368,7 @@ def main():
         del src, dst
     plans = {}
     results = {}
+    decoded = {}
     for v in args.variants.split(","):
         base, _, kv = v.partition(":")
         dt, radix = {"i8r4": ("i8", 4), "f32r2": ("f32", 2), "f16r2": ("f16", 2),
@@ -370,6 +377,7 @@ def main():
         llr = {"i8": llr_i8, "f32": llr_f32, "f16": llr_f16}[dt]
         ms, fwd, tb, bits, _ = time_variant(torch, mv, plans[v], llr, args.steps, args.warmup)
         dec = mv.unpack_bits(bits.cpu().numpy()[: N_FRAMES * (N_INFO // 32)].reshape(N_FRAMES, -1), N_INFO)
+        decoded[v] = dec
         peak = VALU16_PEAK_TOPS if base in PACKED16 and not kv else VALU32_PEAK_TOPS
         results[v] = {
             "gbit_s": round(N_FRAMES * N_INFO / (ms * 1e-3) / 1e9, 3),
@@ -377,10 +385,17 @@ def main():
             "forward_tops": round(ops_per_launch / (fwd * 1e-3) / 1e12, 3),
             "forward_peak_tops": round(peak, 2),
             "forward_frac": round(ops_per_launch / (fwd * 1e-3) / 1e12 / peak, 4),
+            "end_to_end_frac": round(ops_per_launch / (ms * 1e-3) / 1e12 / peak, 4),
             "bit_errors": int((dec != b.msg).sum()),
         }
     head = results.get("i8r4") or next(iter(results.values()))
     hv = "i8r4" if "i8r4" in results else next(iter(results))
+    # the float32 -> int8 quantiser runs once per batch before the timed
+    # step; its time, and the rate with it inside the step
+    qt = torch.empty_like(llr_i8)
+    quant_ms = _gpu_ms(torch, lambda: mv.quantize_i8(llr_f32, int8_scale_for(args.ebn0, code.beta),
+                                                      out=qt), 20)
+    del qt
     achieved = ops_per_launch / (head["forward_ms"] * 1e-3) / 1e12
     peak = head["forward_peak_tops"]
     line = {
@@ -404,7 +419,18 @@ def main():
                      "frac": round(achieved / peak, 4), "traffic": measured_traffic(hv),
                      "kernel": "forward (%s)" % hv,
                      "peak_basis": "packed 16-bit VALU" if peak > VALU32_PEAK_TOPS else "32-bit VALU",
-                     "work": "3 ops x 64 states x %d stages x %d frames per launch" % (S, N_FRAMES)},
+                     "work": "3 ops x 64 states x %d stages x %d frames per launch (the "
+                             "same count for every radix: 2 adds and a compare-select per "
+                             "state and stage)" % (S, N_FRAMES),
+                     "end_to_end_frac": head["end_to_end_frac"],
+                     "binding_kernel": "forward"},
+        "quantizer": {"in_timed_step": False, "ms": round(quant_ms, 4),
+                      "gbit_s_with_quantizer": round(N_FRAMES * N_INFO /
+                                                     ((head["ms_per_step"] + quant_ms) * 1e-3)
+                                                     / 1e9, 3),
+                      "note": "float32 -> int8 soft values (mivit_quantize_i8) of the whole "
+                              "batch; the headline step decodes int8 soft values already in "
+                              "HBM"},
         "variants": results,
     }
     if args.configs:
@@ -412,7 +438,7 @@ def main():
     if args.pcie and "i8r4" in plans:
         line["pcie_inclusive"] = pcie_pipeline(torch, mv, plans["i8r4"], llr_i8)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(code, llr_i8.cpu().numpy())
+        line["cpu_baseline"] = cpu_baseline(code, llr_i8.cpu().numpy(), decoded.get("i8r4"))
     if args.ber:
         line["equal_ber"] = ber_sweep(torch, mv, code, plans.get("i8r4"), plans.get("f32r2"),
                                       plans.get("f16r2"))

@@ -186,10 +186,42 @@ mivit_status mivit_traceback(mivit_plan* plan, uint32_t* bits, void* stream);
  * where c is the codeword of the decoded bits (re-encoded, §II-A; tail bits
  * of terminated frames are zero).  bits is the output of mivit_decode for the
  * same plan; grad_metric and grad_llr are device float32.  Plans with chunked
- * frames or frames whose emitted bits do not cover every stage but a zero
- * tail are rejected with MIVIT_EUNSUPPORTED. */
+ * frames, frames without MIVIT_START_KNOWN (the re-encoding starts from state
+ * 0) or frames whose emitted bits do not cover every stage but a zero tail
+ * are rejected with MIVIT_EUNSUPPORTED. */
 mivit_status mivit_decode_grad(mivit_plan* plan, const uint32_t* bits, const float* grad_metric,
                                float* grad_llr, void* stream);
+
+/* One-call decode of equal-length frames: the input of Algorithm 1 (beta
+ * soft values per stage) for n_frames frames laid out back to back, and the
+ * output of Algorithm 2 (the decoded bits) plus the best path metric of
+ * Eq. (PM), without building a plan.
+ *   llr        device, dtype values; frame f, stage t, value b at element
+ *              f*S*beta + t*beta + b, S = n_info + K - 1 when terminated,
+ *              else n_info.  Read-only.
+ *   dtype      mivit_dtype of the soft values.
+ *   code       host pointer, copied; validated as for mivit_plan_create.
+ *   terminated 1: every frame starts and ends in state 0 (K-1 zero tail
+ *              inputs, not emitted); 0: known start, best final state.
+ *   bits       device uint32 words; frame f writes words [f*W, (f+1)*W),
+ *              W = ceil(n_info/32), bit k of the frame at bit k % 32 of word
+ *              f*W + k/32, the last word zero-padded.  Never NULL.
+ *   metric     device, n_frames values: float32 (float32 and float16 soft
+ *              values) or int64 (int8).  May be NULL.
+ * Kernels: packed radix 4 for int8 soft values of K = 5 or 7 rate-1/2 codes,
+ * radix 2 otherwise; results are those of a plan over the same frames.
+ * Asynchronous on 'stream'.  The library keeps a plan (and its survivor
+ * memory, 2^(K-1) bits per stage and frame) per (device, stream, code,
+ * dtype, n_frames, n_info, terminated), at most 16, releasing the least
+ * recently used one after its stream has drained; calls that overlap on one
+ * stream are ordered by it, calls on different streams never share memory.
+ * n_frames == 0 or zero stages: nothing to do, MIVIT_OK.
+ * Errors: MIVIT_EINVAL (null pointer, negative count, bad dtype or
+ * terminated flag), the code errors of mivit_plan_create, MIVIT_ENOMEM,
+ * MIVIT_EHIP. */
+mivit_status mivit_decode_uniform(const void* llr, int32_t dtype, const mivit_code* code,
+                                  int32_t n_frames, int32_t n_info, int32_t terminated,
+                                  uint32_t* bits, void* metric, void* stream);
 
 /* Release a plan's device and host memory (waits for the device first). */
 mivit_status mivit_plan_destroy(mivit_plan* plan);

@@ -369,10 +369,15 @@ _plan_cache = {}
 
 
 def _cached_plan(key, make):
+    """Plans by (shape, device, stream): a plan owns survivor memory, so one
+    plan only ever serves one stream.  An evicted plan is dropped, not
+    closed: a caller that still holds it (an autograd context between
+    forward and backward) keeps it alive, and it is freed with its last
+    reference."""
     p = _plan_cache.get(key)
     if p is None:
         if len(_plan_cache) >= 8:
-            _plan_cache.pop(next(iter(_plan_cache))).close()
+            _plan_cache.pop(next(iter(_plan_cache)))
         p = make()
         _plan_cache[key] = p
     return p
@@ -388,17 +393,33 @@ def _dtype_name(torch, llr):
 def decode(llr, code, n_info: int, terminated: bool = True, radix: int = 0, stream=None):
     """Equal-length frames.  llr: device tensor [F, S*beta] float32, float16 or int8.
 
+    radix 0 calls mivit_decode_uniform (the library picks the kernel);
+    radix 2, 4 or 8 builds (and caches) a plan with that radix.
     Returns (bit words int32 [F, ceil(N/32)], metric [F]).
     """
     torch = _torch()
     code = _as_code(code)
     F = llr.shape[0] if llr.dim() == 2 else 1
     dt = _dtype_name(torch, llr)
-    key = ("u", code, F, n_info, terminated, dt, radix, llr.device.index)
+    wpf = (n_info + 31) // 32
+    S = n_info + (code.K - 1 if terminated else 0)
+    llr = llr.contiguous()
+    if llr.numel() < F * S * code.beta or not llr.is_cuda:
+        raise ValueError("llr must be a device tensor of at least %d soft values" % (F * S * code.beta))
+    if radix == 0:
+        dtc = {"f32": MIVIT_F32, "i8": MIVIT_I8, "f16": MIVIT_F16}[dt]
+        bits = torch.zeros(max(F * wpf, 1), dtype=torch.int32, device=llr.device)
+        metric = torch.zeros(max(F, 1), dtype=torch.int64 if dt == "i8" else torch.float32,
+                             device=llr.device)
+        st = _capi.load().mivit_decode_uniform(_dptr(llr), dtc, ctypes.byref(code.c_struct()),
+                                               F, int(n_info), int(bool(terminated)), _dptr(bits),
+                                               _dptr(metric), _stream_handle(stream))
+        _capi.check(st, "mivit_decode_uniform")
+        return bits[: F * wpf].view(F, wpf), metric[:F]
+    key = ("u", code, F, n_info, terminated, dt, radix, llr.device.index, _stream_handle(stream))
     plan = _cached_plan(key, lambda: Plan([code], uniform_frames(code, F, n_info, terminated),
                                           dt, radix))
-    bits, metric, _ = plan.decode(llr.contiguous(), stream=stream)
-    wpf = (n_info + 31) // 32
+    bits, metric, _ = plan.decode(llr, stream=stream)
     return bits[: F * wpf].view(F, wpf), metric[:F]
 
 
@@ -412,7 +433,7 @@ def decode_stream(llr, code, n_info: int, chunk: int = 2048, overlap: int = 64, 
     dt = _dtype_name(torch, llr)
     fr = np.zeros(1, FRAME_DTYPE)
     fr[0] = (0, 0, n_info, 0, n_info, 0, MIVIT_START_KNOWN)
-    key = ("s", code, n_info, chunk, overlap, dt, radix, llr.device.index)
+    key = ("s", code, n_info, chunk, overlap, dt, radix, llr.device.index, _stream_handle(stream))
     plan = _cached_plan(key, lambda: Plan([code], fr, dt, radix, chunk, overlap))
     bits, metric, end = plan.decode(llr.contiguous(), stream=stream)
     return bits[: (n_info + 31) // 32]
@@ -455,7 +476,8 @@ def _make_autograd():
         def forward(ctx, llr, code, n_info, terminated=True):
             code = _as_code(code)
             F = llr.shape[0]
-            key = ("u", code, F, n_info, terminated, "f32", 2, llr.device.index)
+            key = ("u", code, F, n_info, terminated, "f32", 2, llr.device.index,
+                   _stream_handle(None))
             plan = _cached_plan(key, lambda: Plan([code], uniform_frames(code, F, n_info, terminated),
                                                   "f32", 2))
             bits, metric, _ = plan.decode(llr.contiguous())

@@ -6,8 +6,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -686,6 +688,9 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
       const mivit_frame& fr = frames[f];
       const int K = codes[fr.code].K;
       const bool term = (fr.flags & MIVIT_END_ZERO) && (fr.flags & MIVIT_START_KNOWN);
+      // the backward re-encodes the decoded bits from state 0: an unknown
+      // start state would leave the first K-1 stages' outputs undetermined
+      if (!(fr.flags & MIVIT_START_KNOWN)) grad = false;
       if (fr.out_begin != 0) grad = false;
       if (!(fr.n_out == fr.n_stages || (term && fr.n_out + K - 1 == fr.n_stages))) grad = false;
       gf[f].llr_off = fr.llr_offset;
@@ -848,6 +853,132 @@ mivit_status mivit_quantize_i8(const float* llr, int8_t* q, int64_t n, float sca
   clear_stale_error();
   hipError_t e = launch_quant(llr, q, n, scale, (hipStream_t)stream);
   return e == hipSuccess ? MIVIT_OK : MIVIT_EHIP;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// One-call decode of equal-length frames.  Plans are kept per (device,
+// stream, code, dtype, shape): a plan owns its survivor memory, so calls on
+// one stream reuse it in stream order and calls on different streams never
+// share one.  The least recently used plan is released (after its stream
+// has drained) when more than kUniformPlans are held.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kUniformPlans = 16;
+
+struct UniformEntry {
+  int device;
+  void* stream;
+  mivit_code code;
+  int32_t dtype, n_frames, n_info, terminated;
+  mivit_plan* plan;
+  uint64_t last_use;
+};
+
+struct UniformCache {
+  std::mutex mu;
+  std::vector<UniformEntry> entries;
+  uint64_t clock = 0;
+};
+
+UniformCache& uniform_cache() {
+  static UniformCache* c = new UniformCache();  // never destroyed: HIP may be gone at exit
+  return *c;
+}
+
+// Radix of the one-call entry points: the packed radix-4 kernel where it
+// applies (int8, K = 5 or 7, beta = 2), radix 2 otherwise.
+int uniform_radix(const mivit_code& code, int dtype) {
+  return (dtype == MIVIT_I8 && packed_ok(code)) ? 4 : 2;
+}
+
+bool same_code(const mivit_code& a, const mivit_code& b) {
+  if (a.K != b.K || a.beta != b.beta) return false;
+  for (int k = 0; k < a.beta; ++k)
+    if (a.gen[k] != b.gen[k]) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+mivit_status mivit_decode_uniform(const void* llr, int32_t dtype, const mivit_code* code,
+                                  int32_t n_frames, int32_t n_info, int32_t terminated,
+                                  uint32_t* bits, void* metric, void* stream) {
+  if (!code || n_frames < 0 || n_info < 0) return MIVIT_EINVAL;
+  if (dtype != MIVIT_F32 && dtype != MIVIT_I8 && dtype != MIVIT_F16) return MIVIT_EINVAL;
+  if (terminated != 0 && terminated != 1) return MIVIT_EINVAL;
+  mivit_status cs = check_code(*code);
+  if (cs != MIVIT_OK) return cs;
+  const int64_t S = (int64_t)n_info + (terminated ? code->K - 1 : 0);
+  const int64_t W = ((int64_t)n_info + 31) / 32;
+  if (S > INT32_MAX || (int64_t)n_frames * W * 32 > ((int64_t)1 << 62)) return MIVIT_EINVAL;
+  if (n_frames == 0 || S == 0) return MIVIT_OK;
+  if (!llr || !bits) return MIVIT_EINVAL;
+  int dev = 0;
+  clear_stale_error();
+  if (hipGetDevice(&dev) != hipSuccess) return MIVIT_EHIP;
+  UniformCache& cache = uniform_cache();
+  std::lock_guard<std::mutex> lock(cache.mu);
+  mivit_plan* plan = nullptr;
+  for (UniformEntry& e : cache.entries)
+    if (e.device == dev && e.stream == stream && e.dtype == dtype && e.n_frames == n_frames &&
+        e.n_info == n_info && e.terminated == terminated && same_code(e.code, *code)) {
+      e.last_use = ++cache.clock;
+      plan = e.plan;
+      break;
+    }
+  if (!plan) {
+    std::vector<mivit_frame> fr;
+    try {
+      fr.resize((size_t)n_frames);
+    } catch (const std::bad_alloc&) {
+      return MIVIT_ENOMEM;
+    }
+    for (int32_t f = 0; f < n_frames; ++f) {
+      mivit_frame& x = fr[(size_t)f];
+      x.llr_offset = (int64_t)f * S * code->beta;
+      x.bit_offset = (int64_t)f * W * 32;
+      x.n_stages = (int32_t)S;
+      x.out_begin = 0;
+      x.n_out = n_info;
+      x.code = 0;
+      x.flags = (uint16_t)(MIVIT_START_KNOWN | (terminated ? MIVIT_END_ZERO : 0));
+    }
+    mivit_opts o;
+    std::memset(&o, 0, sizeof o);
+    o.dtype = dtype;
+    o.radix = uniform_radix(*code, dtype);
+    mivit_status s = mivit_plan_create(&plan, code, 1, fr.data(), n_frames, &o);
+    if (s != MIVIT_OK) return s;
+    if (cache.entries.size() >= kUniformPlans) {
+      auto old = std::min_element(cache.entries.begin(), cache.entries.end(),
+                                  [](const UniformEntry& a, const UniformEntry& b) {
+                                    return a.last_use < b.last_use;
+                                  });
+      {
+        DeviceGuard guard(old->device);
+        (void)hipStreamSynchronize((hipStream_t)old->stream);
+        free_plan(old->plan);
+      }
+      cache.entries.erase(old);
+    }
+    UniformEntry e;
+    e.device = dev;
+    e.stream = stream;
+    e.code = *code;
+    e.dtype = dtype;
+    e.n_frames = n_frames;
+    e.n_info = n_info;
+    e.terminated = terminated;
+    e.plan = plan;
+    e.last_use = ++cache.clock;
+    cache.entries.push_back(e);
+  }
+  return mivit_decode(plan, llr, bits, metric, nullptr, stream);
 }
 
 }  // extern "C"

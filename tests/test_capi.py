@@ -203,3 +203,29 @@ def test_null_and_misc():
     assert lib.mivit_quantize_i8(None, None, -1, 1.0, None) == _capi.MIVIT_EINVAL
     assert lib.mivit_quantize_i8(None, None, 10, 1.0, None) == _capi.MIVIT_EINVAL
     assert lib.mivit_quantize_i8(None, None, 0, 0.0, None) == _capi.MIVIT_EINVAL
+
+
+def test_decode_uniform_rejects_before_device_work():
+    """mivit_decode_uniform validates its arguments before touching the
+    device: null pointers, negative counts, bad dtype, bad terminated flag
+    and bad codes are rejected; an empty batch is a no-op."""
+    lib = _capi.load()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every case fails validation
+    cases = [
+        ((None, 0, K7, 4, 100, 1, fake, None, None), _capi.MIVIT_EINVAL),   # no soft values
+        ((fake, 0, K7, 4, 100, 1, None, None, None), _capi.MIVIT_EINVAL),   # no bits
+        ((fake, 7, K7, 4, 100, 1, fake, None, None), _capi.MIVIT_EINVAL),   # dtype
+        ((fake, 0, K7, -1, 100, 1, fake, None, None), _capi.MIVIT_EINVAL),  # frames
+        ((fake, 0, K7, 4, -5, 1, fake, None, None), _capi.MIVIT_EINVAL),    # length
+        ((fake, 0, K7, 4, 100, 2, fake, None, None), _capi.MIVIT_EINVAL),   # terminated flag
+        ((fake, 0, _code(10, [0o1001, 0o1777]), 4, 100, 1, fake, None, None), _capi.MIVIT_EINVAL),
+        ((fake, 0, _code(7, [0o132, 0o171]), 4, 100, 1, fake, None, None),
+         _capi.MIVIT_EUNSUPPORTED),                                           # no LSB tap
+        ((None, 0, K7, 0, 100, 1, None, None, None), _capi.MIVIT_OK),        # empty batch
+        ((None, 1, K7, 5, 0, 0, None, None, None), _capi.MIVIT_OK),          # zero stages
+    ]
+    for args, want in cases:
+        llr, dt, code, F, n, term, bits, metric, st = args
+        got = lib.mivit_decode_uniform(llr, dt, ctypes.byref(code), F, n, term, bits, metric, st)
+        assert got == want, (args, got)
+    assert lib.mivit_decode_uniform(fake, 0, None, 4, 100, 1, fake, None, None) == _capi.MIVIT_EINVAL

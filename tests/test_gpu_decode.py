@@ -330,43 +330,60 @@ def test_determinism():
     np.testing.assert_array_equal(a1[1], a2[1])
 
 
-@pytest.mark.parametrize("dtype", ["f32", "i8"])
-def test_full_batch_4096x8192_sampled(dtype):
-    """4096 terminated frames of 8192 bits (K=7, 2 dB): every frame's metric
-    is the correlation of its decoded codeword and no smaller than the
-    transmitted one; 48 sampled frames match the oracle exactly."""
+@pytest.mark.parametrize("dtype,eb,seed", [("i8", 2.0, 2002), ("i8", 3.0, 2003), ("i8", 6.0, 2006),
+                                            ("f32", 2.0, 2002), ("f32", 3.0, 2003)])
+def test_full_batch_4096x8192(dtype, eb, seed):
+    """4096 terminated frames of 8192 bits (K=7): every frame of every plan
+    equals the oracle.  int8: radix 2 and packed radix 4, direct and
+    persistent launches, bits and metrics identical to the exact-integer
+    oracle.  float32: radix 2, direct and persistent, bits and metrics
+    identical to the single-precision oracle, bits equal to the
+    double-precision oracle on every frame whose runner-up gap exceeds the
+    float32 error bound, metrics within 1e-5 of it.  3 dB with seed 2003 is
+    the benchmark's own batch; 6 dB covers the high-SNR end of the sweep."""
     from workload import int8_scale_for
-    F, n, eb = 4096, 8192, 2.0
-    b = make_uniform_batch(CODE_K7, F, n, eb, seed=2002)
+    F, n = 4096, 8192
+    b = make_uniform_batch(CODE_K7, F, n, eb, seed=seed)
     if dtype == "i8":
         llr = oracle.quantize_i8(b.llr, int8_scale_for(eb, 2))
-        radixes = (2, 4)
+        ob, om, _ = oracle.decode_uniform(CODE_K7, llr, n, True, oracle.I64)
+        runs = [(2, False), (4, False), (2, True), (4, True)]
     else:
         llr = b.llr
-        radixes = (2,)
-    for radix in radixes:
-        print("full", dtype, radix, flush=True)
-        bits, metric = gpu_decode(llr, CODE_K7, n, True, radix)
-        rng = np.random.default_rng(0)
-        idx = np.sort(rng.choice(F, 48, replace=False))
-        mode = oracle.F32 if dtype == "f32" else oracle.I64
-        ob, om, _ = oracle.decode_uniform(CODE_K7, llr[idx], n, True, mode)
-        np.testing.assert_array_equal(bits[idx], ob)
-        np.testing.assert_array_equal(metric[idx], om)
-        for f in range(0, F, 97):
-            if dtype == "i8":
-                assert oracle.path_correlation(CODE_K7, bits[f], llr[f], exact_int=True) == metric[f]
-                assert metric[f] >= oracle.path_correlation(CODE_K7, b.msg[f], llr[f], exact_int=True)
-            else:
-                c = oracle.path_correlation(CODE_K7, bits[f], llr[f])
-                assert abs(c - metric[f]) <= 1e-5 * abs(c)
-        ber = (bits != b.msg).mean()
-        assert ber < 2e-2  # about 5e-3 at 2 dB for this code
+        ob, om, _ = oracle.decode_uniform(CODE_K7, llr, n, True, oracle.F32)
+        ob64, om64, gap = oracle.decode_uniform(CODE_K7, llr, n, True, oracle.F64, want_gap=True)
+        runs = [(2, False), (2, True)]
+    t = torch.from_numpy(llr).to(DEV)
+    fr = mv.uniform_frames(CODE_K7, F, n, True)
+    wpf = (n + 31) // 32
+    for radix, pers in runs:
+        print("full", dtype, eb, radix, "persistent" if pers else "direct", flush=True)
+        plan = mv.Plan([CODE_K7], fr, dtype, radix, persistent=pers)
+        w, m, _ = plan.decode(t)
+        torch.cuda.synchronize()
+        bits = mv.unpack_bits(w.cpu().numpy()[: F * wpf].reshape(F, wpf), n)
+        metric = m.cpu().numpy()[:F]
+        bad = np.flatnonzero((bits != ob).any(axis=1))
+        assert bad.size == 0, "frames %s differ from the oracle" % bad[:10]
+        np.testing.assert_array_equal(metric, om)
+        if dtype == "f32":
+            bound = f32_error_bound(n + 6, float(np.abs(om64).max()))
+            clear = gap > bound
+            print("frames above the float32 bound: %d of %d" % (clear.sum(), F), flush=True)
+            np.testing.assert_array_equal(bits[clear], ob64[clear])
+            np.testing.assert_allclose(metric.astype(np.float64), om64, rtol=1e-5)
+        plan.close()
+    ber = (ob != b.msg).mean()
+    print("BER %.3e" % ber, flush=True)
+    assert ber < 2e-2  # about 5e-3 at 2 dB for this code
 
 
 def test_gradient_matches_oracle_and_fd():
-    """Backward of the best metric: (-1)^{c(u_hat)} * g for 2048 frames of 1024
-    bits at 2 dB; FD check on frames whose runner-up gap exceeds 1e-2."""
+    """Backward of the best metric for 2048 frames of 1024 bits at 2 dB:
+    every frame's gradient equals the oracle's g * (-1)^{c(u_hat)}; central
+    finite differences of the double-precision oracle metric (step 1e-4),
+    every coordinate of 32 frames whose runner-up gap exceeds 1e-2, match
+    the GPU gradient."""
     F, n = 2048, 1024
     b = make_uniform_batch(CODE_K7, F, n, 2.0, seed=5)
     llr = torch.from_numpy(b.llr).to(DEV).requires_grad_(True)
@@ -377,29 +394,33 @@ def test_gradient_matches_oracle_and_fd():
     bits = mv.unpack_bits(words.cpu().numpy(), n)
     ob, om, _ = oracle.decode_uniform(CODE_K7, b.llr, n, True, oracle.F32)
     np.testing.assert_array_equal(bits, ob)
+    np.testing.assert_array_equal(metric.detach().cpu().numpy(), om)
     gn = g.cpu().numpy()
-    for f in range(0, F, 37):
+    for f in range(F):
         ref = oracle.metric_grad(CODE_K7, bits[f], gn[f])
         np.testing.assert_array_equal(grad[f], ref.astype(np.float32))
-    # finite differences in fp64 on untied frames
-    sub = np.arange(0, F, 256)
-    _, _, gap = oracle.decode_uniform(CODE_K7, b.llr[sub], n, True, oracle.F64, want_gap=True)
+    # central differences in fp64 on 32 untied frames, every coordinate
+    _, _, gap = oracle.decode_uniform(CODE_K7, b.llr, n, True, oracle.F64, want_gap=True)
+    qual = np.flatnonzero(gap > 1e-2)
+    print("frames with runner-up gap > 1e-2: %d of %d" % (qual.size, F), flush=True)
+    assert qual.size >= 32
     rng = np.random.default_rng(2)
-    checked = 0
-    for k, f in enumerate(sub):
-        if gap[k] <= 1e-2:
-            continue
-        for pos in rng.choice(b.llr.shape[1], 8, replace=False):
-            lp = b.llr[f].copy()
-            lm = b.llr[f].copy()
-            lp[pos] = np.float32(np.float64(lp[pos]) + 1e-4)
-            lm[pos] = np.float32(np.float64(lm[pos]) - 1e-4)
-            _, mp, _ = oracle.decode_uniform(CODE_K7, lp[None], n, True, oracle.F64)
-            _, mm, _ = oracle.decode_uniform(CODE_K7, lm[None], n, True, oracle.F64)
-            fd = (mp[0] - mm[0]) / (np.float64(lp[pos]) - np.float64(lm[pos]))
-            assert abs(fd * gn[f] - grad[f, pos]) < 1e-5 * abs(gn[f]) + 1e-6
-            checked += 1
-    assert checked > 0
+    L = b.llr.shape[1]
+    eye = np.arange(L)
+    worst = 0.0
+    for f in np.sort(rng.choice(qual, 32, replace=False)):
+        base = np.broadcast_to(b.llr[f], (L, L))
+        lp = base.copy()
+        lm = base.copy()
+        lp[eye, eye] = (b.llr[f].astype(np.float64) + 1e-4).astype(np.float32)
+        lm[eye, eye] = (b.llr[f].astype(np.float64) - 1e-4).astype(np.float32)
+        _, mp, _ = oracle.decode_uniform(CODE_K7, lp, n, True, oracle.F64)
+        _, mm, _ = oracle.decode_uniform(CODE_K7, lm, n, True, oracle.F64)
+        fd = (mp - mm) / (lp[eye, eye].astype(np.float64) - lm[eye, eye].astype(np.float64))
+        err = np.abs(fd * gn[f] - grad[f]).max()
+        worst = max(worst, float(err))
+        assert err < 1e-5 * abs(gn[f]) + 1e-6, "frame %d: max |fd - grad| = %.3g" % (f, err)
+    print("finite differences: 32 frames x %d coordinates, max error %.3g" % (L, worst), flush=True)
 
 
 def test_plan_reuse_and_empty():
@@ -502,31 +523,14 @@ def test_graph_replays():
     _check_mixed(codes, gplan, fr, ofr, llr, "i8", n_bits, words=bits)
 
 
-@pytest.mark.parametrize("dtype", ["i8", "f32"])
-def test_persistent_single_code_full_shape(dtype):
-    """Persistent launches on the 4096 x 8192 K=7 shape equal the plain ones."""
-    from workload import int8_scale_for
-    F, n = 4096, 8192
-    b = make_uniform_batch(CODE_K7, F, n, 2.0, seed=2002)
-    llr = b.llr if dtype == "f32" else oracle.quantize_i8(b.llr, int8_scale_for(2.0, 2))
-    t = torch.from_numpy(llr).to(DEV)
-    fr = mv.uniform_frames(CODE_K7, F, n, True)
-    radix = 4 if dtype == "i8" else 2
-    out = []
-    for pers in (False, True):
-        plan = mv.Plan([CODE_K7], fr, dtype, radix, persistent=pers)
-        w, m, e = plan.decode(t)
-        torch.cuda.synchronize()
-        out.append((w.cpu().numpy(), m.cpu().numpy()))
-    np.testing.assert_array_equal(out[0][0], out[1][0])
-    np.testing.assert_array_equal(out[0][1], out[1][1])
-
-
 @pytest.mark.parametrize("radix", [4, 2])
 def test_stream_2p26_chunked_full(radix):
     """A 2^26-bit stream (K=7, 4 dB, int8) in 2048-stage chunks with 64 stages
-    of overlap on each side; 66 sampled windows (first, last and 64 seeded)
-    equal the oracle decoding the same windows; BER reported and bounded."""
+    of overlap on each side: every one of the 32768 windows equals the oracle
+    decoding the same windows.  The BER against the transmitted bits is
+    bounded; with radix 4 the oracle also decodes the stream whole (one
+    unchunked frame, best final state) and the chunked bits' disagreement
+    with it is reported and bounded."""
     from workload import int8_scale_for
     n = 1 << 26
     msg, llr = make_stream(CODE_K7, n, 4.0, seed=3)
@@ -538,17 +542,19 @@ def test_stream_2p26_chunked_full(radix):
     torch.cuda.synchronize()
     bits = mv.unpack_bits(words.cpu().numpy(), n)
     del t
-    fr = oracle.chunked_frames(CODE_K7, n, 2048, 64)
-    rng = np.random.default_rng(33)
-    pick = np.unique(np.concatenate([[0, len(fr) - 1], rng.choice(len(fr), 64, replace=False)]))
-    sub = fr[pick]
-    ob, _, _, _ = oracle.decode_frames([CODE_K7], sub, q, oracle.I64, n)
-    for row in sub:
-        a, k = int(row["bit_offset"]), int(row["n_out"])
-        np.testing.assert_array_equal(bits[a:a + k], ob[a:a + k])
+    ob, _, _ = oracle.decode_chunked(CODE_K7, q, n, 2048, 64, oracle.I64)
+    bad = np.flatnonzero(bits != ob)
+    assert bad.size == 0, "%d bits differ from the chunked oracle, first in window %d" % (
+        bad.size, bad[0] // 2048)
     ber = float((bits != msg).mean())
     print("stream BER %.3e" % ber, flush=True)
     assert ber < 1e-3
+    if radix == 4:
+        whole, _ = oracle.decode_stream_whole(CODE_K7, q, n, oracle.I64)
+        d = int((bits != whole).sum())
+        print("chunked vs whole-stream decoding: %d of %d bits differ (%.3e); whole-stream BER %.3e"
+              % (d, n, d / n, float((whole != msg).mean())), flush=True)
+        assert d / n < 1e-4
 
 
 @pytest.mark.parametrize("dtype", ["i8", "f32"])
@@ -556,7 +562,7 @@ def test_mixed_10000_frames_autotuned_graph(dtype):
     """10000 frames, lengths log-uniform in [64, 16384], codes K=5 (23,35),
     K=7 (133,171), K=9 r1/3 (557,663,711), Eb/N0 ~ U[1,5] (int8 scale per
     frame): one autotuned plan whose decode is recorded in a hipGraph and
-    replayed; 120 seeded sample frames equal the oracle."""
+    replayed; every frame's bits and metric equal the oracle."""
     from workload import int8_scale_for, make_mixed_batch
     codes = [CODE_K5, CODE_K7, CODE_K9]
     F = 10000
@@ -591,11 +597,9 @@ def test_mixed_10000_frames_autotuned_graph(dtype):
     n_bits = int(mb.bit_offset[-1] + ((n[-1] + 31) // 32) * 32)
     bits = mv.unpack_bits(bits_t.cpu().numpy()[: n_bits // 32], n_bits)
     metric = metric_t.cpu().numpy()[:F]
-    rng = np.random.default_rng(44)
-    pick = np.sort(rng.choice(F, 120, replace=False))
-    ob, om, _, _ = oracle.decode_frames(codes, ofr[pick], llr, mode, n_bits)
-    np.testing.assert_array_equal(metric[pick], om)
-    for row in ofr[pick]:
+    ob, om, _, _ = oracle.decode_frames(codes, ofr, llr, mode, n_bits)
+    np.testing.assert_array_equal(metric, om)
+    for row in ofr:
         a, k = int(row["bit_offset"]), int(row["n_out"])
         np.testing.assert_array_equal(bits[a:a + k], ob[a:a + k])
     errs = sum(int((bits[int(mb.bit_offset[f]):int(mb.bit_offset[f] + n[f])] != mb.msgs[f]).sum())
@@ -748,9 +752,9 @@ def test_stream_pushes_match_oracle(dtype, chunk, overlap, end_zero, radix):
 @pytest.mark.parametrize("depth", [2, 3])
 def test_pipeline_matches_decode(depth):
     """Batches decoded by the host pipeline (copy in, decode, copy out on
-    three streams) equal plan.decode of each batch on the device: mixed codes
-    and lengths, int8 radix 4 and float32 radix 2, page-locked and ordinary
-    host memory, and runs of 0, 1 and 5 batches."""
+    three streams) equal the oracle decoding each batch: mixed codes and
+    lengths, int8 radix 4 and float32 radix 2, page-locked and ordinary host
+    memory, and runs of 0, 1 and 5 batches."""
     codes, fr, ofr, _, n_bits = _mixed("f32", F=60, seed=21)
     rng = np.random.default_rng(99)
     for dtype, radix in (("i8", 4), ("f32", 2)):
@@ -762,6 +766,12 @@ def test_pipeline_matches_decode(depth):
             llr = torch.from_numpy(rng.integers(-40, 41, size=nb * E).astype(np.int8))
         else:
             llr = torch.from_numpy(rng.normal(0, 3, size=nb * E).astype(np.float32))
+        mode = oracle.I64 if dtype == "i8" else oracle.F32
+        ref = []
+        for b in range(nb):
+            ob, om, _, _ = oracle.decode_frames(codes, ofr, llr[b * E:(b + 1) * E].numpy(), mode,
+                                                W * 32)
+            ref.append((ob, om))
         for pinned in (True, False):
             h_llr = llr.pin_memory() if pinned else llr.clone()
             bits = torch.full((nb * W,), -1, dtype=torch.int32)
@@ -774,10 +784,12 @@ def test_pipeline_matches_decode(depth):
             pipe.run(h_llr, bits, metric, 1)
             pipe.run(h_llr, bits, metric, nb)
             for b in range(nb):
-                w, m, _ = plan.decode(llr[b * E:(b + 1) * E].to(DEV))
-                torch.cuda.synchronize()
-                np.testing.assert_array_equal(bits[b * W:(b + 1) * W].numpy(), w.cpu().numpy()[:W])
-                np.testing.assert_array_equal(metric[b * F:(b + 1) * F].numpy(), m.cpu().numpy()[:F])
+                got = mv.unpack_bits(bits[b * W:(b + 1) * W].numpy(), W * 32)
+                ob, om = ref[b]
+                for k in range(F):
+                    a, n = int(ofr[k]["bit_offset"]), int(ofr[k]["n_out"])
+                    np.testing.assert_array_equal(got[a:a + n], ob[a:a + n])
+                np.testing.assert_array_equal(metric[b * F:(b + 1) * F].numpy(), om)
         with pytest.raises(ValueError):
             pipe.run(h_llr, bits[:-1], None, nb)
         pipe.close()
@@ -820,3 +832,94 @@ def test_gradient_mixed_codes():
         lo, S = int(fr[k]["llr_offset"]), int(fr[k]["n_stages"])
         ref = oracle.metric_grad(code, bits[a:a + n], gn[k])
         np.testing.assert_array_equal(gr[lo:lo + S * code.beta], ref.astype(np.float32))
+
+
+@pytest.mark.parametrize("code", [CODE_K5, CODE_K7, CODE_K9], ids=cid)
+def test_decode_uniform_capi(code):
+    """mivit_decode_uniform called through ctypes (the one-call form: soft
+    values of equal-length frames in, bits and best metrics out) equals the
+    oracle for int8, float32 and float16 soft values, terminated and
+    free-end frames, odd frame counts and ragged lengths; a NULL metric is
+    allowed, and a second stream gets its own plan with the same results."""
+    import ctypes
+    lib = mv._capi.load()
+    cs = mv.Code(code.K, tuple(code.gens)).c_struct()
+    side = torch.cuda.Stream()
+    for dt, F, n, term in [("i8", 3, 1000, 1), ("i8", 64, 257, 0), ("f32", 5, 333, 1),
+                           ("f32", 2, 1, 0), ("f16", 7, 64, 1), ("i8", 1, 4097, 1)]:
+        b = make_uniform_batch(code, F, n, 2.0, seed=7000 + n + F, terminated=bool(term))
+        if dt == "i8":
+            llr = oracle.quantize_i8(b.llr, 6.0)
+            ref, mode = llr, oracle.I64
+        elif dt == "f16":
+            llr = b.llr.astype(np.float16)
+            ref, mode = llr.astype(np.float32), oracle.F32
+        else:
+            llr, ref, mode = b.llr, b.llr, oracle.F32
+        ob, om, _ = oracle.decode_uniform(code, ref, n, bool(term), mode)
+        dtc = {"i8": mv.MIVIT_I8, "f32": mv.MIVIT_F32, "f16": mv.MIVIT_F16}[dt]
+        t = torch.from_numpy(np.ascontiguousarray(llr)).to(DEV)
+        W = (n + 31) // 32
+        for stream in (torch.cuda.current_stream(), side):
+            bits = torch.full((F * W,), -1, dtype=torch.int32, device=DEV)
+            metric = torch.zeros(F, dtype=torch.int64 if dt == "i8" else torch.float32, device=DEV)
+            print("uniform", cid(code), dt, F, n, term, flush=True)
+            with torch.cuda.stream(stream):
+                st = lib.mivit_decode_uniform(t.data_ptr(), dtc, ctypes.byref(cs), F, n, term,
+                                              bits.data_ptr(), metric.data_ptr(),
+                                              stream.cuda_stream)
+            assert st == mv._capi.MIVIT_OK
+            stream.synchronize()
+            got = mv.unpack_bits(bits.cpu().numpy().reshape(F, W), n)
+            np.testing.assert_array_equal(got, ob)
+            np.testing.assert_array_equal(metric.cpu().numpy(), om)
+        bits = torch.zeros(F * W, dtype=torch.int32, device=DEV)
+        st = lib.mivit_decode_uniform(t.data_ptr(), dtc, ctypes.byref(cs), F, n, term,
+                                      bits.data_ptr(), None, torch.cuda.current_stream().cuda_stream)
+        assert st == mv._capi.MIVIT_OK
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(mv.unpack_bits(bits.cpu().numpy().reshape(F, W), n), ob)
+    # the Python one-call decode (radix 0) goes through the same entry point
+    b = make_uniform_batch(code, 4, 500, 2.0, seed=77)
+    q = oracle.quantize_i8(b.llr, 6.0)
+    bits, metric = gpu_decode(q, code, 500, True, 0)
+    ob, om, _ = oracle.decode_uniform(code, q, 500, True, oracle.I64)
+    np.testing.assert_array_equal(bits, ob)
+    np.testing.assert_array_equal(metric, om)
+
+
+def test_gradient_rejects_unknown_start():
+    """The backward re-encodes the decoded bits from state 0, so a plan with
+    a frame of unknown start state refuses it (MIVIT_EUNSUPPORTED) instead of
+    returning a wrong gradient for its first K-1 stages."""
+    code = CODE_K7
+    fr = mv.uniform_frames(code, 2, 100, False)
+    fr["flags"][1] = 0  # unknown start, free end
+    plan = mv.Plan([code], fr, "f32", 2)
+    t = torch.zeros(plan.llr_extent, device=DEV)
+    bits, metric, _ = plan.decode(t)
+    with pytest.raises(mv.MivitError) as ei:
+        plan.decode_grad(bits, torch.ones(2, device=DEV), torch.zeros_like(t))
+    assert ei.value.status == mv._capi.MIVIT_EUNSUPPORTED
+
+
+def test_autograd_survives_plan_cache_eviction():
+    """A forward whose plan is pushed out of the binding's plan cache (more
+    than eight other shapes decoded before its backward) still has a working
+    backward: evicted plans are dropped, not destroyed, while referenced."""
+    code = CODE_K7
+    F, n = 4, 200
+    b = make_uniform_batch(code, F, n, 2.0, seed=91)
+    llr = torch.from_numpy(b.llr).to(DEV).requires_grad_(True)
+    words, metric = mv.ViterbiDecode.apply(llr, code, n, True)
+    for k in range(10):
+        x = make_uniform_batch(code, 2, 50 + k, 2.0, seed=k)
+        mv.decode(torch.from_numpy(x.llr).to(DEV), code, 50 + k, True, 2)
+    metric.sum().backward()
+    torch.cuda.synchronize()
+    bits = mv.unpack_bits(words.cpu().numpy(), n)
+    ob, _, _ = oracle.decode_uniform(code, b.llr, n, True, oracle.F32)
+    np.testing.assert_array_equal(bits, ob)
+    for f in range(F):
+        np.testing.assert_array_equal(llr.grad[f].cpu().numpy(),
+                                      oracle.metric_grad(code, bits[f], 1.0).astype(np.float32))
