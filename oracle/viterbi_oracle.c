@@ -16,12 +16,18 @@
  *                    previous K-1 inputs with in_{t-1} in the MSB.
  *   branch metric    §II-B, Eq. (BM): delta = sum_b (-1)^{alpha_out[b]} l[b],
  *                    summed in order b = 0 .. beta-1.
- *   path metric      §II-B, Eq. (PM) and Eq. (SP0); forward procedure of
- *                    Algorithm 1 (strict '>' test, so a tie keeps the
- *                    predecessor tested second, which we make the
- *                    lower-index one).
- *   traceback        Algorithm 2: start at the chosen final state, walk the
- *                    survivors back to stage 0, emitting alpha_in.
+ *   path metric      §II-B, Eq. (PM) and Eq. (SP0), the forward procedure
+ *                    of Algorithm 1, evaluated branch by branch (every
+ *                    state pushes its two candidates to the states it
+ *                    leads to; a candidate displaces the kept one only
+ *                    when strictly larger, sources in increasing order, so
+ *                    a tie keeps the lower-index previous state); the
+ *                    survivor is stored as the one bit that tells the two
+ *                    previous states of a state apart.
+ *   traceback        the decoding of Algorithm 2: from the chosen final
+ *                    state, shift the register back stage by stage; the
+ *                    state after a stage holds that stage's input bit on
+ *                    top.
  *   radix-4          §VIII-A, Eqs. (radix4:BM), (radix4:PM), (radix4:SP0):
  *                    super-branch metric over 2*beta soft values, maximum
  *                    over prv(prv(j)), two stages per iteration.
@@ -141,79 +147,118 @@ int orc_encode(const orc_code* c, const uint8_t* msg, int32_t n, int32_t termina
 }
 
 /* ------------------------------------------------------------------ */
-/* Radix-2 forward procedure + traceback (Algorithms 1 and 2).        */
+/* Radix-2 forward procedure and traceback (§II-B).                    */
+/*                                                                    */
+/* Forward: Eq. (PM) evaluated branch by branch.  At stage t every     */
+/* state i sends, for each input u, the candidate PM_i + delta(i, u)   */
+/* (delta from Eq. (BM)) to the state next[i][u] the branch enters.    */
+/* Sources are visited in increasing index and a later candidate       */
+/* displaces the kept one only when it is strictly larger, so a tie    */
+/* keeps the lower-index previous state.  The two previous states of a */
+/* state differ only in their least significant bit (the oldest input, */
+/* shifted out of the register), so the survivor of Eq. (SP0) is kept  */
+/* as that single bit per state and stage.                             */
+/*                                                                    */
+/* Traceback: from the chosen final state, the register is shifted     */
+/* back one stage at a time: the state after stage t holds the input   */
+/* of stage t in its top bit, and the state before it is that state    */
+/* shifted up by one with the stored bit entering at the bottom.       */
 /* ------------------------------------------------------------------ */
 
-/* Per-frame scratch: survivors phi[t][j] (the selected previous state),
- * and optionally the ACS margin |PM' - PM''| at each node. */
+/* Per-thread scratch: decision bits (stage t, state j: bit j % 64 of
+ * word t * wps + j / 64) and, when requested, the margin |c' - c''|
+ * between the two candidates of every node (stage-major). */
 typedef struct {
-  int16_t* phi;
+  uint64_t* dec;
   double* margin;
-  size_t cap;  /* entries (stages x states) the buffers hold */
+  size_t cap_words;  /* words dec holds */
+  size_t cap_nodes;  /* entries margin holds */
 } orc_scratch;
 
+static int words_per_stage(int ns) { return (ns + 63) / 64; }
+
 static int scratch_reserve(orc_scratch* s, int S, int ns, int want_margin) {
-  const size_t need = (size_t)S * (size_t)ns;
-  if (need <= s->cap && (!want_margin || s->margin)) return 0;
-  free(s->phi);
-  free(s->margin);
-  s->phi = (int16_t*)malloc((need ? need : 1) * sizeof(int16_t));
-  s->margin = want_margin ? (double*)malloc((need ? need : 1) * sizeof(double)) : NULL;
-  s->cap = need;
-  return (s->phi && (!want_margin || s->margin)) ? 0 : -1;
+  const size_t words = (size_t)(S > 0 ? S : 1) * (size_t)words_per_stage(ns);
+  const size_t nodes = (size_t)(S > 0 ? S : 1) * (size_t)ns;
+  if (words > s->cap_words) {
+    free(s->dec);
+    s->dec = (uint64_t*)malloc(words * sizeof(uint64_t));
+    s->cap_words = s->dec ? words : 0;
+    if (!s->dec) return -1;
+  }
+  if (want_margin && nodes > s->cap_nodes) {
+    free(s->margin);
+    s->margin = (double*)malloc(nodes * sizeof(double));
+    s->cap_nodes = s->margin ? nodes : 0;
+    if (!s->margin) return -1;
+  }
+  return 0;
 }
 
-/* Trace back from state js at the last stage (Algorithm 2); writes the
- * emitted bits and returns the minimum margin along the path. */
-static double traceback(const orc_trellis* tr, const orc_scratch* sc, const orc_frame* fr,
-                        int js, uint8_t* bits) {
+/* Record the survivor bit of state j at stage t: the low bit of the kept
+ * previous state. */
+static void set_decision(uint64_t* dec_t, int j, int i) {
+  const uint64_t m = (uint64_t)1 << (j & 63);
+  if (i & 1) dec_t[j >> 6] |= m;
+  else dec_t[j >> 6] &= ~m;
+}
+
+/* Walk back from state js after the last stage, writing the emitted bits;
+ * returns the smallest margin met along the path (infinity without
+ * margins). */
+static double traceback_bits(const orc_trellis* tr, const orc_scratch* sc, const orc_frame* fr,
+                             int js, int want_margin, uint8_t* bits) {
+  const int ns = tr->ns, wps = words_per_stage(ns), top = tr->K - 2;
   double gmin = INFINITY;
   int j = js;
   for (int t = fr->n_stages - 1; t >= 0; --t) {
-    int i = sc->phi[(size_t)t * tr->ns + j];
-    if (sc->margin) {
-      double m = sc->margin[(size_t)t * tr->ns + j];
+    if (want_margin) {
+      double m = sc->margin[(size_t)t * ns + j];
       if (m < gmin) gmin = m;
     }
     int rel = t - fr->out_begin;
-    if (rel >= 0 && rel < fr->n_out) bits[fr->bit_offset + rel] = (uint8_t)tr->prv_in[j];
-    j = i;
+    if (rel >= 0 && rel < fr->n_out) bits[fr->bit_offset + rel] = (uint8_t)(j >> top);
+    int d = (int)((sc->dec[(size_t)t * wps + (j >> 6)] >> (j & 63)) & 1u);
+    j = ((j << 1) | d) & (ns - 1);
   }
   return gmin;
 }
 
-/* The three precision modes share one shape; each is written out in full
- * so that every arithmetic step is visible in its own type. */
+/* The three precision modes share one shape; each is written out in its
+ * own arithmetic type. */
 
 static int decode_f64(const orc_trellis* tr, const orc_frame* fr, const float* llr,
                       uint8_t* bits, double* metric, int32_t* end_state, double* gap,
                       orc_scratch* sc) {
-  const int ns = tr->ns, beta = tr->beta, S = fr->n_stages;
-  if (scratch_reserve(sc, S > 0 ? S : 1, ns, gap != NULL)) return -2;
+  const int ns = tr->ns, beta = tr->beta, S = fr->n_stages, wps = words_per_stage(ns);
+  const int want_margin = gap != NULL;
+  if (scratch_reserve(sc, S, ns, want_margin)) return -2;
   double pm[ORC_MAXNS], nw[ORC_MAXNS];
+  int got[ORC_MAXNS];
   for (int j = 0; j < ns; ++j) pm[j] = (fr->start_known && j != 0) ? -INFINITY : 0.0;
-  const float* l = llr + fr->llr_offset;
   for (int t = 0; t < S; ++t) {
-    for (int j = 0; j < ns; ++j) {
-      int ia = tr->prv[j][1], ib = tr->prv[j][0]; /* i' (higher), i'' (lower) */
-      int u = tr->prv_in[j];
-      double da = 0.0, db = 0.0;                   /* Eq. (BM) */
-      for (int b = 0; b < beta; ++b) {
-        double v = (double)l[(int64_t)t * beta + b];
-        da += ((tr->out[ia][u] >> b) & 1) ? -v : v;
-        db += ((tr->out[ib][u] >> b) & 1) ? -v : v;
+    const float* l = llr + fr->llr_offset + (int64_t)t * beta;
+    uint64_t* dec_t = sc->dec + (size_t)t * wps;
+    for (int j = 0; j < ns; ++j) got[j] = 0;
+    for (int i = 0; i < ns; ++i)
+      for (int u = 0; u < 2; ++u) {
+        const int j = tr->next[i][u];
+        double delta = 0.0; /* Eq. (BM) */
+        for (int b = 0; b < beta; ++b) delta += ((tr->out[i][u] >> b) & 1) ? -(double)l[b] : (double)l[b];
+        const double c = pm[i] + delta;
+        if (got[j] && want_margin)
+          sc->margin[(size_t)t * ns + j] = (isinf(c) || isinf(nw[j])) ? INFINITY : fabs(c - nw[j]);
+        if (!got[j] || c > nw[j]) {
+          nw[j] = c;
+          set_decision(dec_t, j, i);
+        }
+        got[j] = 1;
       }
-      double pa = pm[ia] + da, pb = pm[ib] + db; /* Eq. (PM) candidates */
-      if (pa > pb) { nw[j] = pa; sc->phi[(size_t)t * ns + j] = (int16_t)ia; }
-      else         { nw[j] = pb; sc->phi[(size_t)t * ns + j] = (int16_t)ib; }
-      if (gap) sc->margin[(size_t)t * ns + j] =
-          (isinf(pa) || isinf(pb)) ? INFINITY : fabs(pa - pb);
-    }
-    memcpy(pm, nw, sizeof(double) * ns);
+    for (int j = 0; j < ns; ++j) pm[j] = nw[j];
   }
   int js = fr->end_state;
   if (js < 0) { js = 0; for (int j = 1; j < ns; ++j) if (pm[j] > pm[js]) js = j; }
-  double g = traceback(tr, sc, fr, js, bits);
+  double g = traceback_bits(tr, sc, fr, js, want_margin, bits);
   if (gap) {
     if (fr->end_state < 0)
       for (int j = 0; j < ns; ++j)
@@ -227,30 +272,32 @@ static int decode_f64(const orc_trellis* tr, const orc_frame* fr, const float* l
 
 static int decode_f32(const orc_trellis* tr, const orc_frame* fr, const float* llr,
                       uint8_t* bits, float* metric, int32_t* end_state, orc_scratch* sc) {
-  const int ns = tr->ns, beta = tr->beta, S = fr->n_stages;
-  if (scratch_reserve(sc, S > 0 ? S : 1, ns, 0)) return -2;
+  const int ns = tr->ns, beta = tr->beta, S = fr->n_stages, wps = words_per_stage(ns);
+  if (scratch_reserve(sc, S, ns, 0)) return -2;
   float pm[ORC_MAXNS], nw[ORC_MAXNS];
+  int got[ORC_MAXNS];
   for (int j = 0; j < ns; ++j) pm[j] = (fr->start_known && j != 0) ? -INFINITY : 0.0f;
-  const float* l = llr + fr->llr_offset;
   for (int t = 0; t < S; ++t) {
-    for (int j = 0; j < ns; ++j) {
-      int ia = tr->prv[j][1], ib = tr->prv[j][0];
-      int u = tr->prv_in[j];
-      float da = 0.0f, db = 0.0f;
-      for (int b = 0; b < beta; ++b) {
-        float v = l[(int64_t)t * beta + b];
-        da += ((tr->out[ia][u] >> b) & 1) ? -v : v;
-        db += ((tr->out[ib][u] >> b) & 1) ? -v : v;
+    const float* l = llr + fr->llr_offset + (int64_t)t * beta;
+    uint64_t* dec_t = sc->dec + (size_t)t * wps;
+    for (int j = 0; j < ns; ++j) got[j] = 0;
+    for (int i = 0; i < ns; ++i)
+      for (int u = 0; u < 2; ++u) {
+        const int j = tr->next[i][u];
+        float delta = 0.0f; /* Eq. (BM), summed in single precision */
+        for (int b = 0; b < beta; ++b) delta += ((tr->out[i][u] >> b) & 1) ? -l[b] : l[b];
+        const float c = pm[i] + delta;
+        if (!got[j] || c > nw[j]) {
+          nw[j] = c;
+          set_decision(dec_t, j, i);
+        }
+        got[j] = 1;
       }
-      float pa = pm[ia] + da, pb = pm[ib] + db;
-      if (pa > pb) { nw[j] = pa; sc->phi[(size_t)t * ns + j] = (int16_t)ia; }
-      else         { nw[j] = pb; sc->phi[(size_t)t * ns + j] = (int16_t)ib; }
-    }
-    memcpy(pm, nw, sizeof(float) * ns);
+    for (int j = 0; j < ns; ++j) pm[j] = nw[j];
   }
   int js = fr->end_state;
   if (js < 0) { js = 0; for (int j = 1; j < ns; ++j) if (pm[j] > pm[js]) js = j; }
-  traceback(tr, sc, fr, js, bits);
+  traceback_bits(tr, sc, fr, js, 0, bits);
   metric[0] = pm[js];
   end_state[0] = js;
   return 0;
@@ -258,30 +305,31 @@ static int decode_f32(const orc_trellis* tr, const orc_frame* fr, const float* l
 
 static int decode_i64(const orc_trellis* tr, const orc_frame* fr, const int8_t* llr,
                       uint8_t* bits, int64_t* metric, int32_t* end_state, orc_scratch* sc) {
-  const int ns = tr->ns, beta = tr->beta, S = fr->n_stages;
-  if (scratch_reserve(sc, S > 0 ? S : 1, ns, 0)) return -2;
+  const int ns = tr->ns, beta = tr->beta, S = fr->n_stages, wps = words_per_stage(ns);
+  if (scratch_reserve(sc, S, ns, 0)) return -2;
   int64_t pm[ORC_MAXNS], nw[ORC_MAXNS];
-  int ok[ORC_MAXNS], nok[ORC_MAXNS]; /* 0 = minus infinity */
+  int ok[ORC_MAXNS], got[ORC_MAXNS]; /* ok = reachable; unreachable is minus infinity */
   for (int j = 0; j < ns; ++j) { pm[j] = 0; ok[j] = !(fr->start_known && j != 0); }
-  const int8_t* l = llr + fr->llr_offset;
   for (int t = 0; t < S; ++t) {
-    for (int j = 0; j < ns; ++j) {
-      int ia = tr->prv[j][1], ib = tr->prv[j][0];
-      int u = tr->prv_in[j];
-      int64_t da = 0, db = 0;
-      for (int b = 0; b < beta; ++b) {
-        int64_t v = l[(int64_t)t * beta + b];
-        da += ((tr->out[ia][u] >> b) & 1) ? -v : v;
-        db += ((tr->out[ib][u] >> b) & 1) ? -v : v;
+    const int8_t* l = llr + fr->llr_offset + (int64_t)t * beta;
+    uint64_t* dec_t = sc->dec + (size_t)t * wps;
+    for (int j = 0; j < ns; ++j) { got[j] = 0; nw[j] = 0; }
+    for (int w = 0; w < wps; ++w) dec_t[w] = 0;
+    for (int i = 0; i < ns; ++i) {
+      if (!ok[i]) continue; /* minus infinity never wins */
+      for (int u = 0; u < 2; ++u) {
+        const int j = tr->next[i][u];
+        int64_t delta = 0; /* Eq. (BM), exact */
+        for (int b = 0; b < beta; ++b) delta += ((tr->out[i][u] >> b) & 1) ? -(int64_t)l[b] : (int64_t)l[b];
+        const int64_t c = pm[i] + delta;
+        if (!got[j] || c > nw[j]) {
+          nw[j] = c;
+          set_decision(dec_t, j, i);
+        }
+        got[j] = 1;
       }
-      int64_t pa = pm[ia] + da, pb = pm[ib] + db;
-      /* pa > pb with minus infinity: a finite value beats -inf, -inf never wins */
-      int a_wins = ok[ia] && (!ok[ib] || pa > pb);
-      if (a_wins) { nw[j] = pa; nok[j] = 1; sc->phi[(size_t)t * ns + j] = (int16_t)ia; }
-      else        { nw[j] = pb; nok[j] = ok[ib]; sc->phi[(size_t)t * ns + j] = (int16_t)ib; }
     }
-    memcpy(pm, nw, sizeof(int64_t) * ns);
-    memcpy(ok, nok, sizeof(int) * ns);
+    for (int j = 0; j < ns; ++j) { pm[j] = nw[j]; ok[j] = got[j]; }
   }
   int js = fr->end_state;
   if (js < 0) {
@@ -290,7 +338,7 @@ static int decode_i64(const orc_trellis* tr, const orc_frame* fr, const int8_t* 
       if (ok[j] && (js < 0 || pm[j] > pm[js])) js = j;
     if (js < 0) js = 0;
   }
-  traceback(tr, sc, fr, js, bits);
+  traceback_bits(tr, sc, fr, js, 0, bits);
   metric[0] = ok[js] ? pm[js] : INT64_MIN;
   end_state[0] = js;
   return 0;
@@ -432,7 +480,7 @@ typedef struct {
 
 static void* worker(void* arg) {
   orc_job* job = (orc_job*)arg;
-  orc_scratch sc = {0, 0, 0};  /* grows to the largest frame seen */
+  orc_scratch sc = {0, 0, 0, 0};  /* grows to the largest frame seen */
   orc_trellis* trs = (orc_trellis*)malloc(sizeof(orc_trellis) * (size_t)job->n_codes);
   if (!trs) { pthread_mutex_lock(&job->mu); job->err = -2; pthread_mutex_unlock(&job->mu); return NULL; }
   for (int c = 0; c < job->n_codes; ++c) build_trellis(&job->codes[c], &trs[c]);
@@ -465,7 +513,7 @@ static void* worker(void* arg) {
     }
     if (rc) { pthread_mutex_lock(&job->mu); job->err = rc; pthread_mutex_unlock(&job->mu); }
   }
-  free(sc.phi);
+  free(sc.dec);
   free(sc.margin);
   free(trs);
   return NULL;
