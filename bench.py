@@ -184,11 +184,30 @@ def ber_sweep(torch, mv, code, frames_plan_i8, frames_plan_f32, frames_plan_f16=
                 x0, x1 = math.log10(b0), math.log10(b1)
                 return d0 + (math.log10(target) - x0) * (d1 - d0) / (x1 - x0)
         return None
-    res = {"points": out}
+    # double-precision oracle errors on the same batches, written by
+    # tests/golden/make_ber_fp64.py (same seeds, same float32 soft values)
+    gold = os.path.join(ROOT, "tests", "golden", "ber_fp64_k7_4096x8192.json")
+    have64 = False
+    if os.path.exists(gold):
+        with open(gold) as fh:
+            f64 = {p["ebn0_db"]: p for p in json.load(fh)["points"]}
+        have64 = all(r["ebn0_db"] in f64 and f64[r["ebn0_db"]]["bits"] == r["bits"] for r in out)
+        if have64:
+            for r in out:
+                r["f64_oracle_errors"] = f64[r["ebn0_db"]]["f64_errors"]
+    for r in out:
+        r["valid"] = all(r[k] >= 100 for k in r if k.endswith("_errors"))
+    res = {"points": out, "validity": "a point with fewer than 100 errors in any decoder is "
+                                      "flagged invalid (the paper's rule)"}
     for tgt in (1e-4, 1e-5):
         a, c = at(tgt, "f32r2_errors"), at(tgt, "i8r4_errors")
         res["ebn0_at_%g" % tgt] = {"f32r2": a, "i8r4": c,
                                    "gap_db": None if a is None or c is None else round(c - a, 4)}
+        if have64:
+            d = at(tgt, "f64_oracle_errors")
+            res["ebn0_at_%g" % tgt]["f64_oracle"] = d
+            res["ebn0_at_%g" % tgt]["i8r4_loss_vs_f64_db"] = (None if d is None or c is None
+                                                              else round(c - d, 4))
         if frames_plan_f16 is not None:
             h = at(tgt, "f16r2_errors")
             res["ebn0_at_%g" % tgt]["f16r2"] = h

@@ -292,3 +292,54 @@ def test_mixed_codes_one_call():
             for row in sub:
                 a, k = int(row["bit_offset"]), int(row["n_out"])
                 np.testing.assert_array_equal(bits[a:a + k], b1[a:a + k])
+
+
+def test_stored_fp64_ber_counts():
+    """The stored double-precision error counts of the equal-BER sweep
+    (tests/golden/ber_fp64_k7_4096x8192.json, written by make_ber_fp64.py)
+    fall with Eb/N0, sit below the K=7 union bound from 4 dB up (the bound
+    is loose below), and the 4 dB point is reproduced by the oracle."""
+    import math
+    from workload import make_uniform_batch
+    path = os.path.join(os.path.dirname(__file__), "golden", "ber_fp64_k7_4096x8192.json")
+    pts = json.load(open(path))["points"]
+    assert [p["ebn0_db"] for p in pts] == list(range(7))
+    errs = [p["f64_errors"] for p in pts]
+    assert all(a >= b for a, b in zip(errs, errs[1:]))
+    spec = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "textbook_spectra.json")))["K7_133_171"]
+    for p in pts:
+        if p["ebn0_db"] < 4:
+            continue
+        ebn0 = 10 ** (p["ebn0_db"] / 10)
+        bound = sum(c * 0.5 * math.erfc(math.sqrt(d * 0.5 * ebn0)) for d, c in zip(spec["d"], spec["c_d"]))
+        assert p["f64_errors"] / p["bits"] <= bound
+    p4 = pts[4]
+    b = make_uniform_batch(CODE_K7, 4096, 8192, 4.0, seed=2004)
+    bits, _, _ = oracle.decode_uniform(CODE_K7, b.llr, 8192, True, oracle.F64)
+    assert int((bits != b.msg).sum()) == p4["f64_errors"]
+
+
+@pytest.mark.parametrize("code,ns", [(CODE_K7, (13, 14, 15, 16)), (CODE_K5, (14, 16)),
+                                     (CODE_K9, (10, 11, 12))], ids=["K7", "K5", "K9_r13"])
+def test_bruteforce_long_frames_with_ties(code, ns):
+    """Exhaustive ML over every message of the longest frames the search
+    covers (2^16 messages for K=7 and K=5, 2^12 for K=9 rate 1/3), tie-heavy
+    int8 soft values and continuous ones: the exact-integer radix-2 oracle,
+    the literal radix-4 recursion and the double-precision oracle return the
+    brute-force message (smallest under the colex rule on ties) and metric."""
+    rng = np.random.default_rng(900 + code.K)
+    for n in ns:
+        S = n + code.K - 1
+        for trial in range(2):
+            l = tie_heavy(rng, S * code.beta)
+            bb, mb = bruteforce.ml_decode(code, l, n, exact_int=True)
+            for mode in (oracle.I64, oracle.R4_I64):
+                ob, om, _ = oracle.decode_uniform(code, l[None], n, True, mode)
+                assert np.array_equal(ob[0], bb), (n, trial, mode)
+                assert int(om[0]) == int(mb)
+        x = rng.normal(0, 2, S * code.beta).astype(np.float32)
+        bb, mb = bruteforce.ml_decode(code, x, n)
+        ob, om, _ = oracle.decode_uniform(code, x[None], n, True, oracle.F64)
+        assert np.array_equal(ob[0], bb)
+        assert abs(float(om[0]) - mb) <= 1e-9 * max(1.0, abs(mb))

@@ -265,9 +265,14 @@ def test_textbook_spectrum_k7():
 
 
 @pytest.mark.parametrize("code,key", [(CODE_K5, "K5_23_35"), (CODE_K9, "K9_557_663_711")])
-def test_textbook_dfree(code, key):
-    a, _ = _spectrum(code, SPECTRA[key]["d_free"] + 1)
-    assert min(d for d in range(len(a)) if a[d]) == SPECTRA[key]["d_free"]
+def test_textbook_spectrum_k5_k9(code, key):
+    """Free distance, path counts a_d and information weights c_d of the
+    first five distances of the other two codes."""
+    ref = SPECTRA[key]
+    a, c = _spectrum(code, max(ref["d"]))
+    assert min(d for d in range(len(a)) if a[d]) == ref["d_free"]
+    assert [a[d] for d in ref["d"]] == ref["a_d"]
+    assert [c[d] for d in ref["d"]] == ref["c_d"]
 
 
 @pytest.mark.parametrize("code", ALL_CODES, ids=lambda c: "K%d_b%d" % (c.K, c.beta))
