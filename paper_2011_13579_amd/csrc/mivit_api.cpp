@@ -347,18 +347,14 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
       continue;
     }
     it.surv_off = words_total;
-    int64_t words;
-    if (kern == kKernRot2)
-      words = (int64_t)((it.n_stages + 31) / 32) * (1 << (c.K - 1)) / 2;
-    else if (kern == kKernRot4P)  // 2^(K-1) 32-bit words per 8 iterations
-      words = (int64_t)((it.n_stages / 2 + 7) / 8) * (1 << (c.K - 1)) / 2;
-    else if (kern == kKernWide)  // 2^(K-1) bytes per 8 stages, whole 32-stage blocks
-      words = (int64_t)((it.n_stages + 31) / 32) * (1 << (c.K - 1)) / 2;
+    if (kern == kKernRot2 || kern == kKernWide)
+      words_total += surv_words_blocks32(c.K, it.n_stages);
+    else if (kern == kKernRot4P)
+      words_total += surv_words_r4p(c.K, it.n_stages);
     else
-      words = (int64_t)it.n_stages * words_per_stage(c.K);
-    words_total += (words + 1) & ~(int64_t)1;
+      words_total += surv_words_natural(c.K, it.n_stages);
   }
-  words_total += 32;  // the traceback reads whole blocks past an item's end
+  words_total += kSurvSlackWords;
   q.surv_words = words_total;
   if (!items.empty()) q.groups.push_back(g);
   q.items = items;

@@ -60,4 +60,24 @@ __host__ __device__ inline int words_per_stage(int K) {
   return ns <= 64 ? 1 : ns / 64;
 }
 
+// Survivor memory of one work item, in uint64 words, per survivor layout
+// (rounded up to an even count so every item starts 16-byte aligned):
+//   rotating radix 2 (K <= 7) and bytes-by-position (K = 8, 9): whole
+//     32-stage blocks of 2^(K-1) 32-bit words;
+//   packed radix 4 (one frame pair): 2^(K-1) 32-bit words per 8 iterations;
+//   natural layouts: words_per_stage(K) per stage.
+__host__ __device__ inline int64_t even_words(int64_t w) { return (w + 1) & ~(int64_t)1; }
+__host__ __device__ inline int64_t surv_words_blocks32(int K, int S) {
+  return even_words((int64_t)((S + 31) / 32) * (1 << (K - 1)) / 2);
+}
+__host__ __device__ inline int64_t surv_words_r4p(int K, int S) {
+  return even_words((int64_t)((S / 2 + 7) / 8) * (1 << (K - 1)) / 2);
+}
+__host__ __device__ inline int64_t surv_words_natural(int K, int S) {
+  return even_words((int64_t)S * words_per_stage(K));
+}
+// The traceback reads whole staging blocks past an item's end: slack words
+// after the last item.
+constexpr int64_t kSurvSlackWords = 32;
+
 }  // namespace mivit
