@@ -299,7 +299,7 @@ def other_configs(torch, mv):
     out["single_frame_1024"] = c1
     # one 2^26-bit stream, 4 dB, int8, chunks of 2048 with 64 stages of overlap
     n = 1 << 26
-    _, llr = make_stream(CODE_K7, n, 4.0, seed=3)
+    msg, llr = make_stream(CODE_K7, n, 4.0, seed=3)
     ls = mv.quantize_i8(torch.from_numpy(llr).to(dev), int8_scale_for(4.0, 2))
     del llr
     one = np.zeros(1, mv.FRAME_DTYPE)
@@ -308,10 +308,22 @@ def other_configs(torch, mv):
     bits, metric, end = plan.empty_outputs(dev)
     ms = _gpu_ms(torch, lambda: plan.decode(ls, bits, metric, end), 5)
     ops = 3 * 64 * plan.total_stages
+    chunked = mv.unpack_bits(bits.cpu().numpy()[: (n + 31) // 32], n)
+    plan.close()
+    # the same stream decoded whole (one unchunked frame, start 0, best end):
+    # the reference for the chunked decode's BER cost
+    whole_plan = mv.Plan([CODE_K7], one, "i8", 4)
+    wb, _, _ = whole_plan.decode(ls)
+    torch.cuda.synchronize()
+    whole = mv.unpack_bits(wb.cpu().numpy()[: (n + 31) // 32], n)
+    whole_plan.close()
     out["stream_2p26_chunk2048_ov64"] = {
         "ms": round(ms, 3), "gbit_s": round(n / ms / 1e6, 2), "stages": plan.total_stages,
-        "tops": round(ops / ms / 1e9, 2), "frac_packed_peak": round(ops / ms / 1e9 / VALU16_PEAK_TOPS, 3)}
-    del ls, bits
+        "tops": round(ops / ms / 1e9, 2), "frac_packed_peak": round(ops / ms / 1e9 / VALU16_PEAK_TOPS, 3),
+        "ber": float((chunked != msg).mean()), "whole_stream_ber": float((whole != msg).mean()),
+        "ber_vs_whole_stream": float((chunked != whole).mean()),
+        "bits_differing_from_whole_stream": int((chunked != whole).sum())}
+    del ls, bits, wb
     # 10000 frames, log-uniform lengths, three codes, Eb/N0 U[1,5]
     codes = [CODE_K5, CODE_K7, CODE_K9]
     F = 10000
@@ -392,12 +404,15 @@ def main():
         base, _, kv = v.partition(":")
         dt, radix = {"i8r4": ("i8", 4), "f32r2": ("f32", 2), "f16r2": ("f16", 2),
                      "i8r2": ("i8", 2), "i8r8": ("i8", 8)}[base]
-        plans[v] = mv.Plan([code], frames, dt, radix, variant=int(kv[1:]) if kv else 0)
+        # suffixes: ":vN" kernel variant N, ":nosplit" frame pairs kept whole
+        plans[v] = mv.Plan([code], frames, dt, radix,
+                           variant=int(kv[1:]) if kv.startswith("v") else 0,
+                           split=kv != "nosplit")
         llr = {"i8": llr_i8, "f32": llr_f32, "f16": llr_f16}[dt]
         ms, fwd, tb, bits, _ = time_variant(torch, mv, plans[v], llr, args.steps, args.warmup)
         dec = mv.unpack_bits(bits.cpu().numpy()[: N_FRAMES * (N_INFO // 32)].reshape(N_FRAMES, -1), N_INFO)
         decoded[v] = dec
-        peak = VALU16_PEAK_TOPS if base in PACKED16 and not kv else VALU32_PEAK_TOPS
+        peak = VALU16_PEAK_TOPS if base in PACKED16 and kv in ("", "nosplit") else VALU32_PEAK_TOPS
         results[v] = {
             "gbit_s": round(N_FRAMES * N_INFO / (ms * 1e-3) / 1e9, 3),
             "ms_per_step": round(ms, 4), "forward_ms": round(fwd, 4), "traceback_ms": round(tb, 4),

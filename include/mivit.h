@@ -106,7 +106,12 @@ typedef struct {
                        previous-state metrics fetched, 2: one partner metric
                        per lane; K = 8, 9: metrics exchanged through LDS
                        every stage), radix 4 through LDS, one frame per lane
-                       group and 32-bit metrics */
+                       group and 32-bit metrics; 3: radix 4 with the
+                       candidate additions on the int8 matrix cores, one
+                       16 x 16 x 32 MFMA per iteration holding all sixteen
+                       dragonflies through the dragonfly groups of
+                       §VIII-D-2 (int8, K = 7, beta = 2 codes with at most
+                       four groups, radix 4 only; else MIVIT_EUNSUPPORTED) */
   uint32_t flags;   /* MIVIT_PLAN_* scheduling options, below */
   int32_t reserved[2]; /* must be zero */
 } mivit_opts;
@@ -133,10 +138,25 @@ typedef struct {
  *                          shapes and keeps the fastest.  All choices give
  *                          identical results (for int8, radices 2, 4 and 8
  *                          the same path, ties included).  Uses extra device memory
- *                          for the plan's soft-value extent while creating. */
+ *                          for the plan's soft-value extent while creating.
+ *   MIVIT_PLAN_NO_SPLIT    keep every frame of the packed radix-4 kernel in one
+ *                          wavefront.  By default (K = 7), when the batch has
+ *                          fewer frame pairs than about four per SIMD, each
+ *                          long pair is cut into parts of whole 48-iteration
+ *                          periods decoded concurrently; a part after the
+ *                          first starts 192 stages early from all-zero path
+ *                          metrics (the unknown start of §III's frames) and
+ *                          keeps no decisions from them.  Its decisions are
+ *                          exact when its metrics where its own stages begin
+ *                          differ from the true ones by a constant in every
+ *                          state; a check after the forward pass compares the
+ *                          range-controlled metrics there bit for bit and
+ *                          re-decodes, from the true metrics, every pair
+ *                          whose check fails.  Results never depend on it. */
 #define MIVIT_PLAN_GRAPH 1u
 #define MIVIT_PLAN_AUTOTUNE 2u
 #define MIVIT_PLAN_PERSISTENT 4u
+#define MIVIT_PLAN_NO_SPLIT 8u
 
 typedef struct mivit_plan mivit_plan;
 

@@ -88,7 +88,7 @@ class Plan:
 
     def __init__(self, codes: Sequence, frames: np.ndarray, dtype: str = "f32", radix: int = 0,
                  chunk: int = 0, overlap: int = 0, variant: int = 0, graph: bool = False,
-                 autotune: bool = False, persistent: bool = False):
+                 autotune: bool = False, persistent: bool = False, split: bool = True):
         lib = _capi.load()
         self.codes = [_as_code(c) for c in codes]
         self.frames = np.ascontiguousarray(frames, dtype=FRAME_DTYPE)
@@ -99,7 +99,8 @@ class Plan:
         opts.variant = int(variant)
         opts.flags = ((_capi.MIVIT_PLAN_GRAPH if graph else 0) |
                       (_capi.MIVIT_PLAN_AUTOTUNE if autotune else 0) |
-                      (_capi.MIVIT_PLAN_PERSISTENT if persistent else 0))
+                      (_capi.MIVIT_PLAN_PERSISTENT if persistent else 0) |
+                      (0 if split else _capi.MIVIT_PLAN_NO_SPLIT))
         h = ctypes.c_void_p()
         st = lib.mivit_plan_create(ctypes.byref(h), arr, len(self.codes),
                                    self.frames.ctypes.data if len(self.frames) else None,

@@ -21,7 +21,7 @@ EXPORTS = (
     "mivit_stream_create", "mivit_stream_push", "mivit_stream_finish", "mivit_stream_destroy",
     "mivit_decode_uniform",
 )
-MIVIT_PLAN_GRAPH, MIVIT_PLAN_AUTOTUNE, MIVIT_PLAN_PERSISTENT = 1, 2, 4
+MIVIT_PLAN_GRAPH, MIVIT_PLAN_AUTOTUNE, MIVIT_PLAN_PERSISTENT, MIVIT_PLAN_NO_SPLIT = 1, 2, 4, 8
 
 
 class Code(ctypes.Structure):

@@ -35,13 +35,18 @@ hipError_t launch_fwd_wide(int K, int beta, int dt, const DevCode* codes, const 
 hipError_t launch_tb_seg(int layout, const DevCode* codes, const Item* items, int n_items,
                          const uint64_t* surv, const int32_t* item_end, uint32_t* bits,
                          int warm, hipStream_t st);
-hipError_t launch_fwd_r4p(int K, const DevCode* codes, const Item* items, const int2* waves,
-                          int n_waves, const int8_t* llr, uint64_t* surv, int64_t* metric,
+hipError_t launch_fwd_r4p(int K, const DevCode* codes, const Item* items, const R4Unit* units,
+                          int n_units, const int8_t* llr, uint64_t* surv, int64_t* metric,
                           int32_t* end_out, int32_t* item_end, int32_t* counter, int grid_limit,
+                          R4Bound* bounds, int64_t* last_m, const R4Unit* split, int n_split,
+                          int64_t* rep_m0, R4Unit* rep_units, int32_t* rep_count,
                           hipStream_t st);
 hipError_t launch_tb_r4p(int K, const Item* items, const int2* pairs, int n_pairs,
                          const uint64_t* surv, const int32_t* item_end, uint32_t* bits, int warm,
                          hipStream_t st);
+hipError_t launch_fwd_r4_mfma(const MfmaGroups& G, const DevCode* codes, const Item* items,
+                              int n_items, const int8_t* llr, uint64_t* surv, int64_t* metric,
+                              int32_t* end_out, int32_t* item_end, hipStream_t st);
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st);
 hipError_t launch_fill_random(void* p, int64_t n, int dt, uint32_t seed, hipStream_t st);
 }  // namespace mivit
@@ -56,6 +61,7 @@ enum : int {
   kKernRot4P = 3,
   kKernWide = 4,
   kKernGeneric8 = 5,
+  kKernMfma4 = 6,  // radix 4, candidate additions on the int8 matrix cores
 };
 enum : int {
   kLayoutNatR2 = 0,
@@ -86,7 +92,20 @@ struct Choice {
   int radix = 2;
   int variant = 0;
   bool persistent = false;
+  bool split = true;  // packed radix 4: split long frame pairs in time
 };
+
+// Time split of the packed radix-4 forward: frame pairs are cut into parts
+// of whole 48-iteration periods (the digit-map period times the table
+// block), later parts warming up for kSplitWarm iterations (192 stages)
+// from all-zero metrics.  Parts are added until the batch has about
+// kSplitWavesPerSimd wavefronts per SIMD, each part at least kSplitMinIt
+// iterations long.
+constexpr int kSplitAlign = 48;
+constexpr int kSplitWarm = 96;
+constexpr int kSplitMinIt = 384;
+constexpr int kSplitMaxParts = 8;
+constexpr int kSplitWavesPerSimd = 4;
 
 struct PlanGroup {
   int kern;   // forward kernel
@@ -116,6 +135,18 @@ struct Part {
   int2* d_pairs = nullptr;  // packed radix-4 traceback: (first item, count) per frame pair
   int32_t* d_counters = nullptr;
   int n_counters = 0;
+  // packed radix 4: work units (parts of entries), split entries' part-0
+  // units, boundary records, last-part metrics, repair units and count
+  R4Unit* d_units = nullptr;
+  int n_units = 0;
+  R4Unit* d_split = nullptr;
+  int n_split = 0;
+  R4Bound* d_bounds = nullptr;
+  int64_t* d_last_m = nullptr;
+  int64_t* d_rep_m0 = nullptr;
+  R4Unit* d_rep_units = nullptr;
+  int32_t* d_rep_count = nullptr;
+  MfmaGroups mg{};  // dragonfly groups (matrix-core radix-4 kernel)
 };
 
 struct GraphEntry {
@@ -180,6 +211,12 @@ int nsl_of(int K) { return K <= 7 ? 1 : (1 << (K - 1)) / 64; }
 
 bool packed_ok(const mivit_code& c) { return c.beta == 2 && (c.K == 5 || c.K == 7); }
 
+// The matrix-core radix-4 kernel: K = 7, rate 1/2, at most four dragonfly groups.
+bool mfma_ok(const mivit_code& c) {
+  MfmaGroups g;
+  return mfma_groups(c.K, c.beta, c.gen, &g);
+}
+
 mivit_status hip_status(hipError_t e) {
   return e == hipSuccess ? MIVIT_OK : (e == hipErrorOutOfMemory ? MIVIT_ENOMEM : MIVIT_EHIP);
 }
@@ -191,6 +228,13 @@ void free_part(Part& q) {
   (void)hipFree(q.d_waves);
   (void)hipFree(q.d_pairs);
   (void)hipFree(q.d_counters);
+  (void)hipFree(q.d_units);
+  (void)hipFree(q.d_split);
+  (void)hipFree(q.d_bounds);
+  (void)hipFree(q.d_last_m);
+  (void)hipFree(q.d_rep_m0);
+  (void)hipFree(q.d_rep_units);
+  (void)hipFree(q.d_rep_count);
   q = Part();
 }
 
@@ -278,6 +322,8 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
   int kern;
   if (ch.radix == 8)
     kern = kKernGeneric8;
+  else if (ch.radix == 4 && ch.variant == 3)
+    kern = kKernMfma4;
   else if (ch.radix == 4)
     kern = (ch.variant == 0 && packed_ok(c) && i8) ? kKernRot4P : kKernGeneric4;
   else
@@ -293,7 +339,7 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
   g.layout = kern == kKernRot2      ? kLayoutRotR2
              : kern == kKernRot4P   ? kLayoutRot4P
              : kern == kKernWide    ? kLayoutRotByte
-             : kern == kKernGeneric4 ? kLayoutNatR4
+             : (kern == kKernGeneric4 || kern == kKernMfma4) ? kLayoutNatR4
              : kern == kKernGeneric8 ? kLayoutNatR8
                                      : kLayoutNatR2;
   g.nsl = nsl_of(c.K);
@@ -311,6 +357,9 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
   // 64/2^(K-1) frames; packed radix 4: up to 2*64/2^(K-1), where the two
   // frames of a lane group must also emit the same stages)
   std::vector<int2> waves, pairs;
+  std::vector<R4Unit> units, split;
+  std::vector<R4Bound> bounds;
+  int n_bounds = 0;
   std::vector<char> pair_hi(items.size(), 0);
   if (kern == kKernRot2 || kern == kKernRot4P) {
     const bool packed = kern == kKernRot4P;
@@ -335,6 +384,47 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
       for (const int2& w : waves)
         for (int s = 0; s < w.y; s += 2) pairs.push_back(make_int2(w.x + s, std::min(2, w.y - s)));
       g.n_pairs = (int)pairs.size();
+      // work units: whole entries, or (K = 7) parts of frame pairs in time
+      int parts_max = 1;
+      // (persistent launches keep frame pairs whole)
+      if (ch.split && !ch.persistent && c.K == 7 && !waves.empty()) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            cus > 0) {
+          const int64_t target = (int64_t)cus * 4 * kSplitWavesPerSimd;
+          parts_max = (int)std::min<int64_t>(kSplitMaxParts,
+                                             (target + (int64_t)waves.size() - 1) / (int64_t)waves.size());
+        }
+      }
+      for (const int2& w : waves) {
+        const int n_it = items[w.x].n_stages >> 1;
+        const int P = std::max(1, std::min(parts_max, n_it / kSplitMinIt));
+        R4Unit u;
+        u.first = w.x;
+        u.count = w.y;
+        u.warm = 0;
+        u.n_parts = P;
+        u.bnd = P > 1 ? n_bounds : -1;
+        int prev = 0;
+        for (int k = 0; k < P; ++k) {
+          const int end = k == P - 1 ? n_it : (int)((int64_t)n_it * (k + 1) / P) / kSplitAlign * kSplitAlign;
+          u.part = k;
+          u.it_begin = prev;
+          u.it_end = end;
+          u.warm = k == 0 ? 0 : std::min(kSplitWarm, prev);
+          units.push_back(u);
+          if (k == 0 && P > 1) split.push_back(u);
+          if (k > 0) {
+            R4Bound b;
+            std::memset(&b, 0, sizeof b);
+            b.it_at = prev;
+            bounds.push_back(b);
+          }
+          prev = end;
+        }
+        if (P > 1) n_bounds += P - 1;
+      }
     }
     if (ch.persistent) g.counter = q.n_counters++;
   }
@@ -356,6 +446,7 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
   }
   words_total += kSurvSlackWords;
   q.surv_words = words_total;
+  if (kern == kKernMfma4 && !mfma_groups(c.K, c.beta, c.gen, &q.mg)) return MIVIT_EUNSUPPORTED;
   if (!items.empty()) q.groups.push_back(g);
   q.items = items;
   hipError_t e = upload(&q.d_items, items.data(), items.size());
@@ -367,6 +458,17 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
     e = hipMalloc((void**)&q.d_surv, (size_t)words_total * sizeof(uint64_t));
   if (e == hipSuccess && q.n_counters > 0)
     e = hipMalloc((void**)&q.d_counters, q.n_counters * sizeof(int32_t));
+  q.n_units = (int)units.size();
+  q.n_split = (int)split.size();
+  if (e == hipSuccess) e = upload(&q.d_units, units.data(), units.size());
+  if (e == hipSuccess) e = upload(&q.d_split, split.data(), split.size());
+  if (e == hipSuccess) e = upload(&q.d_bounds, bounds.data(), bounds.size());
+  if (e == hipSuccess && q.n_split > 0) {
+    e = hipMalloc((void**)&q.d_last_m, items.size() * sizeof(int64_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&q.d_rep_m0, items.size() * sizeof(int64_t));
+    if (e == hipSuccess) e = upload(&q.d_rep_units, split.data(), split.size());
+    if (e == hipSuccess) e = hipMalloc((void**)&q.d_rep_count, sizeof(int32_t));
+  }
   if (e != hipSuccess) {
     free_part(q);
     return hip_status(e);
@@ -385,9 +487,13 @@ hipError_t part_forward(const mivit_plan* p, const Part& q, const void* llr, voi
       if (e != hipSuccess) return e;
     }
     if (g.kern == kKernRot4P)
-      e = launch_fwd_r4p(g.K, p->d_codes, q.d_items, q.d_waves + g.wave_off, g.n_waves,
-                         (const int8_t*)llr, q.d_surv, (int64_t*)metric, end_state,
-                         q.d_item_end, counter, 0, st);
+      e = launch_fwd_r4p(g.K, p->d_codes, q.d_items, q.d_units, q.n_units, (const int8_t*)llr,
+                         q.d_surv, (int64_t*)metric, end_state, q.d_item_end, counter, 0,
+                         q.d_bounds, q.d_last_m, q.d_split, q.n_split, q.d_rep_m0,
+                         q.d_rep_units, q.d_rep_count, st);
+    else if (g.kern == kKernMfma4)
+      e = launch_fwd_r4_mfma(q.mg, p->d_codes, q.d_items + g.first, g.count, (const int8_t*)llr,
+                             q.d_surv, (int64_t*)metric, end_state, q.d_item_end, st);
     else if (g.kern == kKernWide)
       e = launch_fwd_wide(g.K, g.beta, dt, p->d_codes, q.d_items + g.first, g.count, llr,
                           q.d_surv, metric, end_state, q.d_item_end, st);
@@ -447,11 +553,12 @@ hipError_t run_parts(mivit_plan* p, int phases, const void* llr, uint32_t* bits,
 // Candidate kernel choices of a part, for the autotuner.
 std::vector<Choice> candidates(const mivit_code& c, int dtype, int radix) {
   std::vector<Choice> out;
-  auto add = [&](int r, int v, bool pers) {
+  auto add = [&](int r, int v, bool pers, bool split = true) {
     Choice ch;
     ch.radix = r;
     ch.variant = v;
     ch.persistent = pers;
+    ch.split = split;
     out.push_back(ch);
   };
   const bool i8 = dtype == MIVIT_I8;
@@ -474,8 +581,10 @@ std::vector<Choice> candidates(const mivit_code& c, int dtype, int radix) {
     if (packed_ok(c)) {
       add(4, 0, false);
       add(4, 0, true);
+      add(4, 0, false, false);  // frame pairs not split in time
     }
     add(4, 1, false);
+    if (mfma_ok(c)) add(4, 3, false);
   }
   if (i8 && (radix == 0 || radix == 8) && c.K >= 4) add(8, 0, false);
   return out;
@@ -510,6 +619,7 @@ const char* kern_name(int kern) {
     case kKernWide: return "radix-2 rotating, states in registers";
     case kKernRot4P: return "radix-4 packed two-frame";
     case kKernGeneric8: return "radix-8 generic";
+    case kKernMfma4: return "radix-4 matrix-core candidate additions";
   }
   return "?";
 }
@@ -546,8 +656,10 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
   if (o.radix != 0 && o.radix != 2 && o.radix != 4 && o.radix != 8) return MIVIT_EINVAL;
   if ((o.radix == 4 || o.radix == 8) && o.dtype != MIVIT_I8) return MIVIT_EINVAL;
   if (o.chunk < 0 || o.overlap < 0 || (o.chunk > 0 && o.chunk % 32 != 0)) return MIVIT_EINVAL;
-  if (o.variant < 0 || o.variant > 2) return MIVIT_EINVAL;
-  if (o.flags & ~(MIVIT_PLAN_GRAPH | MIVIT_PLAN_AUTOTUNE | MIVIT_PLAN_PERSISTENT))
+  if (o.variant < 0 || o.variant > 3) return MIVIT_EINVAL;
+  if (o.variant == 3 && (o.radix != 4 || o.dtype != MIVIT_I8)) return MIVIT_EUNSUPPORTED;
+  if (o.flags & ~(MIVIT_PLAN_GRAPH | MIVIT_PLAN_AUTOTUNE | MIVIT_PLAN_PERSISTENT |
+                  MIVIT_PLAN_NO_SPLIT))
     return MIVIT_EINVAL;
   if (o.reserved[0] != 0 || o.reserved[1] != 0) return MIVIT_EINVAL;
   for (int c = 0; c < n_codes; ++c) {
@@ -555,6 +667,9 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
     if (s != MIVIT_OK) return s;
   }
   if (o.dtype == MIVIT_F16 && o.variant != 0) return MIVIT_EUNSUPPORTED;
+  if (o.variant == 3)
+    for (int c = 0; c < n_codes; ++c)
+      if (!mfma_ok(codes[c])) return MIVIT_EUNSUPPORTED;
   if (o.radix == 8) {  // one kernel, and at least 8 states
     if (o.variant != 0) return MIVIT_EUNSUPPORTED;
     for (int c = 0; c < n_codes; ++c)
@@ -634,6 +749,7 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
       base.radix = o.radix == 0 ? 2 : o.radix;
       base.variant = o.variant;
       base.persistent = (o.flags & MIVIT_PLAN_PERSISTENT) != 0;
+      base.split = (o.flags & MIVIT_PLAN_NO_SPLIT) == 0;
       std::vector<Choice> cand = tune ? candidates(codes[c], o.dtype, o.radix)
                                       : std::vector<Choice>{base};
       Part best;

@@ -31,6 +31,37 @@ struct Item {
   int32_t slot;       // index of this item in per-item scratch arrays
 };
 
+// One unit of work of the packed radix-4 forward kernel: the frames of one
+// wavefront-table entry (first item, count) over the iterations
+// [it_begin, it_end).  An entry decoded whole is one unit (part 0 of 1).  An
+// entry split in time is n_parts units that run concurrently: unit p > 0
+// first runs `warm` iterations before it_begin from all-zero path metrics
+// (an unknown start, as for the windows of §III) and keeps no decisions from
+// them.  Its decisions are exact when its metrics at it_begin differ from
+// the true ones by a constant, which a check after the forward pass
+// establishes; otherwise a repair unit restarts the frames at it_begin from
+// the metrics part p-1 left there.
+struct R4Unit {
+  int32_t first, count;
+  int32_t it_begin, it_end;
+  int32_t warm;
+  int32_t part, n_parts;
+  int32_t bnd;  // split entries: index of the entry's first boundary record, else -1
+};
+
+// The two sides of boundary k of a split entry (between parts k and k+1, at
+// iteration it_begin of part k+1), per lane: packed metrics (low two bits
+// cleared, after the range control of that iteration), and per frame half
+// the metric of state 0 there, each part counting from its own origin.
+struct R4Bound {
+  uint32_t v_start[64];  // part k+1 after its warm-up
+  uint32_t v_end[64];    // part k at its end
+  int64_t m_start[2];
+  int64_t m_end[2];
+  int32_t it_at;         // the boundary's iteration (part k+1's it_begin)
+  int32_t pad;
+};
+
 // Frame facts the gradient kernel needs.
 struct GradFrame {
   int64_t llr_off;
@@ -39,6 +70,58 @@ struct GradFrame {
   int32_t n_out;   // decoded bits stored; stages >= n_out carry input 0
   int32_t code;
   int32_t pad;
+};
+
+// Dragonfly groups of a K = 7 rate-1/2 code for the matrix-core radix-4
+// kernel (§VIII-D-2): dragonfly f's super-branch outputs are those of
+// leader[group[f]] with the left index y replaced by y ^ a[f].  Unused
+// groups have leader -1.
+struct MfmaGroups {
+  int32_t group[16];
+  int32_t a[16];
+  int32_t leader[4];
+};
+// Fills G from the code; false when the code is not K = 7, rate 1/2 or
+// needs more than four groups.
+bool mfma_groups(int K, int beta, const uint32_t* gen, MfmaGroups* G);
+
+// Decoded bits of one traceback lane, emitted from the highest stage down:
+// bit k (relative to the item's first emitted stage) goes to bit k % 32 of
+// output word (bit_off + k) / 32.  Finished words are held until the
+// aligned group of four words they belong to is complete (or the chase
+// ends) and then stored together, so each 16-byte piece of the output
+// reaches memory in one burst instead of four partial-line writes spread
+// over the whole chase.  Lanes own whole words, so the stores never
+// overlap.
+struct GroupEmitter {
+  uint32_t word = 0;
+  uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0;
+  uint32_t valid = 0;  // pending words, bit i for word gbase + i
+  int64_t gbase = 0;
+  __device__ __forceinline__ void flush(uint32_t* bits) {
+    if (valid & 1u) bits[gbase] = q0;
+    if (valid & 2u) bits[gbase + 1] = q1;
+    if (valid & 4u) bits[gbase + 2] = q2;
+    if (valid & 8u) bits[gbase + 3] = q3;
+    valid = 0;
+  }
+  __device__ __forceinline__ void put(int k, uint32_t u, uint32_t* bits, int64_t bit_off) {
+    word |= u << (k & 31);
+    if ((k & 31) == 0) {
+      const int64_t w = (bit_off + k) >> 5;
+      const int64_t g = w & ~(int64_t)3;
+      if (valid && g != gbase) flush(bits);
+      gbase = g;
+      const int i = (int)(w & 3);
+      q0 = i == 0 ? word : q0;
+      q1 = i == 1 ? word : q1;
+      q2 = i == 2 ? word : q2;
+      q3 = i == 3 ? word : q3;
+      valid |= 1u << i;
+      word = 0;
+      if (i == 0) flush(bits);
+    }
+  }
 };
 
 // Workgroups a persistent grid of 'kernel' keeps resident on the device

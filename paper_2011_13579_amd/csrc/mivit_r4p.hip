@@ -59,6 +59,8 @@
 
 namespace mivit {
 
+hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st);
+
 namespace r4p {
 
 constexpr uint32_t kBase = 16384;
@@ -145,7 +147,8 @@ struct Fwd {
   uint32_t acc;               // decisions of the current group of 8 iterations
   uint32_t vs;                // max result of the last even iteration (its tags)
   uint32_t* sv;               // survivor words of the lane group
-  int r, n_it;
+  int r, n_it;                // n_it: one past the last iteration this unit runs
+  int it_store;               // first iteration whose decisions are stored
   bool store;
   uint64_t off0, off1;        // accumulated renormalisation amounts
 };
@@ -214,7 +217,7 @@ template <int ND>
 __device__ __forceinline__ void group_end(Fwd<ND>& F, int last) {
   constexpr int NS = Fwd<ND>::NS;
   const int n = (last & 7) + 1;
-  if (F.store) F.sv[(last >> 3) * NS + F.r] = F.acc;
+  if (F.store && last >= F.it_store) F.sv[(last >> 3) * NS + F.r] = F.acc;
   F.acc = 0;
   if (n == 8) {
     // bring state 0 (lane 0 of the group) back to kBase in both halves
@@ -335,10 +338,15 @@ constexpr int kR4Waves = 4;
 
 // One wavefront decodes up to 2 * 64 / 2^(K-1) frames of equal length:
 // lane group m (2^(K-1) lanes) holds frames 2m (low halves) and 2m+1 (high).
+// It runs the iterations of one unit (whole frames, one part of frames split
+// in time, or a repair, kind 1).  Split units that are not last leave their
+// end metrics in a boundary record; the last part reports the end state and
+// its own metric, which the check completes.
 template <int ND>
 __device__ __forceinline__ void fwd_r4p_wave(const DevCode* __restrict__ codes,
-                                             const Item* __restrict__ items,
-                                             const int2* __restrict__ waves, int wave,
+                                             const Item* __restrict__ items, const R4Unit U,
+                                             int kind, R4Bound* bounds, int64_t* last_m,
+                                             const int64_t* rep_m0,
                                              const int8_t* __restrict__ llr,
                                              uint64_t* __restrict__ surv, int64_t* metric,
                                              int32_t* end_out, int32_t* item_end,
@@ -346,19 +354,23 @@ __device__ __forceinline__ void fwd_r4p_wave(const DevCode* __restrict__ codes,
   using namespace r4p;
   constexpr int KM1 = 2 * ND, NS = 1 << KM1, PPL = 256 / NS;
   const int m = lane / NS, r = lane % NS;
-  const int2 wv = waves[wave];
-  const bool va = 2 * m < wv.y, vb = 2 * m + 1 < wv.y;
-  const int ia = wv.x + (va ? 2 * m : 0);
+  const bool va = 2 * m < U.count, vb = 2 * m + 1 < U.count;
+  const int ia = U.first + (va ? 2 * m : 0);
   const int ib_ = vb ? ia + 1 : ia;  // a missing frame B repeats frame A
   const Item ita = items[ia], itb = items[ib_];
   const DevCode c = codes[ita.code];
   const int S = __builtin_amdgcn_readfirstlane(ita.n_stages);  // equal within the wave
-  const int lead = S & 1, n_it = S >> 1;
+  const int lead = S & 1;
+  // iterations: warm-up from s0, decisions kept from it_b, last one it_e - 1
+  const int it_b = U.it_begin, it_e = U.it_end, s0 = U.it_begin - U.warm;
+  const bool first_part = kind == 0 && U.part == 0;
+  const bool split = U.n_parts > 1;
 
   Fwd<ND> F;
   F.tbl = &tbl_w[m][0];
   F.r = r;
-  F.n_it = n_it;
+  F.n_it = it_e;
+  F.it_store = it_b;
   // lanes 4k .. 4k+3 (K = 7) fill row k, so one 16-byte store per lane
   // covers the table contiguously (no LDS bank conflicts)
   F.ib = r / (16 / PPL);
@@ -378,8 +390,9 @@ __device__ __forceinline__ void fwd_r4p_wave(const DevCode* __restrict__ codes,
   }
   lane_consts<ND, 0>(F, c, lane, r);
 
-  // metrics entering iteration 0 (lane r holds state r)
-  {
+  // metrics entering iteration s0 (lane r holds state r: s0 is a multiple of
+  // the digit count, so the map is the identity there)
+  if (first_part) {
     const int j = r;
     uint32_t v[2];
     const Item* its[2] = {&ita, &itb};
@@ -405,17 +418,47 @@ __device__ __forceinline__ void fwd_r4p_wave(const DevCode* __restrict__ codes,
       }
     }
     F.V = v[0] | (v[1] << 16) | F.tag[0];
+  } else if (kind == 0) {
+    F.V = kBase2 | F.tag[0];  // a later part: all-zero metrics (unknown start)
+  } else {
+    F.V = (bounds[U.bnd + U.part - 1].v_end[lane] & kStrip) | F.tag[0];  // repair
   }
   {
-    const bool ok = F.ib < n_it;
-    F.w0 = ok ? load_llr4(F.l0 + 4 * F.ib) : 0u;
-    F.w1 = ok ? load_llr4(F.l1 + 4 * F.ib) : 0u;
+    const int itn = s0 + F.ib;
+    const bool ok = itn < it_e;
+    F.w0 = ok ? load_llr4(F.l0 + 4 * (int64_t)itn) : 0u;
+    F.w1 = ok ? load_llr4(F.l1 + 4 * (int64_t)itn) : 0u;
   }
+  // metric of state 0 from this unit's origin, per half, at iteration x
+  // (range control has just brought state 0 back to kBase there)
+  auto m0_at = [&](int x, int h) -> int64_t {
+    const int64_t o = (int64_t)(h ? F.off1 : F.off0);
+    return o / 4 - (int64_t)(kBias / 4) * (x - s0) - (first_part ? (int64_t)kLeadOff * lead : 0);
+  };
   constexpr int SUPER = (ND == 3) ? 3 : 1;  // blocks per period of the phase pattern
-  for (int it0 = 0; it0 < n_it; it0 += 16 * SUPER) super_block<ND, 0, SUPER>(F, it0);
+  for (int it0 = s0; it0 < it_e; it0 += 16 * SUPER) {
+    if (kind == 0 && U.part > 0 && it0 == it_b) {
+      R4Bound& B = bounds[U.bnd + U.part - 1];
+      B.v_start[lane] = F.V & kStrip;
+      if (lane == 0) {
+        B.m_start[0] = m0_at(it_b, 0);
+        B.m_start[1] = m0_at(it_b, 1);
+      }
+    }
+    super_block<ND, 0, SUPER>(F, it0);
+  }
+  if (kind == 0 && split && U.part < U.n_parts - 1) {
+    R4Bound& B = bounds[U.bnd + U.part];
+    B.v_end[lane] = F.V & kStrip;
+    if (lane == 0) {
+      B.m_end[0] = m0_at(it_e, 0);
+      B.m_end[1] = m0_at(it_e, 1);
+    }
+    return;
+  }
 
-  // final metrics: lane r holds state rotr(r, 2 (n_it mod ND))
-  const int js_lane = rotr_n(r, (2 * (n_it % ND)) % KM1, KM1);
+  // final metrics: lane r holds state rotr(r, 2 (it_e mod ND))
+  const int js_lane = rotr_n(r, (2 * (it_e % ND)) % KM1, KM1);
   const uint32_t vs = F.V & kStrip;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -430,19 +473,22 @@ __device__ __forceinline__ void fwd_r4p_wave(const DevCode* __restrict__ codes,
     }
     const bool fixed = it.end_state >= 0;
     const int js = fixed ? it.end_state : 255 - (int)(key & 255);
-    const int src = m * NS + rotl_n(js & (NS - 1), (2 * (n_it % ND)) % KM1, KM1);
+    const int src = m * NS + rotl_n(js & (NS - 1), (2 * (it_e % ND)) % KM1, KM1);
     const uint32_t vfix = (uint32_t)__shfl((int)val, src);
     const uint32_t vbest = fixed ? vfix : key >> 8;
     if (r == 0 && valid) {
       item_end[it.slot] = js;
-      if (it.frame >= 0) {
+      const int64_t o = (int64_t)(h ? F.off1 : F.off0);
+      const int64_t local = ((int64_t)vbest - (int64_t)kBase + o) / 4 -
+                            (int64_t)(kBias / 4) * (it_e - s0) -
+                            (first_part ? (int64_t)kLeadOff * lead : 0);
+      if (kind == 0 && split) {
+        last_m[it.slot] = local;  // completed by the check
+      } else if (it.frame >= 0) {
         if (end_out) end_out[it.frame] = js;
-        if (metric) {
-          const int64_t o = (int64_t)(h ? F.off1 : F.off0);
-          metric[it.frame] = ((int64_t)vbest - (int64_t)kBase + o) / 4 -
-                             (int64_t)(kBias / 4) * n_it - (int64_t)kLeadOff * lead;
-        }
+        if (metric) metric[it.frame] = local + (kind == 1 ? rep_m0[it.slot] : 0);
       }
+      if (kind == 0 && split && it.frame >= 0 && end_out) end_out[it.frame] = js;
     }
   }
 }
@@ -481,17 +527,6 @@ __device__ __forceinline__ int lane_of(uint32_t A) {
 // byte position of lane-digit slot s in the offset form
 __device__ __forceinline__ int slot_pos(int s) { return s == 0 ? 2 : (s == 1 ? 9 : 11); }
 
-struct Emit {
-  uint32_t word = 0;
-  __device__ __forceinline__ void put(int k, uint32_t bit, uint32_t* bits, int64_t bit_off) {
-    word |= bit << (k & 31);
-    if ((k & 31) == 0) {
-      bits[(bit_off + k) >> 5] = word;
-      word = 0;
-    }
-  }
-};
-
 struct Chase {
   int hi, lo;       // iterations hi-1 down to lo are traced (lo >= 0)
   int a, b;         // stages [a, b) are emitted
@@ -518,7 +553,7 @@ __device__ __forceinline__ void chase_all(Chase& c, bool go, bool pair_go, const
                                           uint32_t* bits, int64_t bit_off) {
   constexpr int KM1 = Tb<ND>::KM1, NS = Tb<ND>::NS, IPB = Tb<ND>::IPB;
   const int lane = threadIdx.x & 63;
-  Emit em;
+  GroupEmitter em;
   const bool any = pair_go && c.hi > c.lo;
   const int B0 = any ? (c.hi - 1) / IPB : 0;
   const int nb = any ? B0 - c.lo / IPB + 1 : 0;
@@ -563,6 +598,7 @@ __device__ __forceinline__ void chase_all(Chase& c, bool go, bool pair_go, const
     if (c.emit && lead && c.lo == 0 && c.a <= 0 && c.b > 0)
       em.put(-ob, (uint32_t)(lane_of(A) >> (KM1 - 1)), bits, bit_off);
   }
+  em.flush(bits);
 }
 
 }  // namespace r4p
@@ -642,51 +678,124 @@ __global__ __launch_bounds__(64) void k_tb_r4p(const Item* __restrict__ items,
   }
 }
 
-// One wavefront per wave-table entry, or (counter != nullptr) a persistent
-// grid whose wavefronts take entries in table order from a device counter
-// that starts at zero, until the table is exhausted.
+// One wavefront per unit, or (counter != nullptr) a persistent grid whose
+// wavefronts take units in table order from a device counter that starts at
+// zero, until the table is exhausted.  Repair launches (kind 1) read their
+// unit count from the device (dev_count).
 template <int ND>
 __global__ __launch_bounds__(64 * r4p::kR4Waves) void k_fwd_r4p(
     const DevCode* __restrict__ codes, const Item* __restrict__ items,
-    const int2* __restrict__ waves, int n_waves, const int8_t* __restrict__ llr,
+    const R4Unit* __restrict__ units, int n_units, const int32_t* dev_count, int kind,
+    R4Bound* bounds, int64_t* last_m, const int64_t* rep_m0, const int8_t* __restrict__ llr,
     uint64_t* __restrict__ surv, int64_t* metric, int32_t* end_out, int32_t* item_end,
     int32_t* counter) {
   constexpr int FPG = 64 >> (2 * ND);
   __shared__ uint32_t tbl_all[r4p::kR4Waves][FPG][16 * 16];
   const int wid = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
+  if (dev_count) n_units = min(n_units, __builtin_amdgcn_readfirstlane(*dev_count));
   if (counter == nullptr) {
-    const int wave = blockIdx.x * r4p::kR4Waves + wid;
-    if (wave >= n_waves) return;  // no workgroup barriers: safe to leave
-    fwd_r4p_wave<ND>(codes, items, waves, wave, llr, surv, metric, end_out, item_end,
-                     tbl_all[wid], lane);
+    const int u = blockIdx.x * r4p::kR4Waves + wid;
+    if (u >= n_units) return;  // no workgroup barriers: safe to leave
+    fwd_r4p_wave<ND>(codes, items, units[u], kind, bounds, last_m, rep_m0, llr, surv, metric,
+                     end_out, item_end, tbl_all[wid], lane);
     return;
   }
   for (;;) {
     int w = 0;
     if (lane == 0) w = atomicAdd(counter, 1);
     w = __builtin_amdgcn_readfirstlane(w);
-    if (w >= n_waves) break;
-    fwd_r4p_wave<ND>(codes, items, waves, w, llr, surv, metric, end_out, item_end,
-                     tbl_all[wid], lane);
+    if (w >= n_units) break;
+    fwd_r4p_wave<ND>(codes, items, units[w], kind, bounds, last_m, rep_m0, llr, surv, metric,
+                     end_out, item_end, tbl_all[wid], lane);
   }
 }
 
-hipError_t launch_fwd_r4p(int K, const DevCode* codes, const Item* items, const int2* waves,
-                          int n_waves, const int8_t* llr, uint64_t* surv, int64_t* metric,
+// The check after a split forward pass, one wavefront per split entry (its
+// part-0 unit): boundary k is exact when part k's metrics at its end equal
+// part k+1's after its warm-up in every lane (both are range-controlled to
+// state 0 there, so equal words mean metric vectors that differ by a
+// constant).  All exact: the frames' metrics are the last part's plus the
+// accumulated constants.  Else the entry gets a repair unit from its first
+// inexact boundary, with the true metric of state 0 there.
+__global__ __launch_bounds__(64 * r4p::kR4Waves) void k_r4p_check(
+    const Item* __restrict__ items, const R4Unit* __restrict__ split, int n_split,
+    const R4Bound* __restrict__ bounds, const int64_t* __restrict__ last_m, int64_t* rep_m0,
+    R4Unit* rep_units, int32_t* rep_count, int64_t* metric) {
+  const int lane = threadIdx.x & 63;
+  const int e = blockIdx.x * r4p::kR4Waves + (threadIdx.x >> 6);
+  if (e >= n_split) return;
+  const R4Unit U = split[e];
+  const int n_b = U.n_parts - 1;
+  int64_t T0 = bounds[U.bnd].m_end[0], T1 = bounds[U.bnd].m_end[1];  // part 0 is exact
+  int64_t D0 = 0, D1 = 0;
+  int fail = -1;
+  for (int k = 0; k < n_b; ++k) {
+    const R4Bound& B = bounds[U.bnd + k];
+    if (__ballot(B.v_end[lane] != B.v_start[lane]) != 0) {
+      fail = k;
+      break;
+    }
+    D0 = T0 - B.m_start[0];
+    D1 = T1 - B.m_start[1];
+    if (k + 1 < n_b) {
+      T0 = bounds[U.bnd + k + 1].m_end[0] + D0;
+      T1 = bounds[U.bnd + k + 1].m_end[1] + D1;
+    }
+  }
+  if (lane != 0) return;
+  const Item ia = items[U.first];
+  if (fail < 0) {
+    if (metric && ia.frame >= 0) metric[ia.frame] = last_m[ia.slot] + D0;
+    if (U.count > 1) {
+      const Item ib = items[U.first + 1];
+      if (metric && ib.frame >= 0) metric[ib.frame] = last_m[ib.slot] + D1;
+    }
+    return;
+  }
+  R4Unit R = U;
+  R.it_begin = (int)bounds[U.bnd + fail].it_at;
+  R.it_end = ia.n_stages >> 1;
+  R.warm = 0;
+  R.part = fail + 1;
+  rep_m0[ia.slot] = T0;
+  if (U.count > 1) rep_m0[items[U.first + 1].slot] = T1;
+  rep_units[atomicAdd(rep_count, 1)] = R;
+}
+
+hipError_t launch_fwd_r4p(int K, const DevCode* codes, const Item* items, const R4Unit* units,
+                          int n_units, const int8_t* llr, uint64_t* surv, int64_t* metric,
                           int32_t* end_out, int32_t* item_end, int32_t* counter, int grid_limit,
+                          R4Bound* bounds, int64_t* last_m, const R4Unit* split, int n_split,
+                          int64_t* rep_m0, R4Unit* rep_units, int32_t* rep_count,
                           hipStream_t st) {
-  if (n_waves <= 0) return hipSuccess;
+  if (n_units <= 0) return hipSuccess;
   if (K != 5 && K != 7) return hipErrorInvalidValue;
   auto kernel = K == 7 ? k_fwd_r4p<3> : k_fwd_r4p<2>;
   const int threads = 64 * r4p::kR4Waves;
-  int nb = (n_waves + r4p::kR4Waves - 1) / r4p::kR4Waves;
+  int nb = (n_units + r4p::kR4Waves - 1) / r4p::kR4Waves;
   if (counter) {
     const int lim = grid_limit > 0 ? grid_limit : resident_workgroups(kernel, threads);
     if (lim > 0 && nb > lim) nb = lim;
   }
-  hipLaunchKernelGGL(kernel, dim3(nb), dim3(threads), 0, st, codes, items, waves, n_waves, llr,
+  hipLaunchKernelGGL(kernel, dim3(nb), dim3(threads), 0, st, codes, items, units, n_units,
+                     (const int32_t*)nullptr, 0, bounds, last_m, (const int64_t*)nullptr, llr,
                      surv, metric, end_out, item_end, counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || n_split <= 0) return e;
+  // check the split entries, then repair the inexact ones
+  e = launch_zero_i32(rep_count, 1, st);
+  if (e != hipSuccess) return e;
+  const int ns = (n_split + r4p::kR4Waves - 1) / r4p::kR4Waves;
+  hipLaunchKernelGGL(k_r4p_check, dim3(ns), dim3(threads), 0, st, items, split, n_split,
+                     (const R4Bound*)bounds, (const int64_t*)last_m, rep_m0, rep_units, rep_count,
+                     metric);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kernel, dim3(ns), dim3(threads), 0, st, codes, items,
+                     (const R4Unit*)rep_units, n_split, (const int32_t*)rep_count, 1, bounds,
+                     last_m, (const int64_t*)rep_m0, llr, surv, metric, end_out, item_end,
+                     (int32_t*)nullptr);
   return hipGetLastError();
 }
 

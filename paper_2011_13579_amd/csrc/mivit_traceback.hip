@@ -73,17 +73,6 @@ __device__ __forceinline__ int rotl_bits(int x, int r, int n) {
   return ((x << r) | (x >> (n - r))) & ((1 << n) - 1);
 }
 
-struct Emitter {
-  uint32_t word = 0;
-  __device__ __forceinline__ void put(int k, int u, uint32_t* bits, int64_t bit_off) {
-    word |= (uint32_t)u << (k & 31);
-    if ((k & 31) == 0) {
-      bits[(bit_off + k) >> 5] = word;
-      word = 0;
-    }
-  }
-};
-
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
 // Stream this lane's 64-word block starting at src into LDS buffer buf_k
@@ -123,7 +112,7 @@ __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_
                                           uint32_t* bits, int64_t bit_off) {
   const int lane = threadIdx.x;
   const int SB = g.SB, WB = g.WB;
-  Emitter em;
+  GroupEmitter em;
   if (go && c.top == c.yb) c.y = c.j;
   if (go && c.top == c.xa) c.x = c.j;
   const int B0 = go ? (c.top - 1) / SB : 0;
@@ -148,7 +137,7 @@ __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_
           // odd stage count: the last stage was a radix-2 stage
           const int w = (t - t0) * 2 * g.W + (j >> 5);
           const int d = (word_at(cur, w, lane) >> (j & 31)) & 1;
-          if (t >= c.a && t < c.b) em.put(t - ob, j >> (g.KM1 - 1), bits, bit_off);
+          if (t >= c.a && t < c.b) em.put(t - ob, (uint32_t)(j >> (g.KM1 - 1)), bits, bit_off);
           j = ((j << 1) | d) & (g.NS - 1);
           if (t == c.yb) c.y = j;
           if (t == c.xa) c.x = j;
@@ -160,9 +149,9 @@ __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_
           const int w1 = (t - t0) * 2 * g.W + (j >> 5);
           const int yy = ((word_at(cur, w0, lane) >> (j & 31)) & 1) |
                          (((word_at(cur, w1, lane) >> (j & 31)) & 1) << 1);
-          if (t < c.b) em.put(t - ob, j >> (g.KM1 - 1), bits, bit_off);
+          if (t < c.b) em.put(t - ob, (uint32_t)(j >> (g.KM1 - 1)), bits, bit_off);
           if (t - 1 >= c.a && t - 1 < c.b)
-            em.put(t - 1 - ob, (j >> (g.KM1 - 2)) & 1, bits, bit_off);
+            em.put(t - 1 - ob, (uint32_t)((j >> (g.KM1 - 2)) & 1), bits, bit_off);
           j = 4 * (j & ((g.NS >> 2) - 1)) + yy;
           if (t - 1 == c.yb) c.y = j;
           if (t - 1 == c.xa) c.x = j;
@@ -172,7 +161,7 @@ __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_
         for (; t >= S - S % 3 && t >= t0 && t >= c.a; --t) {
           const int w = (t - t0) * 2 * g.W + (j >> 5);
           const int d = (word_at(cur, w, lane) >> (j & 31)) & 1;
-          if (t < c.b) em.put(t - ob, j >> (g.KM1 - 1), bits, bit_off);
+          if (t < c.b) em.put(t - ob, (uint32_t)(j >> (g.KM1 - 1)), bits, bit_off);
           j = ((j << 1) | d) & (g.NS - 1);
           if (t == c.yb) c.y = j;
           if (t == c.xa) c.x = j;
@@ -185,11 +174,11 @@ __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_
           const int yy = ((word_at(cur, w0, lane) >> sh) & 1) |
                          (((word_at(cur, w1, lane) >> sh) & 1) << 1) |
                          (((word_at(cur, w2, lane) >> sh) & 1) << 2);
-          if (t < c.b) em.put(t - ob, j >> (g.KM1 - 1), bits, bit_off);
+          if (t < c.b) em.put(t - ob, (uint32_t)(j >> (g.KM1 - 1)), bits, bit_off);
           if (t - 1 >= c.a && t - 1 < c.b)
-            em.put(t - 1 - ob, (j >> (g.KM1 - 2)) & 1, bits, bit_off);
+            em.put(t - 1 - ob, (uint32_t)((j >> (g.KM1 - 2)) & 1), bits, bit_off);
           if (t - 2 >= c.a && t - 2 < c.b)
-            em.put(t - 2 - ob, (j >> (g.KM1 - 3)) & 1, bits, bit_off);
+            em.put(t - 2 - ob, (uint32_t)((j >> (g.KM1 - 3)) & 1), bits, bit_off);
           j = 8 * (j & ((g.NS >> 3) - 1)) + yy;
           if (t - 2 == c.yb) c.y = j;
           if (t - 2 == c.xa) c.x = j;
@@ -205,7 +194,7 @@ __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_
           const int a = pos_bit(q);
           const uint32_t word = *(const uint32_t*)(cl + j);
           const int d = (int)((word >> (31 - (t & 31))) & 1u);
-          if (t < c.b) em.put(t - ob, (j >> a) & 1, bits, bit_off);
+          if (t < c.b) em.put(t - ob, (uint32_t)((j >> a) & 1), bits, bit_off);
           j = (j & ~(1 << a)) | (d << a);
           if (t == c.yb) c.y = j;
           if (t == c.xa) c.x = j;
@@ -219,7 +208,7 @@ __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_
           const int q = rot == 0 ? g.KM1 - 1 : rot - 1;  // t mod (K-1)
           const int w = ((t - t0) >> 3) * (g.NS >> 2) + (j >> 2);
           const int d = (word_at(cur, w, lane) >> (8 * (j & 3) + 7 - (t & 7))) & 1;
-          if (t < c.b) em.put(t - ob, (j >> q) & 1, bits, bit_off);
+          if (t < c.b) em.put(t - ob, (uint32_t)((j >> q) & 1), bits, bit_off);
           j = (j & ~(1 << q)) | (d << q);
           if (t == c.yb) c.y = j;
           if (t == c.xa) c.x = j;
@@ -230,7 +219,7 @@ __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_
         for (; t >= lo; --t) {
           const int w = (t - t0) * 2 * g.W + (j >> 5);
           const int d = (word_at(cur, w, lane) >> (j & 31)) & 1;
-          if (t < c.b) em.put(t - ob, j >> (g.KM1 - 1), bits, bit_off);
+          if (t < c.b) em.put(t - ob, (uint32_t)(j >> (g.KM1 - 1)), bits, bit_off);
           j = ((j << 1) | d) & (g.NS - 1);
           if (t == c.yb) c.y = j;
           if (t == c.xa) c.x = j;
@@ -239,6 +228,7 @@ __device__ __forceinline__ void chase_all(const TbGeom<LAYOUT>& g, const uint32_
       c.j = j;
     }
   }
+  em.flush(bits);
 }
 
 template <int LAYOUT>

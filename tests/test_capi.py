@@ -108,7 +108,7 @@ def test_overlapping_outputs():
     dict(dtype=3), dict(dtype=-1), dict(radix=3), dict(radix=16), dict(radix=4, dtype=0),
     dict(radix=4, dtype=2), dict(radix=8, dtype=0), dict(radix=8, dtype=2),
     dict(chunk=-1), dict(chunk=100),
-    dict(overlap=-1), dict(variant=3), dict(flags=8), dict(flags=1 << 31),
+    dict(overlap=-1), dict(variant=4), dict(flags=16), dict(flags=1 << 31),
 ])
 def test_bad_opts(opts):
     assert _plan_status([K7], _frame(), **opts) == _capi.MIVIT_EINVAL
@@ -229,3 +229,16 @@ def test_decode_uniform_rejects_before_device_work():
         got = lib.mivit_decode_uniform(llr, dt, ctypes.byref(code), F, n, term, bits, metric, st)
         assert got == want, (args, got)
     assert lib.mivit_decode_uniform(fake, 0, None, 4, 100, 1, fake, None, None) == _capi.MIVIT_EINVAL
+
+
+def test_mfma_variant_rejections():
+    """Variant 3 (radix 4 on the int8 matrix cores) takes int8 soft values,
+    radix 4 and K = 7 rate-1/2 codes; anything else is refused at plan time."""
+    fr = _frame()
+    assert _plan_status([K7], fr, dtype=0, radix=4, variant=3) == _capi.MIVIT_EINVAL  # float radix 4
+    assert _plan_status([K7], fr, dtype=1, radix=2, variant=3) == _capi.MIVIT_EUNSUPPORTED
+    assert _plan_status([_code(5, [0o23, 0o35])], fr, dtype=1, radix=4,
+                        variant=3) == _capi.MIVIT_EUNSUPPORTED
+    assert _plan_status([_code(9, [0o557, 0o663, 0o711])], fr, dtype=1, radix=4,
+                        variant=3) == _capi.MIVIT_EUNSUPPORTED
+    assert _plan_status([K7], fr, dtype=1, radix=4, variant=4) == _capi.MIVIT_EINVAL

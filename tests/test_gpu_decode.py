@@ -335,8 +335,8 @@ def test_determinism():
 def test_full_batch_4096x8192(dtype, eb, seed):
     """4096 terminated frames of 8192 bits (K=7): every frame of every plan
     equals the oracle.  int8: radix 2 and packed radix 4, direct and
-    persistent launches, bits and metrics identical to the exact-integer
-    oracle.  float32: radix 2, direct and persistent, bits and metrics
+    persistent launches, and radix 4 on the matrix cores, bits and metrics
+    identical to the exact-integer oracle.  float32: radix 2, direct and persistent, bits and metrics
     identical to the single-precision oracle, bits equal to the
     double-precision oracle on every frame whose runner-up gap exceeds the
     float32 error bound, metrics within 1e-5 of it.  3 dB with seed 2003 is
@@ -347,7 +347,7 @@ def test_full_batch_4096x8192(dtype, eb, seed):
     if dtype == "i8":
         llr = oracle.quantize_i8(b.llr, int8_scale_for(eb, 2))
         ob, om, _ = oracle.decode_uniform(CODE_K7, llr, n, True, oracle.I64)
-        runs = [(2, False), (4, False), (2, True), (4, True)]
+        runs = [(2, False), (4, False), (2, True), (4, True), (4, "mfma")]
     else:
         llr = b.llr
         ob, om, _ = oracle.decode_uniform(CODE_K7, llr, n, True, oracle.F32)
@@ -357,8 +357,11 @@ def test_full_batch_4096x8192(dtype, eb, seed):
     fr = mv.uniform_frames(CODE_K7, F, n, True)
     wpf = (n + 31) // 32
     for radix, pers in runs:
-        print("full", dtype, eb, radix, "persistent" if pers else "direct", flush=True)
-        plan = mv.Plan([CODE_K7], fr, dtype, radix, persistent=pers)
+        print("full", dtype, eb, radix, pers, flush=True)
+        if pers == "mfma":  # candidate additions on the matrix cores
+            plan = mv.Plan([CODE_K7], fr, dtype, radix, variant=3)
+        else:
+            plan = mv.Plan([CODE_K7], fr, dtype, radix, persistent=pers)
         w, m, _ = plan.decode(t)
         torch.cuda.synchronize()
         bits = mv.unpack_bits(w.cpu().numpy()[: F * wpf].reshape(F, wpf), n)
@@ -550,11 +553,24 @@ def test_stream_2p26_chunked_full(radix):
     print("stream BER %.3e" % ber, flush=True)
     assert ber < 1e-3
     if radix == 4:
-        whole, _ = oracle.decode_stream_whole(CODE_K7, q, n, oracle.I64)
+        whole, wm = oracle.decode_stream_whole(CODE_K7, q, n, oracle.I64)
         d = int((bits != whole).sum())
         print("chunked vs whole-stream decoding: %d of %d bits differ (%.3e); whole-stream BER %.3e"
               % (d, n, d / n, float((whole != msg).mean())), flush=True)
         assert d / n < 1e-4
+        # the GPU decodes the stream whole too (one unchunked frame, the
+        # benchmark's reference for the chunked BER): identical to the oracle
+        one = np.zeros(1, mv.FRAME_DTYPE)
+        one[0] = (0, 0, n, 0, n, 0, mv.MIVIT_START_KNOWN)
+        plan = mv.Plan([CODE_K7], one, "i8", 4)
+        t = torch.from_numpy(q).to(DEV)
+        w, m, _ = plan.decode(t)
+        torch.cuda.synchronize()
+        gw = mv.unpack_bits(w.cpu().numpy()[: (n + 31) // 32], n)
+        np.testing.assert_array_equal(gw, whole)
+        assert int(m.cpu().numpy()[0]) == int(wm[0])
+        plan.close()
+        del t
 
 
 @pytest.mark.parametrize("dtype", ["i8", "f32"])
@@ -923,3 +939,79 @@ def test_autograd_survives_plan_cache_eviction():
     for f in range(F):
         np.testing.assert_array_equal(llr.grad[f].cpu().numpy(),
                                       oracle.metric_grad(code, bits[f], 1.0).astype(np.float32))
+
+
+def test_r4_mfma_varied_frames():
+    """Radix 4 with the candidate additions on the int8 matrix cores
+    (variant 3, the dragonfly-group mapping): bits, metrics and end states
+    equal the oracle on frames of 0 to 9001 stages, odd and even, known and
+    unknown starts, zero and best ends, tie-heavy and saturated soft values."""
+    rng = np.random.default_rng(4343)
+    lens = [0, 1, 2, 3, 5, 17, 63, 64, 65, 127, 128, 129, 300, 1001, 4093, 9001]
+    cases = [(S, sk, ez) for S in lens for sk in (0, 1) for ez in (0, 1) if not (ez and S < 7)]
+    fr = np.zeros(len(cases), mv.FRAME_DTYPE)
+    ofr = np.zeros(len(cases), oracle.FRAME_DTYPE)
+    off = nb = 0
+    for k, (S, sk, ez) in enumerate(cases):
+        n_out = S - 6 if ez else S
+        flags = (mv.MIVIT_START_KNOWN if sk else 0) | (mv.MIVIT_END_ZERO if ez else 0)
+        fr[k] = (off, nb, S, 0, n_out, 0, flags)
+        ofr[k] = (off, nb, S, 0, n_out, sk, 0 if ez else -1, 0)
+        off += 2 * S
+        nb += ((n_out + 31) // 32) * 32
+    llr = np.where(rng.random(off) < 0.1, rng.integers(-128, 128, off),
+                   rng.integers(-20, 21, off)).astype(np.int8)
+    llr[: off // 8] = np.where(rng.random(off // 8) < 0.5, 127, -128).astype(np.int8)
+    t = torch.from_numpy(llr).to(DEV)
+    ob, om, oend, _ = oracle.decode_frames([CODE_K7], ofr, llr, oracle.I64, nb)
+    plan = mv.Plan([CODE_K7], fr, "i8", 4, variant=3)
+    assert "matrix-core" in plan.describe()
+    w, m, e = plan.decode(t)
+    torch.cuda.synchronize()
+    bits = mv.unpack_bits(w.cpu().numpy()[: nb // 32], nb)
+    np.testing.assert_array_equal(m.cpu().numpy()[: len(fr)], om)
+    np.testing.assert_array_equal(e.cpu().numpy()[: len(fr)], oend)
+    for k in range(len(fr)):
+        s, n = int(ofr[k]["bit_offset"]), int(ofr[k]["n_out"])
+        np.testing.assert_array_equal(bits[s:s + n], ob[s:s + n])
+    # the generator order of the paper, (171, 133): other dragonfly groups
+    code = Code.from_octal(7, ["171", "133"])
+    b = make_uniform_batch(code, 9, 777, 1.0, seed=4344)
+    q = oracle.quantize_i8(b.llr, 8.0)
+    ob2, om2, _ = oracle.decode_uniform(code, q, 777, True, oracle.I64)
+    bits2, m2 = gpu_decode(q, code, 777, True, 0)
+    plan = mv.Plan([code], mv.uniform_frames(code, 9, 777, True), "i8", 4, variant=3)
+    w, m, _ = plan.decode(torch.from_numpy(q).to(DEV))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(mv.unpack_bits(w.cpu().numpy().reshape(9, -1), 777), ob2)
+    np.testing.assert_array_equal(m.cpu().numpy()[:9], om2)
+
+
+@pytest.mark.parametrize("eb", [0.0, 3.0])
+def test_r4_split_in_time_matches_oracle(eb):
+    """Packed radix-4 frame pairs split in time (later parts warm up from
+    all-zero metrics, a check compares the metrics at every boundary and
+    repairs the pairs that disagree): bits, metrics and end states equal the
+    oracle and the unsplit plan, at 0 dB (many repairs) and 3 dB; terminated
+    and free-end frames, an odd frame count and odd stage counts."""
+    from workload import int8_scale_for
+    for F, n, term in [(129, 8192, True), (64, 6001, False)]:
+        b = make_uniform_batch(CODE_K7, F, n, eb, seed=int(6100 + 10 * eb + F), terminated=term)
+        q = oracle.quantize_i8(b.llr, int8_scale_for(eb, 2))
+        ob, om, _ = oracle.decode_uniform(CODE_K7, q, n, term, oracle.I64)
+        fr = mv.uniform_frames(CODE_K7, F, n, term)
+        t = torch.from_numpy(q).to(DEV)
+        wpf = (n + 31) // 32
+        for split in (True, False):
+            print("split", eb, F, n, term, split, flush=True)
+            plan = mv.Plan([CODE_K7], fr, "i8", 4, split=split)
+            w, m, e = plan.decode(t)
+            torch.cuda.synchronize()
+            bits = mv.unpack_bits(w.cpu().numpy()[: F * wpf].reshape(F, wpf), n)
+            bad = np.flatnonzero((bits != ob).any(axis=1))
+            assert bad.size == 0, "frames %s differ" % bad[:10]
+            np.testing.assert_array_equal(m.cpu().numpy()[:F], om)
+            if split:
+                ends = e.cpu().numpy()[:F]
+            else:
+                np.testing.assert_array_equal(e.cpu().numpy()[:F], ends)
