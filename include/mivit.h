@@ -243,6 +243,26 @@ mivit_status mivit_decode_uniform(const void* llr, int32_t dtype, const mivit_co
                                   int32_t n_frames, int32_t n_info, int32_t terminated,
                                   uint32_t* bits, void* metric, void* stream);
 
+/* mivit_decode_uniform for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, layout, kernels and results, but the call's
+ * tables and survivor memory live in one fixed 64 MiB device array of the
+ * library (each GPU the library runs on holds it until the process ends),
+ * and the call allocates nothing and copies nothing from the host: it
+ * launches a table kernel, the forward and the traceback kernel.
+ *   Limit: about 256 B of tables per frame plus the survivor memory, which
+ *   for K <= 7 radix 2 is 2^(K-1)/8 B per stage (whole 32-stage blocks),
+ *   for the packed radix-4 kernel 2^(K-1)/8 B per stage and frame (whole
+ *   16-stage groups per frame pair), for K = 8, 9 2^(K-1)/8 B per stage
+ *   (whole 32-stage blocks); e.g. 1024 K=7 frames of 8192 stages fit.
+ *   A larger batch returns MIVIT_ENOMEM before any launch.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one
+ * GPU (two streams, two threads) race and must be ordered by the caller;
+ * each call writes every table and survivor word it reads. */
+mivit_status mivit_decode_uniform_noalloc(const void* llr, int32_t dtype, const mivit_code* code,
+                                          int32_t n_frames, int32_t n_info, int32_t terminated,
+                                          uint32_t* bits, void* metric, void* stream);
+
 /* Release a plan's device and host memory (waits for the device first). */
 mivit_status mivit_plan_destroy(mivit_plan* plan);
 

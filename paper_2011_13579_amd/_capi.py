@@ -19,7 +19,7 @@ EXPORTS = (
     "mivit_plan_get_info", "mivit_plan_describe", "mivit_quantize_i8", "mivit_strerror",
     "mivit_version", "mivit_pipe_create", "mivit_pipe_run", "mivit_pipe_destroy",
     "mivit_stream_create", "mivit_stream_push", "mivit_stream_finish", "mivit_stream_destroy",
-    "mivit_decode_uniform",
+    "mivit_decode_uniform", "mivit_decode_uniform_noalloc",
 )
 MIVIT_PLAN_GRAPH, MIVIT_PLAN_AUTOTUNE, MIVIT_PLAN_PERSISTENT, MIVIT_PLAN_NO_SPLIT = 1, 2, 4, 8
 
@@ -126,6 +126,9 @@ def load(path: str = LIB_PATH):
     lib.mivit_stream_destroy.argtypes = [vp]
     lib.mivit_decode_uniform.restype = ctypes.c_int
     lib.mivit_decode_uniform.argtypes = [vp, i32, ctypes.POINTER(Code), i32, i32, i32, vp, vp, vp]
+    lib.mivit_decode_uniform_noalloc.restype = ctypes.c_int
+    lib.mivit_decode_uniform_noalloc.argtypes = [vp, i32, ctypes.POINTER(Code), i32, i32, i32, vp,
+                                                 vp, vp]
     _lib = lib
     return lib
 

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmivit.so")
 SOURCES = ["mivit_kernels.hip", "mivit_fwd_rot.hip", "mivit_traceback.hip", "mivit_r4p.hip",
-           "mivit_fwd_wide.hip", "mivit_api.cpp", "mivit_pipe.cpp",
+           "mivit_fwd_wide.hip", "mivit_api.cpp", "mivit_pipe.cpp", "mivit_noalloc.hip",
            "mivit_r4_mfma.hip"]
 ARCH = os.environ.get("MIVIT_OFFLOAD_ARCH", "gfx950")
 
