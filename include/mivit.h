@@ -140,9 +140,9 @@ typedef struct {
  *                          the same path, ties included).  Uses extra device memory
  *                          for the plan's soft-value extent while creating.
  *   MIVIT_PLAN_NO_SPLIT    keep every frame of the packed radix-4 kernel in one
- *                          wavefront.  By default (K = 7), when the batch has
- *                          fewer frame pairs than about four per SIMD, each
- *                          long pair is cut into parts of whole 48-iteration
+ *                          wavefront.  By default, when the batch has fewer
+ *                          wavefront entries than about four per SIMD, each
+ *                          long entry is cut into parts of whole 48-iteration
  *                          periods decoded concurrently; a part after the
  *                          first starts 192 stages early from all-zero path
  *                          metrics (the unknown start of §III's frames) and

@@ -30,16 +30,18 @@ hipError_t launch_fwd_rot(int K, int beta, int dt, int mode, const DevCode* code
                           uint64_t* surv, void* metric, int32_t* end_out, int32_t* item_end,
                           int32_t* counter, int grid_limit, hipStream_t st);
 hipError_t launch_fwd_wide(int K, int beta, int dt, const DevCode* codes, const Item* items,
-                           int n_items, const void* llr, uint64_t* surv, void* metric,
-                           int32_t* end_out, int32_t* item_end, hipStream_t st);
+                           const SplitUnit* units, int n_units, const void* llr, uint64_t* surv,
+                           void* metric, int32_t* end_out, int32_t* item_end, WideBound* bounds,
+                           int64_t* last_m, const SplitUnit* split, int n_split, int64_t* rep_m0,
+                           SplitUnit* rep_units, int32_t* rep_count, hipStream_t st);
 hipError_t launch_tb_seg(int layout, const DevCode* codes, const Item* items, int n_items,
                          const uint64_t* surv, const int32_t* item_end, uint32_t* bits,
                          int warm, hipStream_t st);
-hipError_t launch_fwd_r4p(int K, const DevCode* codes, const Item* items, const R4Unit* units,
+hipError_t launch_fwd_r4p(int K, const DevCode* codes, const Item* items, const SplitUnit* units,
                           int n_units, const int8_t* llr, uint64_t* surv, int64_t* metric,
                           int32_t* end_out, int32_t* item_end, int32_t* counter, int grid_limit,
-                          R4Bound* bounds, int64_t* last_m, const R4Unit* split, int n_split,
-                          int64_t* rep_m0, R4Unit* rep_units, int32_t* rep_count,
+                          R4Bound* bounds, int64_t* last_m, const SplitUnit* split, int n_split,
+                          int64_t* rep_m0, SplitUnit* rep_units, int32_t* rep_count,
                           hipStream_t st);
 hipError_t launch_tb_r4p(int K, const Item* items, const int2* pairs, int n_pairs,
                          const uint64_t* surv, const int32_t* item_end, uint32_t* bits, int warm,
@@ -106,6 +108,12 @@ constexpr int kSplitWarm = 96;
 constexpr int kSplitMinIt = 384;
 constexpr int kSplitMaxParts = 8;
 constexpr int kSplitWavesPerSimd = 4;
+// Time split of the K = 8, 9 radix-2 kernel (int8): a frame longer than
+// twice the batch's stages per wavefront slot (at least kWideSplitLen) is
+// cut into parts of whole lcm(32, K-1)-stage periods, later parts warming up
+// for at least kWideSplitWarm stages.
+constexpr int kWideSplitLen = 2048;
+constexpr int kWideSplitWarm = 192;
 
 struct PlanGroup {
   int kern;   // forward kernel
@@ -137,14 +145,15 @@ struct Part {
   int n_counters = 0;
   // packed radix 4: work units (parts of entries), split entries' part-0
   // units, boundary records, last-part metrics, repair units and count
-  R4Unit* d_units = nullptr;
+  SplitUnit* d_units = nullptr;
   int n_units = 0;
-  R4Unit* d_split = nullptr;
+  SplitUnit* d_split = nullptr;
   int n_split = 0;
   R4Bound* d_bounds = nullptr;
+  WideBound* d_wbounds = nullptr;  // K = 8, 9 radix-2 kernel
   int64_t* d_last_m = nullptr;
   int64_t* d_rep_m0 = nullptr;
-  R4Unit* d_rep_units = nullptr;
+  SplitUnit* d_rep_units = nullptr;
   int32_t* d_rep_count = nullptr;
   MfmaGroups mg{};  // dragonfly groups (matrix-core radix-4 kernel)
 };
@@ -231,6 +240,7 @@ void free_part(Part& q) {
   (void)hipFree(q.d_units);
   (void)hipFree(q.d_split);
   (void)hipFree(q.d_bounds);
+  (void)hipFree(q.d_wbounds);
   (void)hipFree(q.d_last_m);
   (void)hipFree(q.d_rep_m0);
   (void)hipFree(q.d_rep_units);
@@ -357,8 +367,9 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
   // 64/2^(K-1) frames; packed radix 4: up to 2*64/2^(K-1), where the two
   // frames of a lane group must also emit the same stages)
   std::vector<int2> waves, pairs;
-  std::vector<R4Unit> units, split;
+  std::vector<SplitUnit> units, split;
   std::vector<R4Bound> bounds;
+  std::vector<WideBound> wbounds;
   int n_bounds = 0;
   std::vector<char> pair_hi(items.size(), 0);
   if (kern == kKernRot2 || kern == kKernRot4P) {
@@ -384,10 +395,10 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
       for (const int2& w : waves)
         for (int s = 0; s < w.y; s += 2) pairs.push_back(make_int2(w.x + s, std::min(2, w.y - s)));
       g.n_pairs = (int)pairs.size();
-      // work units: whole entries, or (K = 7) parts of frame pairs in time
+      // work units: whole entries, or parts of entries in time
       int parts_max = 1;
       // (persistent launches keep frame pairs whole)
-      if (ch.split && !ch.persistent && c.K == 7 && !waves.empty()) {
+      if (ch.split && !ch.persistent && !waves.empty()) {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
@@ -400,7 +411,7 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
       for (const int2& w : waves) {
         const int n_it = items[w.x].n_stages >> 1;
         const int P = std::max(1, std::min(parts_max, n_it / kSplitMinIt));
-        R4Unit u;
+        SplitUnit u;
         u.first = w.x;
         u.count = w.y;
         u.warm = 0;
@@ -427,6 +438,51 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
       }
     }
     if (ch.persistent) g.counter = q.n_counters++;
+  }
+  // K = 8, 9 radix-2 kernel: one unit per item, int8 frames much longer than
+  // the batch's stages per wavefront slot split in time
+  if (kern == kKernWide) {
+    int64_t total = 0;
+    for (const Item& it : items) total += it.n_stages;
+    int slots = 4096;
+    {
+      int dev = 0, cus = 0;
+      if (hipGetDevice(&dev) == hipSuccess &&
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+          cus > 0)
+        slots = cus * 4 * kSplitWavesPerSimd;
+    }
+    const int64_t len = std::max<int64_t>(kWideSplitLen, total / slots);
+    const int period = (c.K - 1) == 8 ? 32 : 32 * (c.K - 1);  // lcm(32, K-1) for K = 8, 9
+    const int warm = (kWideSplitWarm + period - 1) / period * period;
+    const bool can = ch.split && dtype == MIVIT_I8;
+    for (int k = 0; k < (int)items.size(); ++k) {
+      const int S = items[k].n_stages;
+      int P = can ? (int)std::min<int64_t>(kSplitMaxParts, S / (2 * len) + 1) : 1;
+      if (S < 2 * period + warm) P = 1;
+      SplitUnit u;
+      u.first = k;
+      u.count = 1;
+      u.n_parts = P;
+      u.bnd = P > 1 ? (int)wbounds.size() : -1;
+      int prev = 0;
+      for (int p = 0; p < P; ++p) {
+        const int end = p == P - 1 ? S : (int)((int64_t)S * (p + 1) / P) / period * period;
+        u.part = p;
+        u.it_begin = prev;
+        u.it_end = end;
+        u.warm = p == 0 ? 0 : std::min(warm, prev);
+        units.push_back(u);
+        if (p == 0 && P > 1) split.push_back(u);
+        if (p > 0) {
+          WideBound b;
+          std::memset(&b, 0, sizeof b);
+          b.it_at = prev;
+          wbounds.push_back(b);
+        }
+        prev = end;
+      }
+    }
   }
   // survivor memory, 16-byte aligned per item (per frame pair when packed)
   int64_t words_total = 0;
@@ -463,6 +519,7 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
   if (e == hipSuccess) e = upload(&q.d_units, units.data(), units.size());
   if (e == hipSuccess) e = upload(&q.d_split, split.data(), split.size());
   if (e == hipSuccess) e = upload(&q.d_bounds, bounds.data(), bounds.size());
+  if (e == hipSuccess) e = upload(&q.d_wbounds, wbounds.data(), wbounds.size());
   if (e == hipSuccess && q.n_split > 0) {
     e = hipMalloc((void**)&q.d_last_m, items.size() * sizeof(int64_t));
     if (e == hipSuccess) e = hipMalloc((void**)&q.d_rep_m0, items.size() * sizeof(int64_t));
@@ -495,8 +552,9 @@ hipError_t part_forward(const mivit_plan* p, const Part& q, const void* llr, voi
       e = launch_fwd_r4_mfma(q.mg, p->d_codes, q.d_items + g.first, g.count, (const int8_t*)llr,
                              q.d_surv, (int64_t*)metric, end_state, q.d_item_end, st);
     else if (g.kern == kKernWide)
-      e = launch_fwd_wide(g.K, g.beta, dt, p->d_codes, q.d_items + g.first, g.count, llr,
-                          q.d_surv, metric, end_state, q.d_item_end, st);
+      e = launch_fwd_wide(g.K, g.beta, dt, p->d_codes, q.d_items, q.d_units, q.n_units, llr,
+                          q.d_surv, metric, end_state, q.d_item_end, q.d_wbounds, q.d_last_m,
+                          q.d_split, q.n_split, q.d_rep_m0, q.d_rep_units, q.d_rep_count, st);
     else if (g.kern == kKernRot2)
       e = launch_fwd_rot(g.K, g.beta, dt, kRotMode[q.ch.variant], p->d_codes, q.d_items,
                          q.d_waves + g.wave_off, g.n_waves, llr, q.d_surv, metric, end_state,

@@ -31,9 +31,10 @@ struct Item {
   int32_t slot;       // index of this item in per-item scratch arrays
 };
 
-// One unit of work of the packed radix-4 forward kernel: the frames of one
-// wavefront-table entry (first item, count) over the iterations
-// [it_begin, it_end).  An entry decoded whole is one unit (part 0 of 1).  An
+// One unit of work of a forward kernel that splits frames in time.  For the
+// packed radix-4 kernel: the frames of one wavefront-table entry (first
+// item, count) over the iterations [it_begin, it_end); for the K = 8, 9
+// radix-2 kernel: item `first` (count 1) over the stages [it_begin, it_end).  An entry decoded whole is one unit (part 0 of 1).  An
 // entry split in time is n_parts units that run concurrently: unit p > 0
 // first runs `warm` iterations before it_begin from all-zero path metrics
 // (an unknown start, as for the windows of §III) and keeps no decisions from
@@ -41,7 +42,7 @@ struct Item {
 // the true ones by a constant, which a check after the forward pass
 // establishes; otherwise a repair unit restarts the frames at it_begin from
 // the metrics part p-1 left there.
-struct R4Unit {
+struct SplitUnit {
   int32_t first, count;
   int32_t it_begin, it_end;
   int32_t warm;
@@ -51,14 +52,28 @@ struct R4Unit {
 
 // The two sides of boundary k of a split entry (between parts k and k+1, at
 // iteration it_begin of part k+1), per lane: packed metrics (low two bits
-// cleared, after the range control of that iteration), and per frame half
-// the metric of state 0 there, each part counting from its own origin.
+// cleared, after the range control of that iteration), and per frame of the
+// entry (2 per lane group: up to 8) the metric of state 0 there, each part
+// counting from its own origin.
 struct R4Bound {
   uint32_t v_start[64];  // part k+1 after its warm-up
   uint32_t v_end[64];    // part k at its end
-  int64_t m_start[2];
-  int64_t m_end[2];
+  int64_t m_start[8];
+  int64_t m_end[8];
   int32_t it_at;         // the boundary's iteration (part k+1's it_begin)
+  int32_t pad;
+};
+
+// Boundary k of a frame split in time in the K = 8, 9 radix-2 kernel: the
+// metric of every position (2^(K-1), lane + 64 r) after the range control
+// at stage it_at, for part k at its end and part k+1 after its warm-up, and
+// each part's metric of state 0 there from its own origin.
+struct WideBound {
+  int32_t v_start[256];
+  int32_t v_end[256];
+  int64_t m_start;
+  int64_t m_end;
+  int32_t it_at;
   int32_t pad;
 };
 

@@ -228,7 +228,10 @@ constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
 
 struct Ctx {
   int64_t offset;  // integer metrics: total subtracted by renormalisation
-  int S, lane;
+  int S, lane;     // S: one past the last stage this unit runs
+  int t_store;     // first stage whose decisions are stored
+  int32_t* v_start;  // split part after the first: boundary record to fill at t_store
+  int64_t* m_start;
 };
 
 // One block of up to 32 stages starting at tb; BI its index in the period
@@ -268,6 +271,12 @@ __device__ __forceinline__ void one_block(Wave<DT, 1 << (KM1 - 6)>& W, Ctx& cx,
       for (int r = 0; r < R; ++r) W.pm[r] -= ref;
       cx.offset += ref;
     }
+    if (cx.v_start && tb == cx.t_store) {
+      // a later part of a split frame, at the end of its warm-up
+#pragma unroll
+      for (int r = 0; r < R; ++r) cx.v_start[64 * r + cx.lane] = (int32_t)W.pm[r];
+      if (cx.lane == 0) *cx.m_start = cx.offset;
+    }
   }
   wave_sync();
   constexpr int P0 = (32 * BI) % KM1;
@@ -278,7 +287,7 @@ __device__ __forceinline__ void one_block(Wave<DT, 1 << (KM1 - 6)>& W, Ctx& cx,
     for (int k = 0; k < n; ++k) stage_dyn<KM1, DT, R, NP, 0>(W, bmt + k * NP, pat, (P0 + k) % KM1);
   }
   // four groups of 8 stages: group g of the block is byte 3 - g of acc
-  {
+  if (tb >= cx.t_store) {
     constexpr int NS = 1 << KM1;
     uint8_t* dst = (uint8_t*)sv + (int64_t)(tb >> 3) * NS + cx.lane;
 #pragma unroll
@@ -286,9 +295,10 @@ __device__ __forceinline__ void one_block(Wave<DT, 1 << (KM1 - 6)>& W, Ctx& cx,
       const uint32_t a = n == 32 ? W.acc[r] : W.acc[r] << (32 - n);
 #pragma unroll
       for (int g = 0; g < 4; ++g) dst[g * NS + 64 * r] = (uint8_t)(a >> (24 - 8 * g));
-      W.acc[r] = 0;
     }
   }
+#pragma unroll
+  for (int r = 0; r < R; ++r) W.acc[r] = 0;
   wave_sync();
 }
 
@@ -312,10 +322,17 @@ constexpr int kWideWaves = 4;  // independent wavefronts (frames) per workgroup
 
 }  // namespace wide
 
-// One wavefront per item (frame or chunk window).
+// One wavefront per unit: a whole item (frame or chunk window), or, for
+// int8 soft values, one part of a frame split in time (kind 0), or a repair
+// of one (kind 1, unit count read from the device).  A part after the first
+// runs `warm` stages from all-zero metrics before it_begin and keeps no
+// decisions from them; a part before the last leaves its end metrics in a
+// boundary record, the last part its own metric, which the check completes.
 template <int KM1, int DT, int BETA>
 __global__ __launch_bounds__(64 * wide::kWideWaves) void k_fwd_wide(
-    const DevCode* __restrict__ codes, const Item* __restrict__ items, int n_items,
+    const DevCode* __restrict__ codes, const Item* __restrict__ items,
+    const SplitUnit* __restrict__ units, int n_units, const int32_t* dev_count, int kind,
+    WideBound* bounds, int64_t* last_m, const int64_t* rep_m0,
     const void* __restrict__ llr_v, uint64_t* __restrict__ surv, void* metric,
     int32_t* end_out, int32_t* item_end) {
   using namespace wide;
@@ -327,14 +344,19 @@ __global__ __launch_bounds__(64 * wide::kWideWaves) void k_fwd_wide(
   __shared__ T xpm_all[kWideWaves][NS];
   const int wid = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int item = blockIdx.x * kWideWaves + wid;
-  if (item >= n_items) return;  // no workgroup barriers: safe to leave
-  const Item it = items[item];
+  if (dev_count) n_units = min(n_units, __builtin_amdgcn_readfirstlane(*dev_count));
+  const int u = blockIdx.x * kWideWaves + wid;
+  if (u >= n_units) return;  // no workgroup barriers: safe to leave
+  const SplitUnit U = units[u];
+  const Item it = items[U.first];
   const DevCode c = codes[it.code];
   const In* llr = (const In*)llr_v + it.llr_off;
   uint64_t* sv = surv + it.surv_off;
   T* bmt = bmt_all[wid];
   T* xpm = xpm_all[wid];
+  const bool first_part = kind == 0 && U.part == 0;
+  const bool split = U.n_parts > 1;
+  const int s0 = U.it_begin - U.warm;  // a multiple of SUPER: phases start at 0
 
   // table offset (pattern) of position 64 r + lane at each phase: the even
   // previous state's branch into the state held there after the stage
@@ -355,18 +377,40 @@ __global__ __launch_bounds__(64 * wide::kWideWaves) void k_fwd_wide(
   Wave<DT, R> W;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    W.pm[r] = (it.start_known && (r != 0 || lane != 0)) ? Ty<DT>::unreachable() : (T)0;
+    if (first_part)
+      W.pm[r] = (it.start_known && (r != 0 || lane != 0)) ? Ty<DT>::unreachable() : (T)0;
+    else if (kind == 0)
+      W.pm[r] = (T)0;  // a later part: all-zero metrics (unknown start)
+    else
+      W.pm[r] = Ty<DT>::from(bounds[U.bnd + U.part - 1].v_end[64 * r + lane]);  // repair
     W.acc[r] = 0;
   }
-  Ctx cx{0, it.n_stages, lane};
+  Ctx cx{0, U.it_end, lane, U.it_begin, nullptr, nullptr};
+  if (kind == 0 && U.part > 0) {
+    cx.v_start = bounds[U.bnd + U.part - 1].v_start;
+    cx.m_start = &bounds[U.bnd + U.part - 1].m_start;
+  }
   T lv[BETA];
   {
-    const bool ok = lane < 32 && lane < cx.S;
+    const bool ok = lane < 32 && s0 + lane < cx.S;
 #pragma unroll
-    for (int b = 0; b < BETA; ++b) lv[b] = ok ? (T)llr[(int64_t)lane * BETA + b] : (T)0;
+    for (int b = 0; b < BETA; ++b) lv[b] = ok ? (T)llr[(int64_t)(s0 + lane) * BETA + b] : (T)0;
   }
-  for (int t0 = 0; t0 < cx.S; t0 += SUPER)
+  for (int t0 = s0; t0 < cx.S; t0 += SUPER)
     super_block<KM1, DT, BETA, 0, SUPER / 32>(W, cx, bmt, llr, lv, pat, sv, t0);
+
+  if constexpr (Ty<DT>::kInt) {
+    if (kind == 0 && split && U.part < U.n_parts - 1) {
+      // the end of a part before the last: range control as at a block
+      // start, then the boundary record
+      const T ref = __builtin_amdgcn_readfirstlane(W.pm[0]);
+      WideBound& B = bounds[U.bnd + U.part];
+#pragma unroll
+      for (int r = 0; r < R; ++r) B.v_end[64 * r + lane] = (int32_t)(W.pm[r] - ref);
+      if (lane == 0) B.m_end = cx.offset + ref;
+      return;
+    }
+  }
 
   // final metrics: position p holds state rotr(p, S mod (K-1)); best state
   // with ties to the lowest index
@@ -396,27 +440,97 @@ __global__ __launch_bounds__(64 * wide::kWideWaves) void k_fwd_wide(
     const int js = it.end_state >= 0 ? it.end_state : bs;
     const T vj = xpm[js];
     item_end[it.slot] = js;
-    if (it.frame >= 0) {
-      if (end_out) end_out[it.frame] = js;
-      if (metric) {
-        if constexpr (Ty<DT>::kInt)
-          ((int64_t*)metric)[it.frame] = (int64_t)vj + cx.offset;
-        else
-          ((float*)metric)[it.frame] = vj;
-      }
+    if (it.frame >= 0 && end_out) end_out[it.frame] = js;
+    if constexpr (Ty<DT>::kInt) {
+      const int64_t local = (int64_t)vj + cx.offset;
+      if (kind == 0 && split)
+        last_m[it.slot] = local;  // completed by the check
+      else if (it.frame >= 0 && metric)
+        ((int64_t*)metric)[it.frame] = local + (kind == 1 ? rep_m0[it.slot] : 0);
+    } else {
+      if (it.frame >= 0 && metric) ((float*)metric)[it.frame] = vj;
     }
   }
 }
 
+// The check after a split forward pass of the K = 8, 9 kernel, one wavefront
+// per split frame (its part-0 unit): boundary k is exact when part k's
+// range-controlled metrics at its end equal part k+1's after its warm-up at
+// every position; then the metric is the last part's plus the accumulated
+// constants, else a repair unit restarts the frame at the first inexact
+// boundary from the true metrics.
+__global__ __launch_bounds__(64 * wide::kWideWaves) void k_wide_check(
+    const DevCode* __restrict__ codes, const Item* __restrict__ items,
+    const SplitUnit* __restrict__ split, int n_split,
+    const WideBound* __restrict__ bounds, const int64_t* __restrict__ last_m, int64_t* rep_m0,
+    SplitUnit* rep_units, int32_t* rep_count, int64_t* metric) {
+  const int lane = threadIdx.x & 63;
+  const int e = blockIdx.x * wide::kWideWaves + (threadIdx.x >> 6);
+  if (e >= n_split) return;
+  const SplitUnit U = split[e];
+  const Item it = items[U.first];
+  const int NS = 1 << (codes[it.code].K - 1);  // positions compared
+  const int n_b = U.n_parts - 1;
+  int64_t T = bounds[U.bnd].m_end;  // part 0 is exact
+  int64_t D = 0;
+  int fail = -1;
+  for (int b = 0; b < n_b; ++b) {
+    const WideBound& B = bounds[U.bnd + b];
+    bool diff = false;
+    for (int p = lane; p < NS; p += 64) diff = diff || (B.v_end[p] != B.v_start[p]);
+    if (__ballot(diff) != 0) {
+      fail = b;
+      break;
+    }
+    D = T - B.m_start;
+    if (b + 1 < n_b) T = bounds[U.bnd + b + 1].m_end + D;
+  }
+  if (lane != 0) return;
+  if (fail < 0) {
+    if (metric && it.frame >= 0) metric[it.frame] = last_m[it.slot] + D;
+    return;
+  }
+  rep_m0[it.slot] = T;
+  SplitUnit R = U;
+  R.it_begin = bounds[U.bnd + fail].it_at;
+  R.it_end = it.n_stages;
+  R.warm = 0;
+  R.part = fail + 1;
+  rep_units[atomicAdd(rep_count, 1)] = R;
+}
+
+hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st);
+
 hipError_t launch_fwd_wide(int K, int beta, int dt, const DevCode* codes, const Item* items,
-                           int n_items, const void* llr, uint64_t* surv, void* metric,
-                           int32_t* end_out, int32_t* item_end, hipStream_t st) {
-  if (n_items <= 0) return hipSuccess;
-  const dim3 grid((n_items + wide::kWideWaves - 1) / wide::kWideWaves), block(64 * wide::kWideWaves);
-#define MV_WIDE(KM1, D, B)                                                                  \
-  hipLaunchKernelGGL((k_fwd_wide<KM1, D, B>), grid, block, 0, st, codes, items, n_items, llr, \
-                     surv, metric, end_out, item_end);                                        \
-  return hipGetLastError()
+                           const SplitUnit* units, int n_units, const void* llr, uint64_t* surv,
+                           void* metric, int32_t* end_out, int32_t* item_end, WideBound* bounds,
+                           int64_t* last_m, const SplitUnit* split, int n_split, int64_t* rep_m0,
+                           SplitUnit* rep_units, int32_t* rep_count, hipStream_t st) {
+  if (n_units <= 0) return hipSuccess;
+  if (n_split > 0 && dt != 1) return hipErrorInvalidValue;  // split frames: int8 only
+  const dim3 block(64 * wide::kWideWaves);
+  const dim3 grid((n_units + wide::kWideWaves - 1) / wide::kWideWaves);
+  const dim3 grid_rep((n_split + wide::kWideWaves - 1) / wide::kWideWaves);
+  hipError_t e = hipSuccess;
+#define MV_WIDE(KM1, D, B)                                                                       \
+  do {                                                                                           \
+    hipLaunchKernelGGL((k_fwd_wide<KM1, D, B>), grid, block, 0, st, codes, items, units, n_units, \
+                       (const int32_t*)nullptr, 0, bounds, last_m, (const int64_t*)nullptr, llr,  \
+                       surv, metric, end_out, item_end);                                          \
+    e = hipGetLastError();                                                                        \
+    if (e != hipSuccess || n_split <= 0) return e;                                                \
+    e = launch_zero_i32(rep_count, 1, st);                                                        \
+    if (e != hipSuccess) return e;                                                                \
+    hipLaunchKernelGGL(k_wide_check, grid_rep, block, 0, st, codes, items, split, n_split,        \
+                       (const WideBound*)bounds, (const int64_t*)last_m, rep_m0, rep_units,       \
+                       rep_count, (int64_t*)metric);                                              \
+    e = hipGetLastError();                                                                        \
+    if (e != hipSuccess) return e;                                                                \
+    hipLaunchKernelGGL((k_fwd_wide<KM1, D, B>), grid_rep, block, 0, st, codes, items,            \
+                       (const SplitUnit*)rep_units, n_split, (const int32_t*)rep_count, 1, bounds,\
+                       last_m, (const int64_t*)rep_m0, llr, surv, metric, end_out, item_end);     \
+    return hipGetLastError();                                                                     \
+  } while (0)
 #define MV_WIDE_B(KM1, D)             \
   switch (beta) {                     \
     case 2: MV_WIDE(KM1, D, 2);       \

@@ -25,16 +25,18 @@ hipError_t launch_fwd_rot(int K, int beta, int dt, int mode, const DevCode* code
                           uint64_t* surv, void* metric, int32_t* end_out, int32_t* item_end,
                           int32_t* counter, int grid_limit, hipStream_t st);
 hipError_t launch_fwd_wide(int K, int beta, int dt, const DevCode* codes, const Item* items,
-                           int n_items, const void* llr, uint64_t* surv, void* metric,
-                           int32_t* end_out, int32_t* item_end, hipStream_t st);
+                           const SplitUnit* units, int n_units, const void* llr, uint64_t* surv,
+                           void* metric, int32_t* end_out, int32_t* item_end, WideBound* bounds,
+                           int64_t* last_m, const SplitUnit* split, int n_split, int64_t* rep_m0,
+                           SplitUnit* rep_units, int32_t* rep_count, hipStream_t st);
 hipError_t launch_tb_seg(int layout, const DevCode* codes, const Item* items, int n_items,
                          const uint64_t* surv, const int32_t* item_end, uint32_t* bits,
                          int warm, hipStream_t st);
-hipError_t launch_fwd_r4p(int K, const DevCode* codes, const Item* items, const R4Unit* units,
+hipError_t launch_fwd_r4p(int K, const DevCode* codes, const Item* items, const SplitUnit* units,
                           int n_units, const int8_t* llr, uint64_t* surv, int64_t* metric,
                           int32_t* end_out, int32_t* item_end, int32_t* counter, int grid_limit,
-                          R4Bound* bounds, int64_t* last_m, const R4Unit* split, int n_split,
-                          int64_t* rep_m0, R4Unit* rep_units, int32_t* rep_count,
+                          R4Bound* bounds, int64_t* last_m, const SplitUnit* split, int n_split,
+                          int64_t* rep_m0, SplitUnit* rep_units, int32_t* rep_count,
                           hipStream_t st);
 hipError_t launch_tb_r4p(int K, const Item* items, const int2* pairs, int n_pairs,
                          const uint64_t* surv, const int32_t* item_end, uint32_t* bits, int warm,
@@ -72,15 +74,15 @@ bool make_layout(const mivit_code& c, int dtype, int F, int S, Layout& L) {
   const bool packed = dtype == MIVIT_I8 && c.beta == 2 && (c.K == 5 || c.K == 7);
   L.fam = packed ? kFamR4P : (c.K <= 7 ? kFamRot2 : kFamWide);
   L.fpw = L.fam == kFamR4P ? 2 * (64 >> (c.K - 1)) : L.fam == kFamRot2 ? (64 >> (c.K - 1)) : 1;
-  L.n_waves = L.fam == kFamWide ? 0 : (F + L.fpw - 1) / L.fpw;
+  L.n_waves = (F + L.fpw - 1) / L.fpw;  // the wide kernel: one unit per frame (fpw 1)
   L.n_pairs = L.fam == kFamR4P ? (F + 1) / 2 : 0;
   L.ws = L.fam == kFamR4P ? surv_words_r4p(c.K, S) : surv_words_blocks32(c.K, S);
   const int64_t units = L.fam == kFamR4P ? (F + 1) / 2 : F;
   size_t o = align256(sizeof(DevCode));
   L.off_items = o;
   o = align256(o + (size_t)F * sizeof(Item));
-  L.off_waves = o;  // radix 2: (first, count) per entry; radix 4: one whole-frame unit per entry
-  o = align256(o + (size_t)L.n_waves * (L.fam == kFamR4P ? sizeof(R4Unit) : sizeof(int2)));
+  L.off_waves = o;  // radix 2: (first, count) per entry; else one whole-frame unit per entry
+  o = align256(o + (size_t)L.n_waves * (L.fam == kFamRot2 ? sizeof(int2) : sizeof(SplitUnit)));
   L.off_pairs = o;
   o = align256(o + (size_t)L.n_pairs * sizeof(int2));
   L.off_end = o;
@@ -119,17 +121,17 @@ __global__ void k_uniform_tables(uint8_t* base, DevCode code, int F, int S, int 
   if (k < n_waves) {
     const int first = k * fpw;
     const int count = F - first < fpw ? F - first : fpw;
-    if (fam == kFamR4P) {
-      R4Unit u;
+    if (fam != kFamRot2) {
+      SplitUnit u;
       u.first = first;
       u.count = count;
       u.it_begin = 0;
-      u.it_end = S >> 1;
+      u.it_end = fam == kFamR4P ? S >> 1 : S;  // iterations (radix 4) or stages
       u.warm = 0;
       u.part = 0;
       u.n_parts = 1;
       u.bnd = -1;
-      ((R4Unit*)(base + off_waves))[k] = u;
+      ((SplitUnit*)(base + off_waves))[k] = u;
     } else {
       ((int2*)(base + off_waves))[k] = make_int2(first, count);
     }
@@ -205,7 +207,7 @@ extern "C" mivit_status mivit_decode_uniform_noalloc(const void* llr, int32_t dt
   int32_t* item_end = (int32_t*)(base + L.off_end);
   uint64_t* surv = (uint64_t*)(base + L.off_surv);
   if (L.fam == kFamR4P) {
-    e = launch_fwd_r4p(c.K, d_code, items, (const R4Unit*)waves, L.n_waves, (const int8_t*)llr,
+    e = launch_fwd_r4p(c.K, d_code, items, (const SplitUnit*)waves, L.n_waves, (const int8_t*)llr,
                        surv, (int64_t*)metric, nullptr, item_end, nullptr, 0, nullptr, nullptr,
                        nullptr, 0, nullptr, nullptr, nullptr, st);
     if (e == hipSuccess)
@@ -216,8 +218,9 @@ extern "C" mivit_status mivit_decode_uniform_noalloc(const void* llr, int32_t dt
     if (e == hipSuccess)
       e = launch_tb_seg(kLayoutRotR2, d_code, items, n_frames, surv, item_end, bits, kWarm, st);
   } else {
-    e = launch_fwd_wide(c.K, c.beta, dtype, d_code, items, n_frames, llr, surv, metric, nullptr,
-                        item_end, st);
+    e = launch_fwd_wide(c.K, c.beta, dtype, d_code, items, (const SplitUnit*)waves, n_frames, llr,
+                        surv, metric, nullptr, item_end, nullptr, nullptr, nullptr, 0, nullptr,
+                        nullptr, nullptr, st);
     if (e == hipSuccess)
       e = launch_tb_seg(kLayoutRotByte, d_code, items, n_frames, surv, item_end, bits, kWarm, st);
   }

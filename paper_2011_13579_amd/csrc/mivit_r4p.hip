@@ -344,7 +344,7 @@ constexpr int kR4Waves = 4;
 // its own metric, which the check completes.
 template <int ND>
 __device__ __forceinline__ void fwd_r4p_wave(const DevCode* __restrict__ codes,
-                                             const Item* __restrict__ items, const R4Unit U,
+                                             const Item* __restrict__ items, const SplitUnit U,
                                              int kind, R4Bound* bounds, int64_t* last_m,
                                              const int64_t* rep_m0,
                                              const int8_t* __restrict__ llr,
@@ -440,9 +440,9 @@ __device__ __forceinline__ void fwd_r4p_wave(const DevCode* __restrict__ codes,
     if (kind == 0 && U.part > 0 && it0 == it_b) {
       R4Bound& B = bounds[U.bnd + U.part - 1];
       B.v_start[lane] = F.V & kStrip;
-      if (lane == 0) {
-        B.m_start[0] = m0_at(it_b, 0);
-        B.m_start[1] = m0_at(it_b, 1);
+      if (r == 0) {
+        B.m_start[2 * m] = m0_at(it_b, 0);
+        B.m_start[2 * m + 1] = m0_at(it_b, 1);
       }
     }
     super_block<ND, 0, SUPER>(F, it0);
@@ -450,9 +450,9 @@ __device__ __forceinline__ void fwd_r4p_wave(const DevCode* __restrict__ codes,
   if (kind == 0 && split && U.part < U.n_parts - 1) {
     R4Bound& B = bounds[U.bnd + U.part];
     B.v_end[lane] = F.V & kStrip;
-    if (lane == 0) {
-      B.m_end[0] = m0_at(it_e, 0);
-      B.m_end[1] = m0_at(it_e, 1);
+    if (r == 0) {
+      B.m_end[2 * m] = m0_at(it_e, 0);
+      B.m_end[2 * m + 1] = m0_at(it_e, 1);
     }
     return;
   }
@@ -685,7 +685,7 @@ __global__ __launch_bounds__(64) void k_tb_r4p(const Item* __restrict__ items,
 template <int ND>
 __global__ __launch_bounds__(64 * r4p::kR4Waves) void k_fwd_r4p(
     const DevCode* __restrict__ codes, const Item* __restrict__ items,
-    const R4Unit* __restrict__ units, int n_units, const int32_t* dev_count, int kind,
+    const SplitUnit* __restrict__ units, int n_units, const int32_t* dev_count, int kind,
     R4Bound* bounds, int64_t* last_m, const int64_t* rep_m0, const int8_t* __restrict__ llr,
     uint64_t* __restrict__ surv, int64_t* metric, int32_t* end_out, int32_t* item_end,
     int32_t* counter) {
@@ -719,55 +719,52 @@ __global__ __launch_bounds__(64 * r4p::kR4Waves) void k_fwd_r4p(
 // accumulated constants.  Else the entry gets a repair unit from its first
 // inexact boundary, with the true metric of state 0 there.
 __global__ __launch_bounds__(64 * r4p::kR4Waves) void k_r4p_check(
-    const Item* __restrict__ items, const R4Unit* __restrict__ split, int n_split,
+    const Item* __restrict__ items, const SplitUnit* __restrict__ split, int n_split,
     const R4Bound* __restrict__ bounds, const int64_t* __restrict__ last_m, int64_t* rep_m0,
-    R4Unit* rep_units, int32_t* rep_count, int64_t* metric) {
+    SplitUnit* rep_units, int32_t* rep_count, int64_t* metric) {
   const int lane = threadIdx.x & 63;
   const int e = blockIdx.x * r4p::kR4Waves + (threadIdx.x >> 6);
   if (e >= n_split) return;
-  const R4Unit U = split[e];
+  const SplitUnit U = split[e];
   const int n_b = U.n_parts - 1;
-  int64_t T0 = bounds[U.bnd].m_end[0], T1 = bounds[U.bnd].m_end[1];  // part 0 is exact
-  int64_t D0 = 0, D1 = 0;
+  // lane k < U.count follows frame k of the entry: T = true metric of state
+  // 0 at the current boundary, D = the constant its part adds
+  const bool mine = lane < U.count;
+  const int k = mine ? lane : 0;
+  int64_t T = bounds[U.bnd].m_end[k];  // part 0 is exact
+  int64_t D = 0;
   int fail = -1;
-  for (int k = 0; k < n_b; ++k) {
-    const R4Bound& B = bounds[U.bnd + k];
+  for (int b = 0; b < n_b; ++b) {
+    const R4Bound& B = bounds[U.bnd + b];
     if (__ballot(B.v_end[lane] != B.v_start[lane]) != 0) {
-      fail = k;
+      fail = b;
       break;
     }
-    D0 = T0 - B.m_start[0];
-    D1 = T1 - B.m_start[1];
-    if (k + 1 < n_b) {
-      T0 = bounds[U.bnd + k + 1].m_end[0] + D0;
-      T1 = bounds[U.bnd + k + 1].m_end[1] + D1;
-    }
+    D = T - B.m_start[k];
+    if (b + 1 < n_b) T = bounds[U.bnd + b + 1].m_end[k] + D;
   }
-  if (lane != 0) return;
-  const Item ia = items[U.first];
+  if (!mine) return;
+  const Item it = items[U.first + k];
   if (fail < 0) {
-    if (metric && ia.frame >= 0) metric[ia.frame] = last_m[ia.slot] + D0;
-    if (U.count > 1) {
-      const Item ib = items[U.first + 1];
-      if (metric && ib.frame >= 0) metric[ib.frame] = last_m[ib.slot] + D1;
-    }
+    if (metric && it.frame >= 0) metric[it.frame] = last_m[it.slot] + D;
     return;
   }
-  R4Unit R = U;
-  R.it_begin = (int)bounds[U.bnd + fail].it_at;
-  R.it_end = ia.n_stages >> 1;
-  R.warm = 0;
-  R.part = fail + 1;
-  rep_m0[ia.slot] = T0;
-  if (U.count > 1) rep_m0[items[U.first + 1].slot] = T1;
-  rep_units[atomicAdd(rep_count, 1)] = R;
+  rep_m0[it.slot] = T;
+  if (lane == 0) {
+    SplitUnit R = U;
+    R.it_begin = (int)bounds[U.bnd + fail].it_at;
+    R.it_end = it.n_stages >> 1;
+    R.warm = 0;
+    R.part = fail + 1;
+    rep_units[atomicAdd(rep_count, 1)] = R;
+  }
 }
 
-hipError_t launch_fwd_r4p(int K, const DevCode* codes, const Item* items, const R4Unit* units,
+hipError_t launch_fwd_r4p(int K, const DevCode* codes, const Item* items, const SplitUnit* units,
                           int n_units, const int8_t* llr, uint64_t* surv, int64_t* metric,
                           int32_t* end_out, int32_t* item_end, int32_t* counter, int grid_limit,
-                          R4Bound* bounds, int64_t* last_m, const R4Unit* split, int n_split,
-                          int64_t* rep_m0, R4Unit* rep_units, int32_t* rep_count,
+                          R4Bound* bounds, int64_t* last_m, const SplitUnit* split, int n_split,
+                          int64_t* rep_m0, SplitUnit* rep_units, int32_t* rep_count,
                           hipStream_t st) {
   if (n_units <= 0) return hipSuccess;
   if (K != 5 && K != 7) return hipErrorInvalidValue;
@@ -793,7 +790,7 @@ hipError_t launch_fwd_r4p(int K, const DevCode* codes, const Item* items, const 
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kernel, dim3(ns), dim3(threads), 0, st, codes, items,
-                     (const R4Unit*)rep_units, n_split, (const int32_t*)rep_count, 1, bounds,
+                     (const SplitUnit*)rep_units, n_split, (const int32_t*)rep_count, 1, bounds,
                      last_m, (const int64_t*)rep_m0, llr, surv, metric, end_out, item_end,
                      (int32_t*)nullptr);
   return hipGetLastError();

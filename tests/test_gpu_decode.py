@@ -987,8 +987,9 @@ def test_r4_mfma_varied_frames():
     np.testing.assert_array_equal(m.cpu().numpy()[:9], om2)
 
 
+@pytest.mark.parametrize("code", [CODE_K7, CODE_K5], ids=cid)
 @pytest.mark.parametrize("eb", [0.0, 3.0])
-def test_r4_split_in_time_matches_oracle(eb):
+def test_r4_split_in_time_matches_oracle(eb, code):
     """Packed radix-4 frame pairs split in time (later parts warm up from
     all-zero metrics, a check compares the metrics at every boundary and
     repairs the pairs that disagree): bits, metrics and end states equal the
@@ -996,15 +997,15 @@ def test_r4_split_in_time_matches_oracle(eb):
     and free-end frames, an odd frame count and odd stage counts."""
     from workload import int8_scale_for
     for F, n, term in [(129, 8192, True), (64, 6001, False)]:
-        b = make_uniform_batch(CODE_K7, F, n, eb, seed=int(6100 + 10 * eb + F), terminated=term)
+        b = make_uniform_batch(code, F, n, eb, seed=int(6100 + 10 * eb + F + code.K), terminated=term)
         q = oracle.quantize_i8(b.llr, int8_scale_for(eb, 2))
-        ob, om, _ = oracle.decode_uniform(CODE_K7, q, n, term, oracle.I64)
-        fr = mv.uniform_frames(CODE_K7, F, n, term)
+        ob, om, _ = oracle.decode_uniform(code, q, n, term, oracle.I64)
+        fr = mv.uniform_frames(code, F, n, term)
         t = torch.from_numpy(q).to(DEV)
         wpf = (n + 31) // 32
         for split in (True, False):
-            print("split", eb, F, n, term, split, flush=True)
-            plan = mv.Plan([CODE_K7], fr, "i8", 4, split=split)
+            print("split", cid(code), eb, F, n, term, split, flush=True)
+            plan = mv.Plan([code], fr, "i8", 4, split=split)
             w, m, e = plan.decode(t)
             torch.cuda.synchronize()
             bits = mv.unpack_bits(w.cpu().numpy()[: F * wpf].reshape(F, wpf), n)
@@ -1015,3 +1016,47 @@ def test_r4_split_in_time_matches_oracle(eb):
                 ends = e.cpu().numpy()[:F]
             else:
                 np.testing.assert_array_equal(e.cpu().numpy()[:F], ends)
+
+
+@pytest.mark.parametrize("code", [CODE_K9, Code.from_octal(8, ["247", "371"])], ids=cid)
+@pytest.mark.parametrize("eb", [0.0, 2.0])
+def test_wide_split_in_time_matches_oracle(code, eb):
+    """int8 K = 8, 9 frames much longer than the rest of the batch are split
+    in time by the radix-2 register kernel (later parts warm up from all-zero
+    metrics, a check compares the range-controlled metrics at every boundary
+    and repairs the frames that disagree): bits, metrics and end states equal
+    the oracle, terminated, free-end and unknown-start frames, at 0 dB (many
+    repairs) and 2 dB; the unsplit plan agrees."""
+    from workload import int8_scale_for
+    rng = np.random.default_rng(int(9100 + code.K + 10 * eb))
+    beta = code.beta
+    lens = [30011, 17000, 9000, 300, 64, 5]
+    fr = np.zeros(len(lens), mv.FRAME_DTYPE)
+    ofr = np.zeros(len(lens), oracle.FRAME_DTYPE)
+    parts, off, nb = [], 0, 0
+    for k, n in enumerate(lens):
+        sk, ez = k % 3 != 2, k % 2 == 0
+        S = n + (code.K - 1 if ez else 0)
+        b = make_uniform_batch(code, 1, n, eb, seed=int(rng.integers(1 << 30)), terminated=ez)
+        q = oracle.quantize_i8(b.llr[0], int8_scale_for(eb, beta))
+        parts.append(q)
+        flags = (mv.MIVIT_START_KNOWN if sk else 0) | (mv.MIVIT_END_ZERO if ez else 0)
+        fr[k] = (off, nb, S, 0, n, 0, flags)
+        ofr[k] = (off, nb, S, 0, n, int(sk), 0 if ez else -1, 0)
+        off += S * beta
+        nb += ((n + 31) // 32) * 32
+    llr = np.concatenate(parts)
+    ob, om, oend, _ = oracle.decode_frames([code], ofr, llr, oracle.I64, nb)
+    t = torch.from_numpy(llr).to(DEV)
+    for split in (True, False):
+        print("wide split", cid(code), eb, split, flush=True)
+        plan = mv.Plan([code], fr, "i8", 2, split=split)
+        w, m, e = plan.decode(t)
+        torch.cuda.synchronize()
+        bits = mv.unpack_bits(w.cpu().numpy()[: nb // 32], nb)
+        np.testing.assert_array_equal(m.cpu().numpy()[: len(lens)], om)
+        np.testing.assert_array_equal(e.cpu().numpy()[: len(lens)], oend)
+        for k in range(len(lens)):
+            a, n = int(ofr[k]["bit_offset"]), int(ofr[k]["n_out"])
+            np.testing.assert_array_equal(bits[a:a + n], ob[a:a + n])
+        plan.close()
