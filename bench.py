@@ -41,7 +41,7 @@ VALU16_PEAK_TOPS = 2 * VALU32_PEAK_TOPS           # packed 16-bit: 78.64 T ops/s
 COPY_BYTES = 512 << 20
 # forward kernels whose HBM traffic was counted: profile summary and sources
 TRAFFIC_PROFILES = {
-    "i8r4": ("fwd_r4p_k7_4096x8192_traffic.md", ["mivit_r4p.hip", "mivit_device.h"]),
+    "i8r4": ("fwd_r4q_k7_4096x8192_traffic.md", ["mivit_r4p.hip", "mivit_device.h"]),
     "f32r2": ("fwd_rot_k7_4096x8192_traffic.md", ["mivit_fwd_rot.hip", "mivit_device.h"]),
 }
 # data width of the add-compare-select of each variant's forward kernel
@@ -412,7 +412,9 @@ def main():
         ms, fwd, tb, bits, _ = time_variant(torch, mv, plans[v], llr, args.steps, args.warmup)
         dec = mv.unpack_bits(bits.cpu().numpy()[: N_FRAMES * (N_INFO // 32)].reshape(N_FRAMES, -1), N_INFO)
         decoded[v] = dec
-        peak = VALU16_PEAK_TOPS if base in PACKED16 and kv in ("", "nosplit") else VALU32_PEAK_TOPS
+        # the packed kernels (variant 0, 4) run 16-bit metrics; the others 32-bit
+        peak = (VALU16_PEAK_TOPS if base in PACKED16 and kv in ("", "nosplit", "v4")
+                else VALU32_PEAK_TOPS)
         results[v] = {
             "gbit_s": round(N_FRAMES * N_INFO / (ms * 1e-3) / 1e9, 3),
             "ms_per_step": round(ms, 4), "forward_ms": round(fwd, 4), "traceback_ms": round(tb, 4),

@@ -101,7 +101,8 @@ typedef struct {
                        radix 2 with K = 8 or 9: one frame per wavefront with
                        2^(K-1)/64 states per lane in registers; radix 4
                        with K = 5 or 7, beta = 2: two frames per register
-                       in packed 16-bit metrics); 1 and 2: radix-2 forward
+                       in packed 16-bit metrics, K = 7 with four states per
+                       lane and eight frames per wavefront); 1 and 2: radix-2 forward
                        exchanging through LDS swizzles (1: both
                        previous-state metrics fetched, 2: one partner metric
                        per lane; K = 8, 9: metrics exchanged through LDS
@@ -111,7 +112,10 @@ typedef struct {
                        16 x 16 x 32 MFMA per iteration holding all sixteen
                        dragonflies through the dragonfly groups of
                        §VIII-D-2 (int8, K = 7, beta = 2 codes with at most
-                       four groups, radix 4 only; else MIVIT_EUNSUPPORTED) */
+                       four groups, radix 4 only; else MIVIT_EUNSUPPORTED);
+                       4: radix 4 packed with one state per lane and two
+                       frames per wavefront (int8, K = 5 or 7, beta = 2,
+                       radix 4 only; else MIVIT_EUNSUPPORTED) */
   uint32_t flags;   /* MIVIT_PLAN_* scheduling options, below */
   int32_t reserved[2]; /* must be zero */
 } mivit_opts;

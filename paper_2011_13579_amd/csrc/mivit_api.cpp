@@ -43,6 +43,12 @@ hipError_t launch_fwd_r4p(int K, const DevCode* codes, const Item* items, const 
                           R4Bound* bounds, int64_t* last_m, const SplitUnit* split, int n_split,
                           int64_t* rep_m0, SplitUnit* rep_units, int32_t* rep_count,
                           hipStream_t st);
+hipError_t launch_fwd_r4q(const DevCode* codes, const Item* items, const SplitUnit* units,
+                          int n_units, const int8_t* llr, uint64_t* surv, int64_t* metric,
+                          int32_t* end_out, int32_t* item_end, int32_t* counter, int grid_limit,
+                          R4Bound* bounds, int64_t* last_m, const SplitUnit* split, int n_split,
+                          int64_t* rep_m0, SplitUnit* rep_units, int32_t* rep_count,
+                          hipStream_t st);
 hipError_t launch_tb_r4p(int K, const Item* items, const int2* pairs, int n_pairs,
                          const uint64_t* surv, const int32_t* item_end, uint32_t* bits, int warm,
                          hipStream_t st);
@@ -64,6 +70,7 @@ enum : int {
   kKernWide = 4,
   kKernGeneric8 = 5,
   kKernMfma4 = 6,  // radix 4, candidate additions on the int8 matrix cores
+  kKernRot4Q = 7,  // packed radix 4 with four states per lane (K = 7)
 };
 enum : int {
   kLayoutNatR2 = 0,
@@ -108,6 +115,9 @@ constexpr int kSplitWarm = 96;
 constexpr int kSplitMinIt = 384;
 constexpr int kSplitMaxParts = 8;
 constexpr int kSplitWavesPerSimd = 4;
+// The four-states-per-lane kernel holds eight frames per wavefront and four
+// independent chains per lane: it targets fewer wavefronts per SIMD.
+constexpr int kSplitWavesPerSimdQ = 2;
 // Time split of the K = 8, 9 radix-2 kernel (int8): a frame longer than
 // twice the batch's stages per wavefront slot (at least kWideSplitLen) is
 // cut into parts of whole lcm(32, K-1)-stage periods, later parts warming up
@@ -219,6 +229,7 @@ mivit_status check_code(const mivit_code& c) {
 int nsl_of(int K) { return K <= 7 ? 1 : (1 << (K - 1)) / 64; }
 
 bool packed_ok(const mivit_code& c) { return c.beta == 2 && (c.K == 5 || c.K == 7); }
+bool quad_ok(const mivit_code& c) { return c.beta == 2 && c.K == 7; }
 
 // The matrix-core radix-4 kernel: K = 7, rate 1/2, at most four dragonfly groups.
 bool mfma_ok(const mivit_code& c) {
@@ -334,8 +345,12 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
     kern = kKernGeneric8;
   else if (ch.radix == 4 && ch.variant == 3)
     kern = kKernMfma4;
+  else if (ch.radix == 4 && ch.variant == 4)
+    kern = kKernRot4P;  // packed, one state per lane (the K = 5 default)
+  else if (ch.radix == 4 && ch.variant == 0 && packed_ok(c) && i8)
+    kern = quad_ok(c) ? kKernRot4Q : kKernRot4P;
   else if (ch.radix == 4)
-    kern = (ch.variant == 0 && packed_ok(c) && i8) ? kKernRot4P : kKernGeneric4;
+    kern = kKernGeneric4;
   else
     kern = c.K <= 7 ? kKernRot2 : (ch.variant == 0 ? kKernWide : kKernGeneric2);
   // longest first; items that can share a packed lane group next to each other
@@ -347,7 +362,7 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
   PlanGroup g;
   g.kern = kern;
   g.layout = kern == kKernRot2      ? kLayoutRotR2
-             : kern == kKernRot4P   ? kLayoutRot4P
+             : (kern == kKernRot4P || kern == kKernRot4Q) ? kLayoutRot4P
              : kern == kKernWide    ? kLayoutRotByte
              : (kern == kKernGeneric4 || kern == kKernMfma4) ? kLayoutNatR4
              : kern == kKernGeneric8 ? kLayoutNatR8
@@ -372,9 +387,9 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
   std::vector<WideBound> wbounds;
   int n_bounds = 0;
   std::vector<char> pair_hi(items.size(), 0);
-  if (kern == kKernRot2 || kern == kKernRot4P) {
-    const bool packed = kern == kKernRot4P;
-    const int fpw = (packed ? 2 : 1) * (64 >> (c.K - 1));
+  if (kern == kKernRot2 || kern == kKernRot4P || kern == kKernRot4Q) {
+    const bool packed = kern != kKernRot2;
+    const int fpw = kern == kKernRot4Q ? 8 : (packed ? 2 : 1) * (64 >> (c.K - 1));
     for (int k = 0; k < (int)items.size(); ++k) {
       if (!waves.empty()) {
         int2& w = waves.back();
@@ -403,7 +418,8 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
             cus > 0) {
-          const int64_t target = (int64_t)cus * 4 * kSplitWavesPerSimd;
+          const int64_t target =
+              (int64_t)cus * 4 * (kern == kKernRot4Q ? kSplitWavesPerSimdQ : kSplitWavesPerSimd);
           parts_max = (int)std::min<int64_t>(kSplitMaxParts,
                                              (target + (int64_t)waves.size() - 1) / (int64_t)waves.size());
         }
@@ -417,9 +433,18 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
         u.warm = 0;
         u.n_parts = P;
         u.bnd = P > 1 ? n_bounds : -1;
+        // part 0 has no warm-up: it takes kSplitWarm more iterations than
+        // the others, so every part runs about T iterations in all
+        const int64_t T = ((int64_t)n_it + (int64_t)(P - 1) * kSplitWarm) / P;
         int prev = 0;
         for (int k = 0; k < P; ++k) {
-          const int end = k == P - 1 ? n_it : (int)((int64_t)n_it * (k + 1) / P) / kSplitAlign * kSplitAlign;
+          int end = n_it;
+          if (k < P - 1) {
+            const int64_t x = T + (int64_t)k * (T - kSplitWarm);  // nearest period boundary
+            end = (int)((x + kSplitAlign / 2) / kSplitAlign * kSplitAlign);
+            end = std::max(end, prev + kSplitAlign);
+            end = std::min(end, n_it - kSplitAlign * (P - 1 - k));
+          }
           u.part = k;
           u.it_begin = prev;
           u.it_end = end;
@@ -488,14 +513,14 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
   int64_t words_total = 0;
   for (size_t k = 0; k < items.size(); ++k) {
     Item& it = items[k];
-    if (kern == kKernRot4P && pair_hi[k]) {
+    if ((kern == kKernRot4P || kern == kKernRot4Q) && pair_hi[k]) {
       it.surv_off = items[k - 1].surv_off;
       continue;
     }
     it.surv_off = words_total;
     if (kern == kKernRot2 || kern == kKernWide)
       words_total += surv_words_blocks32(c.K, it.n_stages);
-    else if (kern == kKernRot4P)
+    else if (kern == kKernRot4P || kern == kKernRot4Q)
       words_total += surv_words_r4p(c.K, it.n_stages);
     else
       words_total += surv_words_natural(c.K, it.n_stages);
@@ -548,6 +573,11 @@ hipError_t part_forward(const mivit_plan* p, const Part& q, const void* llr, voi
                          q.d_surv, (int64_t*)metric, end_state, q.d_item_end, counter, 0,
                          q.d_bounds, q.d_last_m, q.d_split, q.n_split, q.d_rep_m0,
                          q.d_rep_units, q.d_rep_count, st);
+    else if (g.kern == kKernRot4Q)
+      e = launch_fwd_r4q(p->d_codes, q.d_items, q.d_units, q.n_units, (const int8_t*)llr,
+                         q.d_surv, (int64_t*)metric, end_state, q.d_item_end, counter, 0,
+                         q.d_bounds, q.d_last_m, q.d_split, q.n_split, q.d_rep_m0,
+                         q.d_rep_units, q.d_rep_count, st);
     else if (g.kern == kKernMfma4)
       e = launch_fwd_r4_mfma(q.mg, p->d_codes, q.d_items + g.first, g.count, (const int8_t*)llr,
                              q.d_surv, (int64_t*)metric, end_state, q.d_item_end, st);
@@ -572,7 +602,7 @@ hipError_t part_forward(const mivit_plan* p, const Part& q, const void* llr, voi
 hipError_t part_traceback(const mivit_plan* p, const Part& q, uint32_t* bits, hipStream_t st) {
   for (const PlanGroup& g : q.groups) {
     hipError_t e =
-        g.kern == kKernRot4P
+        g.layout == kLayoutRot4P
             ? launch_tb_r4p(g.K, q.d_items, q.d_pairs + g.pair_off, g.n_pairs, q.d_surv,
                             q.d_item_end, bits, kWarmStagesR4P, st)
             : launch_tb_seg(g.layout, p->d_codes, q.d_items + g.first, g.count, q.d_surv,
@@ -643,6 +673,7 @@ std::vector<Choice> candidates(const mivit_code& c, int dtype, int radix) {
     }
     add(4, 1, false);
     if (mfma_ok(c)) add(4, 3, false);
+    if (quad_ok(c)) add(4, 4, false);  // one state per lane (variant 0 holds four)
   }
   if (i8 && (radix == 0 || radix == 8) && c.K >= 4) add(8, 0, false);
   return out;
@@ -676,6 +707,7 @@ const char* kern_name(int kern) {
     case kKernRot2: return "radix-2 rotating";
     case kKernWide: return "radix-2 rotating, states in registers";
     case kKernRot4P: return "radix-4 packed two-frame";
+    case kKernRot4Q: return "radix-4 packed, four states per lane";
     case kKernGeneric8: return "radix-8 generic";
     case kKernMfma4: return "radix-4 matrix-core candidate additions";
   }
@@ -714,8 +746,8 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
   if (o.radix != 0 && o.radix != 2 && o.radix != 4 && o.radix != 8) return MIVIT_EINVAL;
   if ((o.radix == 4 || o.radix == 8) && o.dtype != MIVIT_I8) return MIVIT_EINVAL;
   if (o.chunk < 0 || o.overlap < 0 || (o.chunk > 0 && o.chunk % 32 != 0)) return MIVIT_EINVAL;
-  if (o.variant < 0 || o.variant > 3) return MIVIT_EINVAL;
-  if (o.variant == 3 && (o.radix != 4 || o.dtype != MIVIT_I8)) return MIVIT_EUNSUPPORTED;
+  if (o.variant < 0 || o.variant > 4) return MIVIT_EINVAL;
+  if (o.variant >= 3 && (o.radix != 4 || o.dtype != MIVIT_I8)) return MIVIT_EUNSUPPORTED;
   if (o.flags & ~(MIVIT_PLAN_GRAPH | MIVIT_PLAN_AUTOTUNE | MIVIT_PLAN_PERSISTENT |
                   MIVIT_PLAN_NO_SPLIT))
     return MIVIT_EINVAL;
@@ -728,6 +760,9 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
   if (o.variant == 3)
     for (int c = 0; c < n_codes; ++c)
       if (!mfma_ok(codes[c])) return MIVIT_EUNSUPPORTED;
+  if (o.variant == 4)
+    for (int c = 0; c < n_codes; ++c)
+      if (!packed_ok(codes[c])) return MIVIT_EUNSUPPORTED;
   if (o.radix == 8) {  // one kernel, and at least 8 states
     if (o.variant != 0) return MIVIT_EUNSUPPORTED;
     for (int c = 0; c < n_codes; ++c)
@@ -1001,7 +1036,7 @@ mivit_status mivit_plan_describe(const mivit_plan* p, char* buf, int32_t len) {
     char line[256];
     for (const PlanGroup& g : q.groups) {
       // the rotating kernels run a wave table; the others one wavefront per item
-      const bool table = g.kern == kKernRot2 || g.kern == kKernRot4P;
+      const bool table = g.kern == kKernRot2 || g.kern == kKernRot4P || g.kern == kKernRot4Q;
       std::snprintf(line, sizeof line,
                     "%scode %d: K=%d beta=%d, %s forward, variant %d, %s, %d items, %d wavefronts",
                     s.empty() ? "" : "; ", q.code, g.K, g.beta, kern_name(g.kern), q.ch.variant,

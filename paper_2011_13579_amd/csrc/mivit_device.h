@@ -51,13 +51,14 @@ struct SplitUnit {
 };
 
 // The two sides of boundary k of a split entry (between parts k and k+1, at
-// iteration it_begin of part k+1), per lane: packed metrics (low two bits
-// cleared, after the range control of that iteration), and per frame of the
-// entry (2 per lane group: up to 8) the metric of state 0 there, each part
+// iteration it_begin of part k+1), per lane (and register, for the kernel
+// with four states per lane: 256 words, else the first 64): packed metrics
+// (low two bits cleared, after the range control of that iteration), and
+// per frame of the entry (up to 8) the metric of state 0 there, each part
 // counting from its own origin.
 struct R4Bound {
-  uint32_t v_start[64];  // part k+1 after its warm-up
-  uint32_t v_end[64];    // part k at its end
+  uint32_t v_start[256];  // part k+1 after its warm-up
+  uint32_t v_end[256];    // part k at its end
   int64_t m_start[8];
   int64_t m_end[8];
   int32_t it_at;         // the boundary's iteration (part k+1's it_begin)

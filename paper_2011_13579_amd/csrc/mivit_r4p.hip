@@ -721,7 +721,7 @@ __global__ __launch_bounds__(64 * r4p::kR4Waves) void k_fwd_r4p(
 __global__ __launch_bounds__(64 * r4p::kR4Waves) void k_r4p_check(
     const Item* __restrict__ items, const SplitUnit* __restrict__ split, int n_split,
     const R4Bound* __restrict__ bounds, const int64_t* __restrict__ last_m, int64_t* rep_m0,
-    SplitUnit* rep_units, int32_t* rep_count, int64_t* metric) {
+    SplitUnit* rep_units, int32_t* rep_count, int64_t* metric, int nv) {
   const int lane = threadIdx.x & 63;
   const int e = blockIdx.x * r4p::kR4Waves + (threadIdx.x >> 6);
   if (e >= n_split) return;
@@ -736,7 +736,9 @@ __global__ __launch_bounds__(64 * r4p::kR4Waves) void k_r4p_check(
   int fail = -1;
   for (int b = 0; b < n_b; ++b) {
     const R4Bound& B = bounds[U.bnd + b];
-    if (__ballot(B.v_end[lane] != B.v_start[lane]) != 0) {
+    bool diff = false;
+    for (int x = lane; x < nv; x += 64) diff = diff || B.v_end[x] != B.v_start[x];
+    if (__ballot(diff) != 0) {
       fail = b;
       break;
     }
@@ -757,6 +759,496 @@ __global__ __launch_bounds__(64 * r4p::kR4Waves) void k_r4p_check(
     R.warm = 0;
     R.part = fail + 1;
     rep_units[atomicAdd(rep_count, 1)] = R;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Packed radix 4 with four states per lane (K = 7).
+//
+// The same trellis, digit map, packed tagged metrics, tables and survivor
+// words as above, laid out differently: a frame pair occupies one row of 16
+// lanes (up to four pairs, eight frames, per wavefront) and lane-digit slot
+// 2 becomes the register index, so position p = l + 16 q holds, in register
+// q of lane l of the pair's row, what lane p holds in the one-state kernel.
+// Phases 0 and 1 are the DPP exchanges above applied to each register; the
+// dragonfly groups of phase 2 differ only in the register index, so that
+// phase is evaluated inside every lane with no exchange (the 4 x 4 transpose
+// of the one-state kernel, four permlane swaps, disappears), and the four
+// registers are independent dependency chains.
+//
+// Scheduling.  Every lane fills one table row of its pair per 16-iteration
+// block; three blocks of tables rotate in LDS, so a block's table is written
+// one block before it is read, and rows are padded (20 words) and pairs
+// offset (16 banks) so neither the 16-byte table stores nor the lookups
+// conflict on LDS banks.  Each iteration loads the table entries of the next
+// one (the last iteration of a block those of the next block's first), and
+// a block is branch-free: pairs beyond the entry's frame count repeat pair 0
+// exactly (they store the same words to the same places), and the warm-up
+// iterations of a split unit, whose decisions are not kept, run a copy of
+// the loop without stores.
+//
+// Table addresses.  The output pattern of a two-stage branch is linear over
+// GF(2) in the left state and the two inputs (the code is a convolution), so
+// a lane's 48 candidate patterns are the XOR of a part that depends on its
+// lane, one that depends on the register only and one of the inputs.
+//
+// The survivor word of position p is word G*64 + p as above, so the same
+// traceback reads it.
+// ---------------------------------------------------------------------------
+namespace r4q {
+
+using namespace r4p;
+
+constexpr int kRow = 20;                   // words per table row (16 used)
+constexpr int kPairTbl = 16 * kRow + 16;   // words per pair table: pairs 16 banks apart
+constexpr int kBufWords = 4 * kPairTbl;    // one block's tables of a wavefront
+constexpr int kWaves = 2;                  // wavefronts per workgroup
+
+// +-4 sign row of output pattern p (bit b set: soft value b enters negated)
+__host__ __device__ constexpr int32_t sign_row(int p) {
+  return (int32_t)(((p & 1) ? 0xFCu : 0x04u) | (((p & 2) ? 0xFCu : 0x04u) << 8) |
+                   (((p & 4) ? 0xFCu : 0x04u) << 16) | (((p & 8) ? 0xFCu : 0x04u) << 24));
+}
+
+// Output pattern (4 bits: stage 2t's two output bits, then stage 2t+1's) of
+// the two-stage branch from left state i on inputs u (u & 1 first), K = 7.
+__device__ __forceinline__ int pattern(const DevCode& c, int i, int u) {
+  const int mid = ((u & 1) << 5) | (i >> 1);
+  return branch_out2(c, i, u & 1) | (branch_out2(c, mid, u >> 1) << 2);
+}
+
+struct Fq {
+  const uint32_t* tp[3][4][4];  // table entry (buffer 0, row 0) of candidate k of register q at phase ph
+  uint32_t tag0, tag1;          // tie tags entering phases 0 and 1
+  uint32_t tag2[4];             // entering phase 2: 3 - q (held in registers, so the
+                                // retag is one v_and_or with the strip mask)
+  int32_t sg[8];                // sign rows of patterns 0..7 (scalar registers)
+  uint32_t bias;                // 2048 in both halves
+  uint32_t* trow;               // this lane's row in its pair table (buffer 0)
+  const int8_t* l0;             // soft values of iteration 0, frames A / B of the pair
+  const int8_t* l1;
+  uint32_t w0, w1;              // soft values of this lane's row, block after the current one
+  uint32_t V[4];                // packed metrics of positions l + 16 q, tagged
+  uint32_t cur[16];             // table entries of the next iteration
+  uint32_t acc[4], vs[4];       // decisions of the current group; last even iteration's max
+  uint32_t* sv;                 // survivor words of the pair, plus the lane's position l
+  int n_it;
+  uint64_t off0, off1;          // accumulated renormalisation amounts of the pair
+};
+
+// Orders this wavefront's table stores before its later table loads (and
+// its earlier loads before the stores), without waiting for either.
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Table of one block (buffer nb) from this lane's soft values: its row.
+// Pattern p ^ 15 negates every soft value of pattern p, so its entry is
+// 2 * 2048 - (entry of p) in each half.
+__device__ __forceinline__ void q_table(Fq& F, int nb) {
+  uint4* dst = (uint4*)(F.trow + nb * kBufWords);
+  uint32_t t[16];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    // frame A's entry + 2048 in the low half, frame B's + 2048 in the high
+    // (the second product accumulates into the shifted first, in place)
+    const uint32_t b = (uint32_t)__builtin_amdgcn_sdot4((int)F.w1, F.sg[p], 0, false);
+    t[p] = (uint32_t)__builtin_amdgcn_sdot4((int)F.w0, F.sg[p], (int)((b << 16) + F.bias), false);
+    t[p ^ 15] = (uint32_t)(2 * kBias) * 0x10001u - t[p];
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) dst[e] = make_uint4(t[4 * e], t[4 * e + 1], t[4 * e + 2], t[4 * e + 3]);
+}
+
+// Soft values of iteration itn (0 past the unit's last iteration); n_it >= 1.
+__device__ __forceinline__ void q_load(Fq& F, int itn) {
+  const int64_t x = 4 * (int64_t)min(itn, F.n_it - 1);
+  const uint32_t a = load_llr4(F.l0 + x), b = load_llr4(F.l1 + x);
+  const bool ok = itn < F.n_it;
+  F.w0 = ok ? a : 0u;
+  F.w1 = ok ? b : 0u;
+}
+
+// Table entries of an iteration at phase PH, word offset o (buffer, row).
+template <int PH>
+__device__ __forceinline__ void q_fetch(const Fq& F, int o, uint32_t (&t)[16]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t[4 * q + k] = F.tp[PH][q][k][o];
+}
+
+// One iteration at phase PH with table entries t; v receives the max
+// results (tags = decisions) of the four registers.
+template <int PH>
+__device__ __forceinline__ void q_step(Fq& F, const uint32_t (&t)[16], uint32_t (&v)[4]) {
+  if constexpr (PH == 2) {
+    // the right state of register u takes the best of the left states in
+    // registers y = 0..3 of the same lane (entry 4u + y)
+    uint32_t c[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) c[u][y] = F.V[y] + t[4 * u + y];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = pk_max(pk_max(c[u][0], c[u][1]), pk_max(c[u][2], c[u][3]));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) F.V[q] = (v[q] & kStrip) | F.tag0;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint32_t x[4];
+      fetch4<PH>(F.V[q], x);
+      const uint32_t c0 = x[0] + t[4 * q];
+      const uint32_t c1 = x[1] + t[4 * q + 1];
+      const uint32_t c2 = x[2] + t[4 * q + 2];
+      const uint32_t c3 = x[3] + t[4 * q + 3];
+      v[q] = pk_max(pk_max(c0, c1), pk_max(c2, c3));
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) F.V[q] = (v[q] & kStrip) | (PH == 0 ? F.tag1 : F.tag2[q]);
+  }
+}
+
+// Decisions of iteration K8 (static) of a group, per register.
+template <int K8>
+__device__ __forceinline__ void q_collect(Fq& F, const uint32_t (&v)[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if constexpr ((K8 & 1) == 0) {
+      F.vs[q] = v[q];
+    } else {
+      const uint32_t t = __builtin_amdgcn_perm(v[q], F.vs[q], 0x06040200u) & kTagBytes;
+      F.acc[q] = K8 == 1 ? t : (F.acc[q] | (t << (K8 - 1)));
+    }
+  }
+}
+
+__device__ __forceinline__ void q_renorm(Fq& F) {
+  // bring state 0 (register 0 of the row's lane 0) back to kBase
+  const uint32_t ref = (uint32_t)__builtin_amdgcn_mov_dpp((int)F.V[0], 0x150, 0xF, 0xF, false);
+  const uint32_t d = (ref & kStrip) - kBase2;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) F.V[q] -= d;
+  F.off0 += d & 0xFFFFu;
+  F.off1 += d >> 16;
+}
+
+// End of a whole group of 8 iterations ending at iteration `last`.
+template <bool STORE>
+__device__ __forceinline__ void q_group_end(Fq& F, int last) {
+  if constexpr (STORE) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) F.sv[(last >> 3) * 64 + 16 * q] = F.acc[q];
+  }
+  q_renorm(F);
+}
+
+template <int P0, int Q, bool STORE>
+__device__ __forceinline__ void q_iterate_full(Fq& F, int it0, int ob, int ob_next) {
+  if constexpr (Q < 16) {
+    uint32_t t[16], v[4];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t[e] = F.cur[e];
+    if constexpr (Q < 15)
+      q_fetch<(P0 + Q + 1) % 3>(F, ob + (Q + 1) * kRow, F.cur);
+    else
+      q_fetch<(P0 + 1) % 3>(F, ob_next, F.cur);  // the next block's first row
+    q_step<(P0 + Q) % 3>(F, t, v);
+    q_collect<Q & 7>(F, v);
+    if constexpr ((Q & 7) == 7) q_group_end<STORE>(F, it0 + Q);
+    // keep each iteration's loads one iteration ahead of their use
+    __builtin_amdgcn_sched_barrier(0);
+    q_iterate_full<P0, Q + 1, STORE>(F, it0, ob, ob_next);
+  }
+}
+
+// Block B (0, 1, 2) of a 48-iteration period from it0: its table is buffer
+// B (and its first row's entries are in F.cur); it writes buffer B+1 for the
+// next block and loads the soft values of the block after that.
+template <int B, bool STORE>
+__device__ __forceinline__ void q_block(Fq& F, int it0) {
+  constexpr int P0 = (16 * B) % 3;
+  q_table(F, (B + 1) % 3);
+  q_load(F, it0 + 32 + (int)(threadIdx.x & 15));
+  wave_fence();
+  const int n = min(16, F.n_it - it0);
+  if (n == 16) {
+    q_iterate_full<P0, 0, STORE>(F, it0, B * kBufWords, ((B + 1) % 3) * kBufWords);
+  } else {
+    // the unit's last, partial block (stores: the warm-up is whole periods);
+    // the static groups leave their decisions in acc
+#pragma unroll
+    for (int r = 0; r < 4; ++r) F.acc[r] = 0;
+#pragma unroll 1
+    for (int q = 0; q < n; ++q) {
+      uint32_t t[16], v[4];
+      const int o = B * kBufWords + q * kRow;
+      const int ph = (P0 + q) % 3;
+      if (ph == 0) {
+        q_fetch<0>(F, o, t);
+        q_step<0>(F, t, v);
+      } else if (ph == 1) {
+        q_fetch<1>(F, o, t);
+        q_step<1>(F, t, v);
+      } else {
+        q_fetch<2>(F, o, t);
+        q_step<2>(F, t, v);
+      }
+      const uint32_t sel = (q & 1) ? 0x02000C0Cu : 0x0C0C0200u;  // 0x0C: a zero byte
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        F.acc[r] |= (__builtin_amdgcn_perm(v[r], v[r], sel) & kTagBytes) << (2 * ((q & 7) >> 1));
+      if ((q & 7) == 7 || q == n - 1) {
+        const int last = it0 + q;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) F.sv[(last >> 3) * 64 + 16 * r] = F.acc[r];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) F.acc[r] = 0;
+        if ((q & 7) == 7) q_renorm(F);
+      }
+    }
+  }
+}
+
+template <int B, bool STORE>
+__device__ __forceinline__ void q_period(Fq& F, int it0) {
+  if constexpr (B < 3) {
+    const int itb = it0 + 16 * B;
+    if (itb < F.n_it) {
+      q_block<B, STORE>(F, itb);
+      q_period<B + 1, STORE>(F, it0);
+    }
+  }
+}
+
+}  // namespace r4q
+
+// One wavefront decodes up to 8 frames of equal length: the row of lanes
+// 16m .. 16m+15 holds frames 2m (low halves) and 2m+1 (high).  Units, split
+// boundaries and repairs as in fwd_r4p_wave; boundary records hold position
+// p = l + 16 q of pair m at index 64 q + 16 m + l.
+__device__ __forceinline__ void fwd_r4q_wave(const DevCode* __restrict__ codes,
+                                             const Item* __restrict__ items, const SplitUnit U,
+                                             int kind, R4Bound* bounds, int64_t* last_m,
+                                             const int64_t* rep_m0,
+                                             const int8_t* __restrict__ llr,
+                                             uint64_t* __restrict__ surv, int64_t* metric,
+                                             int32_t* end_out, int32_t* item_end,
+                                             uint32_t* tbl, int lane) {
+  using namespace r4q;
+  constexpr int KM1 = 6;
+  const int m = lane >> 4, l = lane & 15;
+  const bool va = 2 * m < U.count, vb = 2 * m + 1 < U.count;
+  // a pair beyond the frame count repeats pair 0 (same inputs, same stores)
+  const int ia = U.first + (va ? 2 * m : 0);
+  const int ib_ = va ? (vb ? ia + 1 : ia) : U.first + (U.count > 1 ? 1 : 0);
+  const Item ita = items[ia], itb = items[ib_];
+  const DevCode c = codes[__builtin_amdgcn_readfirstlane(ita.code)];  // one code per part
+  const int S = __builtin_amdgcn_readfirstlane(ita.n_stages);  // equal within the wave
+  const int lead = S & 1;
+  const int it_b = U.it_begin, it_e = U.it_end, s0 = U.it_begin - U.warm;
+  const bool first_part = kind == 0 && U.part == 0;
+  const bool split = U.n_parts > 1;
+
+  Fq F;
+  F.trow = tbl + m * kPairTbl + l * kRow;
+  F.n_it = it_e;
+  F.sv = (uint32_t*)(surv + ita.surv_off) + l;
+  F.l0 = llr + ita.llr_off + 2 * lead;
+  F.l1 = llr + itb.llr_off + 2 * lead;
+  F.off0 = F.off1 = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) F.acc[q] = F.vs[q] = 0;
+  // table entries of every candidate (the digit map of lane_consts):
+  // pattern(i, u) = pattern(i_lane, 0) ^ pattern(i_reg, 0) ^ pattern(0, u)
+  {
+    const uint32_t* pt = tbl + m * kPairTbl;
+#pragma unroll
+    for (int ph = 0; ph < 2; ++ph) {
+      uint32_t src[4];
+      if (ph == 0)
+        fetch4<0>((uint32_t)lane, src);
+      else
+        fetch4<1>((uint32_t)lane, src);
+      // the right state's new digit u sits in slot ph of the lane: l's digit ph
+      const int zu = pattern(c, 0, (l >> (2 * ph)) & 3);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int xk = pattern(c, rotr_n((int)(src[k] & 15), 2 * ph, KM1), 0) ^ zu;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          F.tp[ph][q][k] = pt + (xk ^ pattern(c, rotr_n(16 * q, 2 * ph, KM1), 0));
+      }
+    }
+    // phase 2: right state l + 16 u from the left states of registers y
+    const int d = pattern(c, rotr_n(l, 4, KM1), 0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+        F.tp[2][u][y] = pt + (d ^ pattern(c, rotr_n(16 * y, 4, KM1), u));
+  }
+  F.tag0 = (uint32_t)(3 - (l & 3)) * 0x10001u;
+  F.tag1 = (uint32_t)(3 - ((l >> 2) & 3)) * 0x10001u;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    // a register copy the compiler does not fold back into two literals
+    asm volatile("v_mov_b32 %0, %1" : "=v"(F.tag2[q]) : "n"((3 - q) * 0x10001));
+  }
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    // in scalar registers (not literals), so the products can read them directly
+    asm volatile("s_mov_b32 %0, %1" : "=s"(F.sg[p]) : "n"(sign_row(p)));
+  }
+  F.bias = (uint32_t)((kBias << 16) | kBias);
+
+  // metrics entering iteration s0 (a multiple of 3: position p holds state p)
+  if (first_part) {
+    const Item* its[2] = {&ita, &itb};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = l + 16 * q;
+      uint32_t v[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const bool known = its[h]->start_known != 0;
+        if (lead) {
+          const int8_t* p = llr + its[h]->llr_off;
+          const int i0 = (j << 1) & 63;
+          const int w = branch_out2(c, i0, j >> (KM1 - 1));
+          const int bm = ((w & 1) ? -(int)p[0] : (int)p[0]) + ((w & 2) ? -(int)p[1] : (int)p[1]);
+          int pm;
+          bool reach = true;
+          if (known) {
+            reach = i0 == 0;
+            pm = bm;
+          } else {
+            pm = bm < 0 ? -bm : bm;
+          }
+          v[h] = reach ? kBase + 4u * (uint32_t)(pm + kLeadOff) : 0u;
+        } else {
+          v[h] = (!known || j == 0) ? kBase : 0u;
+        }
+      }
+      F.V[q] = v[0] | (v[1] << 16) | F.tag0;
+    }
+  } else if (kind == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) F.V[q] = kBase2 | F.tag0;  // later part: unknown start
+  } else {
+    const R4Bound& B = bounds[U.bnd + U.part - 1];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) F.V[q] = (B.v_end[64 * q + lane] & kStrip) | F.tag0;  // repair
+  }
+  auto m0_at = [&](int x, int h) -> int64_t {
+    const int64_t o = (int64_t)(h ? F.off1 : F.off0);
+    return o / 4 - (int64_t)(kBias / 4) * (x - s0) - (first_part ? (int64_t)kLeadOff * lead : 0);
+  };
+  if (it_e > s0) {
+    // tables of the first block, its first row, soft values of the second
+    q_load(F, s0 + l);
+    q_table(F, 0);
+    q_load(F, s0 + 16 + l);
+    wave_fence();
+    q_fetch<0>(F, 0, F.cur);
+    int it0 = s0;
+    for (; it0 < it_b; it0 += 48) q_period<0, false>(F, it0);  // warm-up: no stores
+    if (kind == 0 && U.part > 0) {
+      R4Bound& B = bounds[U.bnd + U.part - 1];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) B.v_start[64 * q + lane] = F.V[q] & kStrip;
+      if (l == 0) {
+        B.m_start[2 * m] = m0_at(it_b, 0);
+        B.m_start[2 * m + 1] = m0_at(it_b, 1);
+      }
+    }
+    for (; it0 < it_e; it0 += 48) q_period<0, true>(F, it0);
+  }
+  if (kind == 0 && split && U.part < U.n_parts - 1) {
+    R4Bound& B = bounds[U.bnd + U.part];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) B.v_end[64 * q + lane] = F.V[q] & kStrip;
+    if (l == 0) {
+      B.m_end[2 * m] = m0_at(it_e, 0);
+      B.m_end[2 * m + 1] = m0_at(it_e, 1);
+    }
+    return;
+  }
+
+  // final metrics: position p holds state rotr(p, 2 (it_e mod 3))
+  const int rot = (2 * (it_e % 3)) % KM1;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const Item& it = h ? itb : ita;
+    const bool valid = h ? vb : va;
+    uint32_t val[4];
+    uint32_t key = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      val[q] = ((F.V[q] & kStrip) >> (16 * h)) & 0xFFFFu;
+      const int js_q = rotr_n(l + 16 * q, rot, KM1);
+      const uint32_t kq = (val[q] << 8) | (uint32_t)(255 - js_q);
+      key = kq > key ? kq : key;
+    }
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      const uint32_t other = (uint32_t)__shfl_xor((int)key, o);
+      key = other > key ? other : key;
+    }
+    const bool fixed = it.end_state >= 0;
+    const int js = fixed ? it.end_state : 255 - (int)(key & 255);
+    const int pos = rotl_n(js & 63, rot, KM1);
+    const int src = 16 * m + (pos & 15);
+    uint32_t vfix = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t x = (uint32_t)__shfl((int)val[q], src);
+      vfix = (pos >> 4) == q ? x : vfix;
+    }
+    const uint32_t vbest = fixed ? vfix : key >> 8;
+    if (l == 0 && valid) {
+      item_end[it.slot] = js;
+      const int64_t o = (int64_t)(h ? F.off1 : F.off0);
+      const int64_t local = ((int64_t)vbest - (int64_t)kBase + o) / 4 -
+                            (int64_t)(kBias / 4) * (it_e - s0) -
+                            (first_part ? (int64_t)kLeadOff * lead : 0);
+      if (kind == 0 && split) {
+        last_m[it.slot] = local;  // completed by the check
+        if (it.frame >= 0 && end_out) end_out[it.frame] = js;
+      } else if (it.frame >= 0) {
+        if (end_out) end_out[it.frame] = js;
+        if (metric) metric[it.frame] = local + (kind == 1 ? rep_m0[it.slot] : 0);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(64 * r4q::kWaves, 2) void k_fwd_r4q(
+    const DevCode* __restrict__ codes, const Item* __restrict__ items,
+    const SplitUnit* __restrict__ units, int n_units, const int32_t* dev_count, int kind,
+    R4Bound* bounds, int64_t* last_m, const int64_t* rep_m0, const int8_t* __restrict__ llr,
+    uint64_t* __restrict__ surv, int64_t* metric, int32_t* end_out, int32_t* item_end,
+    int32_t* counter) {
+  __shared__ __align__(16) uint32_t tbl_all[r4q::kWaves][3 * r4q::kBufWords];
+  const int wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  if (dev_count) n_units = min(n_units, __builtin_amdgcn_readfirstlane(*dev_count));
+  if (counter == nullptr) {
+    const int u = blockIdx.x * r4q::kWaves + wid;
+    if (u >= n_units) return;  // no workgroup barriers: safe to leave
+    fwd_r4q_wave(codes, items, units[u], kind, bounds, last_m, rep_m0, llr, surv, metric,
+                 end_out, item_end, tbl_all[wid], lane);
+    return;
+  }
+  for (;;) {
+    int w = 0;
+    if (lane == 0) w = atomicAdd(counter, 1);
+    w = __builtin_amdgcn_readfirstlane(w);
+    if (w >= n_units) break;
+    fwd_r4q_wave(codes, items, units[w], kind, bounds, last_m, rep_m0, llr, surv, metric,
+                 end_out, item_end, tbl_all[wid], lane);
   }
 }
 
@@ -786,10 +1278,44 @@ hipError_t launch_fwd_r4p(int K, const DevCode* codes, const Item* items, const 
   const int ns = (n_split + r4p::kR4Waves - 1) / r4p::kR4Waves;
   hipLaunchKernelGGL(k_r4p_check, dim3(ns), dim3(threads), 0, st, items, split, n_split,
                      (const R4Bound*)bounds, (const int64_t*)last_m, rep_m0, rep_units, rep_count,
-                     metric);
+                     metric, 64);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kernel, dim3(ns), dim3(threads), 0, st, codes, items,
+                     (const SplitUnit*)rep_units, n_split, (const int32_t*)rep_count, 1, bounds,
+                     last_m, (const int64_t*)rep_m0, llr, surv, metric, end_out, item_end,
+                     (int32_t*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd_r4q(const DevCode* codes, const Item* items, const SplitUnit* units,
+                          int n_units, const int8_t* llr, uint64_t* surv, int64_t* metric,
+                          int32_t* end_out, int32_t* item_end, int32_t* counter, int grid_limit,
+                          R4Bound* bounds, int64_t* last_m, const SplitUnit* split, int n_split,
+                          int64_t* rep_m0, SplitUnit* rep_units, int32_t* rep_count,
+                          hipStream_t st) {
+  if (n_units <= 0) return hipSuccess;
+  const int threads = 64 * r4q::kWaves;
+  int nb = (n_units + r4q::kWaves - 1) / r4q::kWaves;
+  if (counter) {
+    const int lim = grid_limit > 0 ? grid_limit : resident_workgroups(k_fwd_r4q, threads);
+    if (lim > 0 && nb > lim) nb = lim;
+  }
+  hipLaunchKernelGGL(k_fwd_r4q, dim3(nb), dim3(threads), 0, st, codes, items, units, n_units,
+                     (const int32_t*)nullptr, 0, bounds, last_m, (const int64_t*)nullptr, llr,
+                     surv, metric, end_out, item_end, counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || n_split <= 0) return e;
+  e = launch_zero_i32(rep_count, 1, st);
+  if (e != hipSuccess) return e;
+  const int ns = (n_split + r4p::kR4Waves - 1) / r4p::kR4Waves;
+  hipLaunchKernelGGL(k_r4p_check, dim3(ns), dim3(64 * r4p::kR4Waves), 0, st, items, split,
+                     n_split, (const R4Bound*)bounds, (const int64_t*)last_m, rep_m0, rep_units,
+                     rep_count, metric, 256);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nr = (n_split + r4q::kWaves - 1) / r4q::kWaves;
+  hipLaunchKernelGGL(k_fwd_r4q, dim3(nr), dim3(threads), 0, st, codes, items,
                      (const SplitUnit*)rep_units, n_split, (const int32_t*)rep_count, 1, bounds,
                      last_m, (const int64_t*)rep_m0, llr, surv, metric, end_out, item_end,
                      (int32_t*)nullptr);

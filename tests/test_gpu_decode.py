@@ -347,7 +347,7 @@ def test_full_batch_4096x8192(dtype, eb, seed):
     if dtype == "i8":
         llr = oracle.quantize_i8(b.llr, int8_scale_for(eb, 2))
         ob, om, _ = oracle.decode_uniform(CODE_K7, llr, n, True, oracle.I64)
-        runs = [(2, False), (4, False), (2, True), (4, True), (4, "mfma")]
+        runs = [(2, False), (4, False), (2, True), (4, True), (4, "mfma"), (4, "one-state")]
     else:
         llr = b.llr
         ob, om, _ = oracle.decode_uniform(CODE_K7, llr, n, True, oracle.F32)
@@ -360,6 +360,8 @@ def test_full_batch_4096x8192(dtype, eb, seed):
         print("full", dtype, eb, radix, pers, flush=True)
         if pers == "mfma":  # candidate additions on the matrix cores
             plan = mv.Plan([CODE_K7], fr, dtype, radix, variant=3)
+        elif pers == "one-state":  # packed, one state per lane
+            plan = mv.Plan([CODE_K7], fr, dtype, radix, variant=4)
         else:
             plan = mv.Plan([CODE_K7], fr, dtype, radix, persistent=pers)
         w, m, _ = plan.decode(t)
@@ -625,13 +627,13 @@ def test_mixed_10000_frames_autotuned_graph(dtype):
 
 
 def test_r4_packed_varied_frames():
-    """Packed K=7 radix-4 plans (direct and persistent launches) give the
-    oracle's bits, metrics and end states on frames of 1 to 9001 stages, odd
-    and even, known and unknown starts, zero and best ends, in wavefront
-    entries holding one or both frames of a pair."""
+    """Packed K=7 radix-4 plans (one and four states per lane; direct and
+    persistent launches) give the oracle's bits, metrics and end states on
+    frames of 1 to 9001 stages, odd and even, known and unknown starts, zero
+    and best ends, in wavefront entries holding one to eight frames."""
     rng = np.random.default_rng(4242)
     lens = [0, 1, 2, 3, 5, 17, 64, 65, 127, 300, 1001, 4093, 9001]
-    for copies in (1, 3):
+    for copies in (1, 3, 5):
         cases = [(S, sk, ez) for S in lens for sk in (0, 1) for ez in (0, 1)
                  if not (ez and S < 7)]
         cases = [cs for cs in cases for _ in range(copies)]
@@ -649,9 +651,9 @@ def test_r4_packed_varied_frames():
                        rng.integers(-20, 21, off)).astype(np.int8)
         t = torch.from_numpy(llr).to(DEV)
         ob, om, oend, _ = oracle.decode_frames([CODE_K7], ofr, llr, oracle.I64, nb)
-        for pers in (False, True):
-            print("varied", copies, pers, flush=True)
-            plan = mv.Plan([CODE_K7], fr, "i8", 4, persistent=pers)
+        for variant, pers in ((0, False), (0, True), (4, False), (4, True)):
+            print("varied", copies, variant, pers, flush=True)
+            plan = mv.Plan([CODE_K7], fr, "i8", 4, variant=variant, persistent=pers)
             assert "packed" in plan.describe()
             w, m, e = plan.decode(t)
             torch.cuda.synchronize()
@@ -987,9 +989,10 @@ def test_r4_mfma_varied_frames():
     np.testing.assert_array_equal(m.cpu().numpy()[:9], om2)
 
 
-@pytest.mark.parametrize("code", [CODE_K7, CODE_K5], ids=cid)
+@pytest.mark.parametrize("code,variant", [(CODE_K7, 0), (CODE_K7, 4), (CODE_K5, 0)],
+                         ids=["K7", "K7-one-state", "K5"])
 @pytest.mark.parametrize("eb", [0.0, 3.0])
-def test_r4_split_in_time_matches_oracle(eb, code):
+def test_r4_split_in_time_matches_oracle(eb, code, variant):
     """Packed radix-4 frame pairs split in time (later parts warm up from
     all-zero metrics, a check compares the metrics at every boundary and
     repairs the pairs that disagree): bits, metrics and end states equal the
@@ -1004,8 +1007,8 @@ def test_r4_split_in_time_matches_oracle(eb, code):
         t = torch.from_numpy(q).to(DEV)
         wpf = (n + 31) // 32
         for split in (True, False):
-            print("split", cid(code), eb, F, n, term, split, flush=True)
-            plan = mv.Plan([code], fr, "i8", 4, split=split)
+            print("split", cid(code), variant, eb, F, n, term, split, flush=True)
+            plan = mv.Plan([code], fr, "i8", 4, variant=variant, split=split)
             w, m, e = plan.decode(t)
             torch.cuda.synchronize()
             bits = mv.unpack_bits(w.cpu().numpy()[: F * wpf].reshape(F, wpf), n)
