@@ -831,6 +831,7 @@ struct Fq {
   uint32_t V[4];                // packed metrics of positions l + 16 q, tagged
   uint32_t cur[16];             // table entries of the next iteration
   uint32_t acc[4], vs[4];       // decisions of the current group; last even iteration's max
+  uint32_t hi[4];               // decisions of iterations 4..5 of the group
   uint32_t* sv;                 // survivor words of the pair, plus the lane's position l
   int n_it;
   uint64_t off0, off1;          // accumulated renormalisation amounts of the pair
@@ -919,8 +920,12 @@ __device__ __forceinline__ void q_collect(Fq& F, const uint32_t (&v)[4]) {
     if constexpr ((K8 & 1) == 0) {
       F.vs[q] = v[q];
     } else {
+      // pairs of iterations combined as a tree: one shift-or each
       const uint32_t t = __builtin_amdgcn_perm(v[q], F.vs[q], 0x06040200u) & kTagBytes;
-      F.acc[q] = K8 == 1 ? t : (F.acc[q] | (t << (K8 - 1)));
+      if constexpr (K8 == 1) F.acc[q] = t;
+      if constexpr (K8 == 3) F.acc[q] |= t << 2;
+      if constexpr (K8 == 5) F.hi[q] = t;
+      if constexpr (K8 == 7) F.acc[q] |= (F.hi[q] | (t << 2)) << 4;
     }
   }
 }
