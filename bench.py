@@ -226,7 +226,7 @@ def pcie_pipeline(torch, mv, plan, llr_dev, n_batches=8, depth=3):
     for b in range(n_batches):
         h_llr[b * pipe.llr_elems:(b + 1) * pipe.llr_elems].copy_(one)
     h_bits = torch.empty(n_batches * pipe.bit_words, dtype=torch.int32).pin_memory()
-    pipe.run(h_llr, h_bits, None, 2)
+    pipe.run(h_llr, h_bits, None, n_batches)  # first touch of every host page
     t0 = time.perf_counter()
     pipe.run(h_llr, h_bits, None, n_batches)
     dt = time.perf_counter() - t0
@@ -412,8 +412,8 @@ def main():
         ms, fwd, tb, bits, _ = time_variant(torch, mv, plans[v], llr, args.steps, args.warmup)
         dec = mv.unpack_bits(bits.cpu().numpy()[: N_FRAMES * (N_INFO // 32)].reshape(N_FRAMES, -1), N_INFO)
         decoded[v] = dec
-        # the packed kernels (variant 0, 4) run 16-bit metrics; the others 32-bit
-        peak = (VALU16_PEAK_TOPS if base in PACKED16 and kv in ("", "nosplit", "v4")
+        # the packed kernels (variants 0, 4, 5) run 16-bit metrics; the others 32-bit
+        peak = (VALU16_PEAK_TOPS if base in PACKED16 and kv in ("", "nosplit", "v4", "v5")
                 else VALU32_PEAK_TOPS)
         results[v] = {
             "gbit_s": round(N_FRAMES * N_INFO / (ms * 1e-3) / 1e9, 3),

@@ -101,8 +101,10 @@ typedef struct {
                        radix 2 with K = 8 or 9: one frame per wavefront with
                        2^(K-1)/64 states per lane in registers; radix 4
                        with K = 5 or 7, beta = 2: two frames per register
-                       in packed 16-bit metrics, K = 7 with four states per
-                       lane and eight frames per wavefront); 1 and 2: radix-2 forward
+                       in packed 16-bit metrics; K = 7 batches that fill
+                       the device with groups of eight equal-length frames
+                       run four states per lane, eight frames per
+                       wavefront); 1 and 2: radix-2 forward
                        exchanging through LDS swizzles (1: both
                        previous-state metrics fetched, 2: one partner metric
                        per lane; K = 8, 9: metrics exchanged through LDS
@@ -115,7 +117,10 @@ typedef struct {
                        four groups, radix 4 only; else MIVIT_EUNSUPPORTED);
                        4: radix 4 packed with one state per lane and two
                        frames per wavefront (int8, K = 5 or 7, beta = 2,
-                       radix 4 only; else MIVIT_EUNSUPPORTED) */
+                       radix 4 only; else MIVIT_EUNSUPPORTED); 5: radix 4
+                       packed with four states per lane for any batch (int8,
+                       K = 7, beta = 2, radix 4 only; else
+                       MIVIT_EUNSUPPORTED) */
   uint32_t flags;   /* MIVIT_PLAN_* scheduling options, below */
   int32_t reserved[2]; /* must be zero */
 } mivit_opts;

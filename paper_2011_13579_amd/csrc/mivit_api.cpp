@@ -9,6 +9,7 @@
 #include <climits>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -328,6 +329,29 @@ void expand_items(const mivit_code* codes, const mivit_frame* frames, const std:
   }
 }
 
+// The four-state radix-4 kernel holds eight frames of one length per
+// wavefront and, with its longer iterations, needs about two wavefronts per
+// SIMD (after the time split) to hide latency; batches that fill fewer
+// (few frames, or frames of many different lengths) run the one-state
+// kernel faster.
+bool quad_pays(const std::vector<Item>& items) {
+  if (items.empty()) return false;
+  std::map<int, int64_t> by_len;  // stages -> frames
+  for (const Item& it : items) by_len[it.n_stages]++;
+  int64_t entries = 0, waves = 0;
+  for (const auto& kv : by_len) {
+    const int64_t e = (kv.second + 7) / 8;
+    entries += e;
+    waves += e * std::max(1, std::min(kSplitMaxParts, (kv.first >> 1) / kSplitMinIt));
+  }
+  if (24 * entries > 4 * (int64_t)items.size()) return false;  // entries under 3/4 full
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return false;
+  return waves >= 2 * 4 * (int64_t)cus;
+}
+
 // Build one part: kernel per item, groups, wave and pair tables, survivor
 // memory, device copies.
 mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
@@ -347,8 +371,10 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
     kern = kKernMfma4;
   else if (ch.radix == 4 && ch.variant == 4)
     kern = kKernRot4P;  // packed, one state per lane (the K = 5 default)
+  else if (ch.radix == 4 && ch.variant == 5)
+    kern = kKernRot4Q;  // packed, four states per lane, whatever the batch
   else if (ch.radix == 4 && ch.variant == 0 && packed_ok(c) && i8)
-    kern = quad_ok(c) ? kKernRot4Q : kKernRot4P;
+    kern = quad_ok(c) && quad_pays(items) ? kKernRot4Q : kKernRot4P;
   else if (ch.radix == 4)
     kern = kKernGeneric4;
   else
@@ -673,7 +699,10 @@ std::vector<Choice> candidates(const mivit_code& c, int dtype, int radix) {
     }
     add(4, 1, false);
     if (mfma_ok(c)) add(4, 3, false);
-    if (quad_ok(c)) add(4, 4, false);  // one state per lane (variant 0 holds four)
+    if (quad_ok(c)) {
+      add(4, 4, false);  // one state per lane
+      add(4, 5, false);  // four states per lane
+    }
   }
   if (i8 && (radix == 0 || radix == 8) && c.K >= 4) add(8, 0, false);
   return out;
@@ -746,7 +775,7 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
   if (o.radix != 0 && o.radix != 2 && o.radix != 4 && o.radix != 8) return MIVIT_EINVAL;
   if ((o.radix == 4 || o.radix == 8) && o.dtype != MIVIT_I8) return MIVIT_EINVAL;
   if (o.chunk < 0 || o.overlap < 0 || (o.chunk > 0 && o.chunk % 32 != 0)) return MIVIT_EINVAL;
-  if (o.variant < 0 || o.variant > 4) return MIVIT_EINVAL;
+  if (o.variant < 0 || o.variant > 5) return MIVIT_EINVAL;
   if (o.variant >= 3 && (o.radix != 4 || o.dtype != MIVIT_I8)) return MIVIT_EUNSUPPORTED;
   if (o.flags & ~(MIVIT_PLAN_GRAPH | MIVIT_PLAN_AUTOTUNE | MIVIT_PLAN_PERSISTENT |
                   MIVIT_PLAN_NO_SPLIT))
@@ -763,6 +792,9 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
   if (o.variant == 4)
     for (int c = 0; c < n_codes; ++c)
       if (!packed_ok(codes[c])) return MIVIT_EUNSUPPORTED;
+  if (o.variant == 5)
+    for (int c = 0; c < n_codes; ++c)
+      if (!quad_ok(codes[c])) return MIVIT_EUNSUPPORTED;
   if (o.radix == 8) {  // one kernel, and at least 8 states
     if (o.variant != 0) return MIVIT_EUNSUPPORTED;
     for (int c = 0; c < n_codes; ++c)

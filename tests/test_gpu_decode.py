@@ -347,7 +347,8 @@ def test_full_batch_4096x8192(dtype, eb, seed):
     if dtype == "i8":
         llr = oracle.quantize_i8(b.llr, int8_scale_for(eb, 2))
         ob, om, _ = oracle.decode_uniform(CODE_K7, llr, n, True, oracle.I64)
-        runs = [(2, False), (4, False), (2, True), (4, True), (4, "mfma"), (4, "one-state")]
+        runs = [(2, False), (4, False), (2, True), (4, True), (4, "mfma"), (4, "one-state"),
+                (4, "four-state")]
     else:
         llr = b.llr
         ob, om, _ = oracle.decode_uniform(CODE_K7, llr, n, True, oracle.F32)
@@ -362,6 +363,8 @@ def test_full_batch_4096x8192(dtype, eb, seed):
             plan = mv.Plan([CODE_K7], fr, dtype, radix, variant=3)
         elif pers == "one-state":  # packed, one state per lane
             plan = mv.Plan([CODE_K7], fr, dtype, radix, variant=4)
+        elif pers == "four-state":  # packed, four states per lane (also the default here)
+            plan = mv.Plan([CODE_K7], fr, dtype, radix, variant=5)
         else:
             plan = mv.Plan([CODE_K7], fr, dtype, radix, persistent=pers)
         w, m, _ = plan.decode(t)
@@ -651,7 +654,8 @@ def test_r4_packed_varied_frames():
                        rng.integers(-20, 21, off)).astype(np.int8)
         t = torch.from_numpy(llr).to(DEV)
         ob, om, oend, _ = oracle.decode_frames([CODE_K7], ofr, llr, oracle.I64, nb)
-        for variant, pers in ((0, False), (0, True), (4, False), (4, True)):
+        for variant, pers in ((0, False), (0, True), (4, False), (4, True), (5, False),
+                              (5, True)):
             print("varied", copies, variant, pers, flush=True)
             plan = mv.Plan([CODE_K7], fr, "i8", 4, variant=variant, persistent=pers)
             assert "packed" in plan.describe()
@@ -989,8 +993,8 @@ def test_r4_mfma_varied_frames():
     np.testing.assert_array_equal(m.cpu().numpy()[:9], om2)
 
 
-@pytest.mark.parametrize("code,variant", [(CODE_K7, 0), (CODE_K7, 4), (CODE_K5, 0)],
-                         ids=["K7", "K7-one-state", "K5"])
+@pytest.mark.parametrize("code,variant", [(CODE_K7, 5), (CODE_K7, 4), (CODE_K5, 0)],
+                         ids=["K7-four-state", "K7-one-state", "K5"])
 @pytest.mark.parametrize("eb", [0.0, 3.0])
 def test_r4_split_in_time_matches_oracle(eb, code, variant):
     """Packed radix-4 frame pairs split in time (later parts warm up from
