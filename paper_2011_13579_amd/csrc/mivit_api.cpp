@@ -42,14 +42,12 @@ hipError_t launch_fwd_r4p(int K, const DevCode* codes, const Item* items, const 
                           int n_units, const int8_t* llr, uint64_t* surv, int64_t* metric,
                           int32_t* end_out, int32_t* item_end, int32_t* counter, int grid_limit,
                           R4Bound* bounds, int64_t* last_m, const SplitUnit* split, int n_split,
-                          int64_t* rep_m0, SplitUnit* rep_units, int32_t* rep_count,
-                          hipStream_t st);
+                          int64_t* rep_m0, hipStream_t st);
 hipError_t launch_fwd_r4q(const DevCode* codes, const Item* items, const SplitUnit* units,
                           int n_units, const int8_t* llr, uint64_t* surv, int64_t* metric,
                           int32_t* end_out, int32_t* item_end, int32_t* counter, int grid_limit,
                           R4Bound* bounds, int64_t* last_m, const SplitUnit* split, int n_split,
-                          int64_t* rep_m0, SplitUnit* rep_units, int32_t* rep_count,
-                          hipStream_t st);
+                          int64_t* rep_m0, hipStream_t st);
 hipError_t launch_tb_r4p(int K, const Item* items, const int2* pairs, int n_pairs,
                          const uint64_t* surv, const int32_t* item_end, uint32_t* bits, int warm,
                          hipStream_t st);
@@ -114,7 +112,7 @@ struct Choice {
 constexpr int kSplitAlign = 48;
 constexpr int kSplitWarm = 96;
 constexpr int kSplitMinIt = 384;
-constexpr int kSplitMaxParts = 8;
+constexpr int kSplitMaxParts = kMaxSplitParts;
 constexpr int kSplitWavesPerSimd = 4;
 // The four-states-per-lane kernel holds eight frames per wavefront and four
 // independent chains per lane: it targets fewer wavefronts per SIMD.
@@ -597,13 +595,11 @@ hipError_t part_forward(const mivit_plan* p, const Part& q, const void* llr, voi
     if (g.kern == kKernRot4P)
       e = launch_fwd_r4p(g.K, p->d_codes, q.d_items, q.d_units, q.n_units, (const int8_t*)llr,
                          q.d_surv, (int64_t*)metric, end_state, q.d_item_end, counter, 0,
-                         q.d_bounds, q.d_last_m, q.d_split, q.n_split, q.d_rep_m0,
-                         q.d_rep_units, q.d_rep_count, st);
+                         q.d_bounds, q.d_last_m, q.d_split, q.n_split, q.d_rep_m0, st);
     else if (g.kern == kKernRot4Q)
       e = launch_fwd_r4q(p->d_codes, q.d_items, q.d_units, q.n_units, (const int8_t*)llr,
                          q.d_surv, (int64_t*)metric, end_state, q.d_item_end, counter, 0,
-                         q.d_bounds, q.d_last_m, q.d_split, q.n_split, q.d_rep_m0,
-                         q.d_rep_units, q.d_rep_count, st);
+                         q.d_bounds, q.d_last_m, q.d_split, q.n_split, q.d_rep_m0, st);
     else if (g.kern == kKernMfma4)
       e = launch_fwd_r4_mfma(q.mg, p->d_codes, q.d_items + g.first, g.count, (const int8_t*)llr,
                              q.d_surv, (int64_t*)metric, end_state, q.d_item_end, st);

@@ -31,6 +31,9 @@ struct Item {
   int32_t slot;       // index of this item in per-item scratch arrays
 };
 
+// Most parts a frame is split into in time (see SplitUnit).
+constexpr int kMaxSplitParts = 8;
+
 // One unit of work of a forward kernel that splits frames in time.  For the
 // packed radix-4 kernel: the frames of one wavefront-table entry (first
 // item, count) over the iterations [it_begin, it_end); for the K = 8, 9

@@ -36,8 +36,7 @@ hipError_t launch_fwd_r4p(int K, const DevCode* codes, const Item* items, const 
                           int n_units, const int8_t* llr, uint64_t* surv, int64_t* metric,
                           int32_t* end_out, int32_t* item_end, int32_t* counter, int grid_limit,
                           R4Bound* bounds, int64_t* last_m, const SplitUnit* split, int n_split,
-                          int64_t* rep_m0, SplitUnit* rep_units, int32_t* rep_count,
-                          hipStream_t st);
+                          int64_t* rep_m0, hipStream_t st);
 hipError_t launch_tb_r4p(int K, const Item* items, const int2* pairs, int n_pairs,
                          const uint64_t* surv, const int32_t* item_end, uint32_t* bits, int warm,
                          hipStream_t st);
@@ -209,7 +208,7 @@ extern "C" mivit_status mivit_decode_uniform_noalloc(const void* llr, int32_t dt
   if (L.fam == kFamR4P) {
     e = launch_fwd_r4p(c.K, d_code, items, (const SplitUnit*)waves, L.n_waves, (const int8_t*)llr,
                        surv, (int64_t*)metric, nullptr, item_end, nullptr, 0, nullptr, nullptr,
-                       nullptr, 0, nullptr, nullptr, nullptr, st);
+                       nullptr, 0, nullptr, st);
     if (e == hipSuccess)
       e = launch_tb_r4p(c.K, items, pairs, L.n_pairs, surv, item_end, bits, kWarmR4P, st);
   } else if (L.fam == kFamRot2) {

@@ -713,53 +713,84 @@ __global__ __launch_bounds__(64 * r4p::kR4Waves) void k_fwd_r4p(
 
 // The check after a split forward pass, one wavefront per split entry (its
 // part-0 unit): boundary k is exact when part k's metrics at its end equal
-// part k+1's after its warm-up in every lane (both are range-controlled to
-// state 0 there, so equal words mean metric vectors that differ by a
-// constant).  All exact: the frames' metrics are the last part's plus the
-// accumulated constants.  Else the entry gets a repair unit from its first
-// inexact boundary, with the true metric of state 0 there.
-__global__ __launch_bounds__(64 * r4p::kR4Waves) void k_r4p_check(
-    const Item* __restrict__ items, const SplitUnit* __restrict__ split, int n_split,
-    const R4Bound* __restrict__ bounds, const int64_t* __restrict__ last_m, int64_t* rep_m0,
-    SplitUnit* rep_units, int32_t* rep_count, int64_t* metric, int nv) {
-  const int lane = threadIdx.x & 63;
-  const int e = blockIdx.x * r4p::kR4Waves + (threadIdx.x >> 6);
-  if (e >= n_split) return;
-  const SplitUnit U = split[e];
+// part k+1's after its warm-up at every position (both are range-controlled
+// to state 0 there, so equal words mean metric vectors that differ by a
+// constant).  Every boundary of the entry is loaded at once.  Lane k
+// follows frame k of the entry: T = the true metric of state 0 at the first
+// inexact boundary, D = the constant the last part's metrics lack when all
+// are exact.
+struct EntryCheck {
+  int fail;  // first inexact boundary, or -1
+  int64_t T, D;
+};
+
+template <int NV>
+__device__ __forceinline__ EntryCheck check_entry(const SplitUnit& U,
+                                                  const R4Bound* __restrict__ bounds, int lane) {
   const int n_b = U.n_parts - 1;
-  // lane k < U.count follows frame k of the entry: T = true metric of state
-  // 0 at the current boundary, D = the constant its part adds
-  const bool mine = lane < U.count;
-  const int k = mine ? lane : 0;
-  int64_t T = bounds[U.bnd].m_end[k];  // part 0 is exact
-  int64_t D = 0;
-  int fail = -1;
-  for (int b = 0; b < n_b; ++b) {
-    const R4Bound& B = bounds[U.bnd + b];
-    bool diff = false;
-    for (int x = lane; x < nv; x += 64) diff = diff || B.v_end[x] != B.v_start[x];
-    if (__ballot(diff) != 0) {
-      fail = b;
-      break;
+  const int k = lane < U.count ? lane : 0;
+  uint32_t bad = 0;
+#pragma unroll
+  for (int b = 0; b < kMaxSplitParts - 1; ++b) {
+    if (b < n_b) {
+      const R4Bound& B = bounds[U.bnd + b];
+      bool diff = false;
+#pragma unroll
+      for (int x = 0; x < NV / 64; ++x) diff = diff || B.v_end[64 * x + lane] != B.v_start[64 * x + lane];
+      if (__ballot(diff) != 0) bad |= 1u << b;
     }
-    D = T - B.m_start[k];
+  }
+  EntryCheck r;
+  r.fail = bad ? (int)__builtin_ctz(bad) : -1;
+  const int last = r.fail < 0 ? n_b : r.fail;
+  int64_t T = bounds[U.bnd].m_end[k], D = 0;  // part 0 is exact
+  for (int b = 0; b < last; ++b) {
+    D = T - bounds[U.bnd + b].m_start[k];
     if (b + 1 < n_b) T = bounds[U.bnd + b + 1].m_end[k] + D;
   }
-  if (!mine) return;
-  const Item it = items[U.first + k];
-  if (fail < 0) {
-    if (metric && it.frame >= 0) metric[it.frame] = last_m[it.slot] + D;
+  r.T = T;
+  r.D = D;
+  return r;
+}
+
+// The repair unit of an entry whose boundary `fail` is inexact: the frames
+// from that boundary to their end, from the metrics part `fail` left there.
+__device__ __forceinline__ SplitUnit repair_unit(const SplitUnit& U, const R4Bound* bounds,
+                                                 int fail, int n_stages) {
+  SplitUnit R = U;
+  R.it_begin = bounds[U.bnd + fail].it_at;
+  R.it_end = n_stages >> 1;
+  R.warm = 0;
+  R.part = fail + 1;
+  return R;
+}
+
+// Check of the one-state kernel's split entries; an entry with an inexact
+// boundary is repaired by the same wavefront, right here.
+template <int ND>
+__global__ __launch_bounds__(64 * r4p::kR4Waves) void k_r4p_check(
+    const DevCode* __restrict__ codes, const Item* __restrict__ items,
+    const SplitUnit* __restrict__ split, int n_split, R4Bound* bounds,
+    const int64_t* __restrict__ last_m, int64_t* rep_m0, const int8_t* __restrict__ llr,
+    uint64_t* __restrict__ surv, int64_t* metric, int32_t* end_out, int32_t* item_end) {
+  constexpr int FPG = 64 >> (2 * ND);
+  __shared__ uint32_t tbl_all[r4p::kR4Waves][FPG][16 * 16];
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int e = blockIdx.x * r4p::kR4Waves + wid;
+  if (e >= n_split) return;  // no workgroup barriers: safe to leave
+  const SplitUnit U = split[e];
+  const EntryCheck c = check_entry<64>(U, bounds, lane);
+  const bool mine = lane < U.count;
+  const Item it = items[U.first + (mine ? lane : 0)];
+  if (c.fail < 0) {
+    if (mine && metric && it.frame >= 0) metric[it.frame] = last_m[it.slot] + c.D;
     return;
   }
-  rep_m0[it.slot] = T;
-  if (lane == 0) {
-    SplitUnit R = U;
-    R.it_begin = (int)bounds[U.bnd + fail].it_at;
-    R.it_end = it.n_stages >> 1;
-    R.warm = 0;
-    R.part = fail + 1;
-    rep_units[atomicAdd(rep_count, 1)] = R;
-  }
+  if (mine) rep_m0[it.slot] = c.T;
+  __threadfence();
+  fwd_r4p_wave<ND>(codes, items, repair_unit(U, bounds, c.fail, items[U.first].n_stages), 1,
+                   bounds, const_cast<int64_t*>(last_m), rep_m0, llr, surv, metric, end_out,
+                   item_end, tbl_all[wid], lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -1257,12 +1288,38 @@ __global__ __launch_bounds__(64 * r4q::kWaves, 2) void k_fwd_r4q(
   }
 }
 
+// Check of the four-state kernel's split entries, with repairs in place.
+__global__ __launch_bounds__(64 * r4q::kWaves, 2) void k_r4q_check(
+    const DevCode* __restrict__ codes, const Item* __restrict__ items,
+    const SplitUnit* __restrict__ split, int n_split, R4Bound* bounds,
+    const int64_t* __restrict__ last_m, int64_t* rep_m0, const int8_t* __restrict__ llr,
+    uint64_t* __restrict__ surv, int64_t* metric, int32_t* end_out, int32_t* item_end) {
+  __shared__ __align__(16) uint32_t tbl_all[r4q::kWaves][3 * r4q::kBufWords];
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int e = blockIdx.x * r4q::kWaves + wid;
+  if (e >= n_split) return;  // no workgroup barriers: safe to leave
+  const SplitUnit U = split[e];
+  const EntryCheck c = check_entry<256>(U, bounds, lane);
+  const bool mine = lane < U.count;
+  const Item it = items[U.first + (mine ? lane : 0)];
+  if (c.fail < 0) {
+    if (mine && metric && it.frame >= 0) metric[it.frame] = last_m[it.slot] + c.D;
+    return;
+  }
+  if (mine) rep_m0[it.slot] = c.T;
+  __threadfence();
+  fwd_r4q_wave(codes, items, repair_unit(U, bounds, c.fail, items[U.first].n_stages), 1, bounds,
+               const_cast<int64_t*>(last_m), rep_m0, llr, surv, metric, end_out, item_end,
+               tbl_all[wid], lane);
+}
+
+// Forward pass of a part; split entries are then checked (and repaired in
+// place) by one more launch.
 hipError_t launch_fwd_r4p(int K, const DevCode* codes, const Item* items, const SplitUnit* units,
                           int n_units, const int8_t* llr, uint64_t* surv, int64_t* metric,
                           int32_t* end_out, int32_t* item_end, int32_t* counter, int grid_limit,
                           R4Bound* bounds, int64_t* last_m, const SplitUnit* split, int n_split,
-                          int64_t* rep_m0, SplitUnit* rep_units, int32_t* rep_count,
-                          hipStream_t st) {
+                          int64_t* rep_m0, hipStream_t st) {
   if (n_units <= 0) return hipSuccess;
   if (K != 5 && K != 7) return hipErrorInvalidValue;
   auto kernel = K == 7 ? k_fwd_r4p<3> : k_fwd_r4p<2>;
@@ -1277,19 +1334,10 @@ hipError_t launch_fwd_r4p(int K, const DevCode* codes, const Item* items, const 
                      surv, metric, end_out, item_end, counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || n_split <= 0) return e;
-  // check the split entries, then repair the inexact ones
-  e = launch_zero_i32(rep_count, 1, st);
-  if (e != hipSuccess) return e;
+  auto check = K == 7 ? k_r4p_check<3> : k_r4p_check<2>;
   const int ns = (n_split + r4p::kR4Waves - 1) / r4p::kR4Waves;
-  hipLaunchKernelGGL(k_r4p_check, dim3(ns), dim3(threads), 0, st, items, split, n_split,
-                     (const R4Bound*)bounds, (const int64_t*)last_m, rep_m0, rep_units, rep_count,
-                     metric, 64);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kernel, dim3(ns), dim3(threads), 0, st, codes, items,
-                     (const SplitUnit*)rep_units, n_split, (const int32_t*)rep_count, 1, bounds,
-                     last_m, (const int64_t*)rep_m0, llr, surv, metric, end_out, item_end,
-                     (int32_t*)nullptr);
+  hipLaunchKernelGGL(check, dim3(ns), dim3(threads), 0, st, codes, items, split, n_split, bounds,
+                     (const int64_t*)last_m, rep_m0, llr, surv, metric, end_out, item_end);
   return hipGetLastError();
 }
 
@@ -1297,8 +1345,7 @@ hipError_t launch_fwd_r4q(const DevCode* codes, const Item* items, const SplitUn
                           int n_units, const int8_t* llr, uint64_t* surv, int64_t* metric,
                           int32_t* end_out, int32_t* item_end, int32_t* counter, int grid_limit,
                           R4Bound* bounds, int64_t* last_m, const SplitUnit* split, int n_split,
-                          int64_t* rep_m0, SplitUnit* rep_units, int32_t* rep_count,
-                          hipStream_t st) {
+                          int64_t* rep_m0, hipStream_t st) {
   if (n_units <= 0) return hipSuccess;
   const int threads = 64 * r4q::kWaves;
   int nb = (n_units + r4q::kWaves - 1) / r4q::kWaves;
@@ -1311,19 +1358,10 @@ hipError_t launch_fwd_r4q(const DevCode* codes, const Item* items, const SplitUn
                      surv, metric, end_out, item_end, counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || n_split <= 0) return e;
-  e = launch_zero_i32(rep_count, 1, st);
-  if (e != hipSuccess) return e;
-  const int ns = (n_split + r4p::kR4Waves - 1) / r4p::kR4Waves;
-  hipLaunchKernelGGL(k_r4p_check, dim3(ns), dim3(64 * r4p::kR4Waves), 0, st, items, split,
-                     n_split, (const R4Bound*)bounds, (const int64_t*)last_m, rep_m0, rep_units,
-                     rep_count, metric, 256);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int nr = (n_split + r4q::kWaves - 1) / r4q::kWaves;
-  hipLaunchKernelGGL(k_fwd_r4q, dim3(nr), dim3(threads), 0, st, codes, items,
-                     (const SplitUnit*)rep_units, n_split, (const int32_t*)rep_count, 1, bounds,
-                     last_m, (const int64_t*)rep_m0, llr, surv, metric, end_out, item_end,
-                     (int32_t*)nullptr);
+  const int ns = (n_split + r4q::kWaves - 1) / r4q::kWaves;
+  hipLaunchKernelGGL(k_r4q_check, dim3(ns), dim3(threads), 0, st, codes, items, split, n_split,
+                     bounds, (const int64_t*)last_m, rep_m0, llr, surv, metric, end_out,
+                     item_end);
   return hipGetLastError();
 }
 
