@@ -117,11 +117,11 @@ constexpr int kSplitWavesPerSimd = 4;
 // The four-states-per-lane kernel holds eight frames per wavefront and four
 // independent chains per lane: it targets fewer wavefronts per SIMD.
 constexpr int kSplitWavesPerSimdQ = 2;
-// Time split of the K = 8, 9 radix-2 kernel (int8): a frame longer than
-// twice the batch's stages per wavefront slot (at least kWideSplitLen) is
-// cut into parts of whole lcm(32, K-1)-stage periods, later parts warming up
-// for at least kWideSplitWarm stages.
-constexpr int kWideSplitLen = 2048;
+// Time split of the K = 8, 9 radix-2 kernel (int8): a frame is cut into
+// about S / len parts of whole lcm(32, K-1)-stage periods, len being the
+// batch's stages per wavefront slot (at least kWideSplitLen), later parts
+// warming up for at least kWideSplitWarm stages.
+constexpr int kWideSplitLen = 1024;
 constexpr int kWideSplitWarm = 192;
 
 struct PlanGroup {
@@ -434,23 +434,28 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
       for (const int2& w : waves)
         for (int s = 0; s < w.y; s += 2) pairs.push_back(make_int2(w.x + s, std::min(2, w.y - s)));
       g.n_pairs = (int)pairs.size();
-      // work units: whole entries, or parts of entries in time
-      int parts_max = 1;
-      // (persistent launches keep frame pairs whole)
+      // work units: whole entries, or parts of entries in time.  The batch
+      // is to fill about kSplitWavesPerSimd wavefronts per SIMD: with slots
+      // such wavefront places and I iterations over all entries, an entry
+      // of n iterations is cut into about n * slots / I parts, so in a
+      // batch of mixed lengths the longest entries are cut the most (in a
+      // batch of one length every entry gets the same number of parts).
+      // Persistent launches keep frame pairs whole.
+      int64_t slots = 0, total_it = 0;
       if (ch.split && !ch.persistent && !waves.empty()) {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-            cus > 0) {
-          const int64_t target =
-              (int64_t)cus * 4 * (kern == kKernRot4Q ? kSplitWavesPerSimdQ : kSplitWavesPerSimd);
-          parts_max = (int)std::min<int64_t>(kSplitMaxParts,
-                                             (target + (int64_t)waves.size() - 1) / (int64_t)waves.size());
-        }
+            cus > 0)
+          slots = (int64_t)cus * 4 * (kern == kKernRot4Q ? kSplitWavesPerSimdQ : kSplitWavesPerSimd);
+        for (const int2& w : waves) total_it += items[w.x].n_stages >> 1;
       }
       for (const int2& w : waves) {
         const int n_it = items[w.x].n_stages >> 1;
-        const int P = std::max(1, std::min(parts_max, n_it / kSplitMinIt));
+        int64_t want = 1;
+        if (slots > 0 && total_it > 0) want = ((int64_t)n_it * slots + total_it - 1) / total_it;
+        const int P = (int)std::max<int64_t>(
+            1, std::min<int64_t>(want, std::min(kSplitMaxParts, n_it / kSplitMinIt)));
         SplitUnit u;
         u.first = w.x;
         u.count = w.y;
@@ -507,7 +512,7 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
     const bool can = ch.split && dtype == MIVIT_I8;
     for (int k = 0; k < (int)items.size(); ++k) {
       const int S = items[k].n_stages;
-      int P = can ? (int)std::min<int64_t>(kSplitMaxParts, S / (2 * len) + 1) : 1;
+      int P = can ? (int)std::min<int64_t>(kSplitMaxParts, (S + len - 1) / len) : 1;
       if (S < 2 * period + warm) P = 1;
       SplitUnit u;
       u.first = k;

@@ -182,4 +182,16 @@ __host__ __device__ inline int64_t surv_words_natural(int K, int S) {
 // after the last item.
 constexpr int64_t kSurvSlackWords = 32;
 
+// Shift a decision into a lane's word: acc = 2*acc + d in one add-with-carry,
+// the carry-in being the wave mask of the comparison.  The wait state covers
+// a VALU-written SGPR read as carry by the next VALU instruction.
+__device__ __forceinline__ uint32_t push_decision(uint32_t acc, uint64_t mask) {
+  uint32_t out;
+  uint64_t carry_out;
+  asm("s_nop 1\n\tv_addc_co_u32_e64 %0, %1, %2, %2, %3"
+         : "=v"(out), "=s"(carry_out)
+         : "v"(acc), "s"(mask));
+  return out;
+}
+
 }  // namespace mivit

@@ -128,18 +128,6 @@ struct Frame {
   uint64_t bmask[KM1];  // lanes whose bit q is set, per phase q
 };
 
-// Shift a decision into a lane's word: acc = 2*acc + d in one add-with-carry,
-// the carry-in being the wave mask of the comparison.  The wait state covers
-// a VALU-written SGPR read as carry by the next VALU instruction.
-__device__ __forceinline__ uint32_t push_decision(uint32_t acc, uint64_t mask) {
-  uint32_t out;
-  uint64_t carry_out;
-  asm volatile("s_nop 1\n\tv_addc_co_u32_e64 %0, %1, %2, %2, %3"
-               : "=v"(out), "=s"(carry_out)
-               : "v"(acc), "s"(mask));
-  return out;
-}
-
 // Mode 2 picks, per lane bit, the cheapest exchange that stays in the VALU:
 //   bits 0, 1  both previous-state metrics by DPP quad permutations (fixed roles)
 //   bit 2      partner (lane ^ 4) = quad reverse of the row half-mirror (two DPPs)

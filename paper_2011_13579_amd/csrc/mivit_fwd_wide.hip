@@ -130,19 +130,36 @@ __device__ __forceinline__ typename Ty<DT>::T partner_fetch(typename Ty<DT>::T x
 template <int DT, int R>
 struct Wave {
   using T = typename Ty<DT>::T;
-  T pm[R];          // metric of the state at position 64 r + lane
-  uint32_t acc[R];  // decisions of position 64 r + lane in the current block
+  T pm[R];           // metric of the state at position 64 r + lane
+  uint32_t acc[R];   // decisions of position 64 r + lane in the current block
+  uint32_t pend[R];  // the previous block's decision words, not yet stored
 };
 
 
-// Add, compare, select for one position: the even and odd previous states'
-// metrics e and o, m the even one's branch metric.
-template <typename T>
-__device__ __forceinline__ T acs(T e, T o, T m, bool& d) {
-  const T ce = e + m;
-  const T co = o - m;
-  d = co > ce;
-  return d ? co : ce;
+// The larger of two metrics: v_max for floats too, so that the select does
+// not wait on the comparison's mask (no NaN arises: finite soft values, and
+// -inf plus finite branch metrics for unreachable float states).
+__device__ __forceinline__ float tmax(float a, float b) { return __builtin_fmaxf(a, b); }
+__device__ __forceinline__ int tmax(int a, int b) { return a > b ? a : b; }
+
+// push_decision for every register of a stage: one wait state pair for all
+// of them (a VALU-written SGPR read as carry needs two).
+template <int R>
+__device__ __forceinline__ void push_decisions(uint32_t (&acc)[R], const uint64_t (&d)[R]) {
+  if constexpr (R == 4) {
+    uint64_t c0, c1, c2, c3;
+    asm("s_nop 1\n\t"
+        "v_addc_co_u32_e64 %0, %4, %0, %0, %8\n\t"
+        "v_addc_co_u32_e64 %1, %5, %1, %1, %9\n\t"
+        "v_addc_co_u32_e64 %2, %6, %2, %2, %10\n\t"
+        "v_addc_co_u32_e64 %3, %7, %3, %3, %11"
+        : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "=s"(c0), "=s"(c1), "=s"(c2),
+          "=s"(c3)
+        : "s"(d[0]), "s"(d[1]), "s"(d[2]), "s"(d[3]));
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = push_decision(acc[r], d[r]);
+  }
 }
 
 // One stage at phase Q; bm[r] the branch metric of position 64r + lane: of
@@ -156,49 +173,82 @@ template <int KM1, int DT, int R, int Q>
 __device__ __forceinline__ void stage(Wave<DT, R>& W, const typename Ty<DT>::T (&bm)[R]) {
   using T = typename Ty<DT>::T;
   T nv[R];
-  bool d[R];
+  uint64_t d[R];  // lanes whose odd previous state won
   if constexpr (own_partner<DT, Q>()) {
-    const bool own_odd = ((threadIdx.x >> Q) & 1) != 0;
+    // lanes with bit Q set hold the odd previous state
+    constexpr uint64_t odd = Q == 2 ? 0xF0F0F0F0F0F0F0F0ull : 0xFF00FF00FF00FF00ull;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const T cp = partner_fetch<Q, DT>(W.pm[r]) - bm[r];
       const T co = W.pm[r] + bm[r];
-      nv[r] = cp > co ? cp : co;
-      d[r] = own_odd ? (co > cp) : (cp > co);
+      nv[r] = tmax(cp, co);
+      d[r] = (__builtin_amdgcn_ballot_w64(cp > co) & ~odd) |
+             (__builtin_amdgcn_ballot_w64(co > cp) & odd);
     }
   } else if constexpr (Q < 6) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       T e, o;
       pair_fetch<Q, DT>(W.pm[r], e, o);
-      nv[r] = acs(e, o, bm[r], d[r]);
+      const T ce = e + bm[r], co = o - bm[r];
+      nv[r] = tmax(ce, co);
+      d[r] = __builtin_amdgcn_ballot_w64(co > ce);
     }
   } else {
     constexpr int rb = 1 << (Q - 6);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int re = r & ~rb, ro = r | rb;
-      nv[r] = acs(W.pm[re], W.pm[ro], bm[r], d[r]);
+      const T ce = W.pm[re] + bm[r], co = W.pm[ro] - bm[r];
+      nv[r] = tmax(ce, co);
+      d[r] = __builtin_amdgcn_ballot_w64(co > ce);
     }
   }
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    W.pm[r] = nv[r];
-    W.acc[r] = 2u * W.acc[r] + (d[r] ? 1u : 0u);
-  }
+  for (int r = 0; r < R; ++r) W.pm[r] = nv[r];
+  push_decisions<R>(W.acc, d);
 }
 
-// Stages K0..31 of a full block starting at phase P0 (static phases).
+// Branch metrics are read from LDS kPrefetch stages ahead of their use: a
+// lone wavefront (the longest frame of a batch, once the others are done)
+// otherwise waits out the LDS latency at every stage.
+constexpr int kPrefetch = 3;
+
+template <int KM1, int DT, int R, int NP, int P0, int K>
+__device__ __forceinline__ void fetch_bm(typename Ty<DT>::T (&dst)[R],
+                                         const typename Ty<DT>::T* bmt,
+                                         const int (&pat)[KM1][R]) {
+  constexpr int Q = (P0 + K) % KM1;
+#pragma unroll
+  for (int r = 0; r < R; ++r) dst[r] = bmt[K * NP + pat[Q][r]];
+}
+
+// Stages K0..31 of a full block starting at phase P0 (static phases); q
+// holds the branch metrics of stages K0 .. K0 + kPrefetch - 1.
 template <int KM1, int DT, int R, int NP, int P0, int K0>
 __device__ __forceinline__ void stages_full(Wave<DT, R>& W, const typename Ty<DT>::T* bmt,
-                                            const int (&pat)[KM1][R]) {
+                                            const int (&pat)[KM1][R],
+                                            typename Ty<DT>::T (&q)[kPrefetch][R]) {
   if constexpr (K0 < 32) {
     constexpr int Q = (P0 + K0) % KM1;
     typename Ty<DT>::T bm[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) bm[r] = bmt[K0 * NP + pat[Q][r]];
+    for (int r = 0; r < R; ++r) bm[r] = q[K0 % kPrefetch][r];
+    if constexpr (K0 + kPrefetch < 32)
+      fetch_bm<KM1, DT, R, NP, P0, K0 + kPrefetch>(q[K0 % kPrefetch], bmt, pat);
     stage<KM1, DT, R, Q>(W, bm);
-    stages_full<KM1, DT, R, NP, P0, K0 + 1>(W, bmt, pat);
+    __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of their stages
+    stages_full<KM1, DT, R, NP, P0, K0 + 1>(W, bmt, pat, q);
+  }
+}
+
+template <int KM1, int DT, int R, int NP, int P0, int K>
+__device__ __forceinline__ void prefetch_first(typename Ty<DT>::T (&q)[kPrefetch][R],
+                                               const typename Ty<DT>::T* bmt,
+                                               const int (&pat)[KM1][R]) {
+  if constexpr (K < kPrefetch) {
+    fetch_bm<KM1, DT, R, NP, P0, K>(q[K], bmt, pat);
+    prefetch_first<KM1, DT, R, NP, P0, K + 1>(q, bmt, pat);
   }
 }
 
@@ -232,7 +282,20 @@ struct Ctx {
   int t_store;     // first stage whose decisions are stored
   int32_t* v_start;  // split part after the first: boundary record to fill at t_store
   int64_t* m_start;
+  uint8_t* pend_dst;  // where the pending decision words go, or null
 };
+
+// Store one block's decision words: four groups of 8 stages, group g of the
+// block being byte 3 - g of the word.
+template <int KM1, int R>
+__device__ __forceinline__ void store_block(uint8_t* dst, const uint32_t (&a)[R]) {
+  constexpr int NS = 1 << KM1;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) dst[g * NS + 64 * r] = (uint8_t)(a[r] >> (24 - 8 * g));
+  }
+}
 
 // One block of up to 32 stages starting at tb; BI its index in the period
 // of the phase pattern.  lv: this lane's soft values of stage tb + lane
@@ -263,6 +326,11 @@ __device__ __forceinline__ void one_block(Wave<DT, 1 << (KM1 - 6)>& W, Ctx& cx,
 #pragma unroll
     for (int b = 0; b < BETA; ++b) lv[b] = ok ? (T)llr[(int64_t)t * BETA + b] : (T)0;
   }
+  // the previous block's decisions go out here, after the next soft values
+  // are requested: the memory counter the next block start waits on (for
+  // those soft values) covers stores too, so stores issued at the end of a
+  // block would hold up the start of the next
+  if (cx.pend_dst) store_block<KM1, R>(cx.pend_dst, W.pend);
   if constexpr (Ty<DT>::kInt) {
     if (tb > 0) {
       // renormalise by the metric of state 0 (always position 0: lane 0, register 0)
@@ -281,21 +349,20 @@ __device__ __forceinline__ void one_block(Wave<DT, 1 << (KM1 - 6)>& W, Ctx& cx,
   wave_sync();
   constexpr int P0 = (32 * BI) % KM1;
   if (n == 32) {
-    stages_full<KM1, DT, R, NP, P0, 0>(W, bmt, pat);
+    T q[kPrefetch][R];
+    prefetch_first<KM1, DT, R, NP, P0, 0>(q, bmt, pat);
+    stages_full<KM1, DT, R, NP, P0, 0>(W, bmt, pat, q);
   } else {
 #pragma unroll 1
     for (int k = 0; k < n; ++k) stage_dyn<KM1, DT, R, NP, 0>(W, bmt + k * NP, pat, (P0 + k) % KM1);
   }
-  // four groups of 8 stages: group g of the block is byte 3 - g of acc
+  // this block's decisions: stored at the next block's start, or after the
+  // last block
+  cx.pend_dst = nullptr;
   if (tb >= cx.t_store) {
-    constexpr int NS = 1 << KM1;
-    uint8_t* dst = (uint8_t*)sv + (int64_t)(tb >> 3) * NS + cx.lane;
+    cx.pend_dst = (uint8_t*)sv + (int64_t)(tb >> 3) * (1 << KM1) + cx.lane;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const uint32_t a = n == 32 ? W.acc[r] : W.acc[r] << (32 - n);
-#pragma unroll
-      for (int g = 0; g < 4; ++g) dst[g * NS + 64 * r] = (uint8_t)(a >> (24 - 8 * g));
-    }
+    for (int r = 0; r < R; ++r) W.pend[r] = n == 32 ? W.acc[r] : W.acc[r] << (32 - n);
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) W.acc[r] = 0;
@@ -329,7 +396,7 @@ constexpr int kWideWaves = 4;  // independent wavefronts (frames) per workgroup
 // decisions from them; a part before the last leaves its end metrics in a
 // boundary record, the last part its own metric, which the check completes.
 template <int KM1, int DT, int BETA>
-__global__ __launch_bounds__(64 * wide::kWideWaves) void k_fwd_wide(
+__global__ __launch_bounds__(64 * wide::kWideWaves, 3) void k_fwd_wide(
     const DevCode* __restrict__ codes, const Item* __restrict__ items,
     const SplitUnit* __restrict__ units, int n_units, const int32_t* dev_count, int kind,
     WideBound* bounds, int64_t* last_m, const int64_t* rep_m0,
@@ -385,7 +452,7 @@ __global__ __launch_bounds__(64 * wide::kWideWaves) void k_fwd_wide(
       W.pm[r] = Ty<DT>::from(bounds[U.bnd + U.part - 1].v_end[64 * r + lane]);  // repair
     W.acc[r] = 0;
   }
-  Ctx cx{0, U.it_end, lane, U.it_begin, nullptr, nullptr};
+  Ctx cx{0, U.it_end, lane, U.it_begin, nullptr, nullptr, nullptr};
   if (kind == 0 && U.part > 0) {
     cx.v_start = bounds[U.bnd + U.part - 1].v_start;
     cx.m_start = &bounds[U.bnd + U.part - 1].m_start;
@@ -398,6 +465,7 @@ __global__ __launch_bounds__(64 * wide::kWideWaves) void k_fwd_wide(
   }
   for (int t0 = s0; t0 < cx.S; t0 += SUPER)
     super_block<KM1, DT, BETA, 0, SUPER / 32>(W, cx, bmt, llr, lv, pat, sv, t0);
+  if (cx.pend_dst) store_block<KM1, R>(cx.pend_dst, W.pend);
 
   if constexpr (Ty<DT>::kInt) {
     if (kind == 0 && split && U.part < U.n_parts - 1) {
