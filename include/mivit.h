@@ -120,7 +120,13 @@ typedef struct {
                        radix 4 only; else MIVIT_EUNSUPPORTED); 5: radix 4
                        packed with four states per lane for any batch (int8,
                        K = 7, beta = 2, radix 4 only; else
-                       MIVIT_EUNSUPPORTED) */
+                       MIVIT_EUNSUPPORTED); 6 and 7: radix 2 with each
+                       frame's states in the registers of two (6: K = 8
+                       or 9) or four (7: K = 9) wavefronts, the stages on
+                       a wavefront bit exchanging through LDS (float32
+                       only; else MIVIT_EUNSUPPORTED): a long frame's
+                       serial chain runs with fewer instructions per
+                       wavefront */
   uint32_t flags;   /* MIVIT_PLAN_* scheduling options, below */
   int32_t reserved[2]; /* must be zero */
 } mivit_opts;

@@ -30,7 +30,8 @@ hipError_t launch_fwd_rot(int K, int beta, int dt, int mode, const DevCode* code
                           const Item* items, const int2* waves, int n_waves, const void* llr,
                           uint64_t* surv, void* metric, int32_t* end_out, int32_t* item_end,
                           int32_t* counter, int grid_limit, hipStream_t st);
-hipError_t launch_fwd_wide(int K, int beta, int dt, const DevCode* codes, const Item* items,
+hipError_t launch_fwd_wide(int K, int beta, int dt, int wpf, const DevCode* codes,
+                           const Item* items,
                            const SplitUnit* units, int n_units, const void* llr, uint64_t* surv,
                            void* metric, int32_t* end_out, int32_t* item_end, WideBound* bounds,
                            int64_t* last_m, const SplitUnit* split, int n_split, int64_t* rep_m0,
@@ -123,6 +124,10 @@ constexpr int kSplitWavesPerSimdQ = 2;
 // warming up for at least kWideSplitWarm stages.
 constexpr int kWideSplitLen = 1024;
 constexpr int kWideSplitWarm = 192;
+
+// Wavefronts per frame of the K = 8, 9 radix-2 kernel: variants 6 and 7
+// spread a float32 frame's states over two or four wavefronts.
+int waves_per_frame(const Choice& ch) { return ch.variant == 6 ? 2 : ch.variant == 7 ? 4 : 1; }
 
 struct PlanGroup {
   int kern;   // forward kernel
@@ -376,7 +381,8 @@ mivit_status build_part(const mivit_code* codes, const mivit_frame* frames,
   else if (ch.radix == 4)
     kern = kKernGeneric4;
   else
-    kern = c.K <= 7 ? kKernRot2 : (ch.variant == 0 ? kKernWide : kKernGeneric2);
+    kern = c.K <= 7 ? kKernRot2
+                    : ((ch.variant == 0 || ch.variant >= 6) ? kKernWide : kKernGeneric2);
   // longest first; items that can share a packed lane group next to each other
   std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) {
     if (a.n_stages != b.n_stages) return a.n_stages > b.n_stages;
@@ -609,8 +615,9 @@ hipError_t part_forward(const mivit_plan* p, const Part& q, const void* llr, voi
       e = launch_fwd_r4_mfma(q.mg, p->d_codes, q.d_items + g.first, g.count, (const int8_t*)llr,
                              q.d_surv, (int64_t*)metric, end_state, q.d_item_end, st);
     else if (g.kern == kKernWide)
-      e = launch_fwd_wide(g.K, g.beta, dt, p->d_codes, q.d_items, q.d_units, q.n_units, llr,
-                          q.d_surv, metric, end_state, q.d_item_end, q.d_wbounds, q.d_last_m,
+      e = launch_fwd_wide(g.K, g.beta, dt, waves_per_frame(q.ch), p->d_codes, q.d_items,
+                          q.d_units, q.n_units, llr, q.d_surv, metric, end_state, q.d_item_end,
+                          q.d_wbounds, q.d_last_m,
                           q.d_split, q.n_split, q.d_rep_m0, q.d_rep_units, q.d_rep_count, st);
     else if (g.kern == kKernRot2)
       e = launch_fwd_rot(g.K, g.beta, dt, kRotMode[q.ch.variant], p->d_codes, q.d_items,
@@ -690,6 +697,8 @@ std::vector<Choice> candidates(const mivit_code& c, int dtype, int radix) {
     } else {
       add(2, 0, false);  // registers (wide kernel)
       add(2, 1, false);  // LDS exchanges (generic kernel)
+      if (dtype == MIVIT_F32) add(2, 6, false);  // registers, two wavefronts per frame
+      if (dtype == MIVIT_F32 && c.K == 9) add(2, 7, false);  // four wavefronts per frame
     }
   }
   if (i8 && (radix == 0 || radix == 4)) {
@@ -776,8 +785,11 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
   if (o.radix != 0 && o.radix != 2 && o.radix != 4 && o.radix != 8) return MIVIT_EINVAL;
   if ((o.radix == 4 || o.radix == 8) && o.dtype != MIVIT_I8) return MIVIT_EINVAL;
   if (o.chunk < 0 || o.overlap < 0 || (o.chunk > 0 && o.chunk % 32 != 0)) return MIVIT_EINVAL;
-  if (o.variant < 0 || o.variant > 5) return MIVIT_EINVAL;
-  if (o.variant >= 3 && (o.radix != 4 || o.dtype != MIVIT_I8)) return MIVIT_EUNSUPPORTED;
+  if (o.variant < 0 || o.variant > 7) return MIVIT_EINVAL;
+  if (o.variant >= 3 && o.variant <= 5 && (o.radix != 4 || o.dtype != MIVIT_I8))
+    return MIVIT_EUNSUPPORTED;
+  if (o.variant >= 6 && ((o.radix != 0 && o.radix != 2) || o.dtype != MIVIT_F32))
+    return MIVIT_EUNSUPPORTED;
   if (o.flags & ~(MIVIT_PLAN_GRAPH | MIVIT_PLAN_AUTOTUNE | MIVIT_PLAN_PERSISTENT |
                   MIVIT_PLAN_NO_SPLIT))
     return MIVIT_EINVAL;
@@ -796,6 +808,9 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
   if (o.variant == 5)
     for (int c = 0; c < n_codes; ++c)
       if (!quad_ok(codes[c])) return MIVIT_EUNSUPPORTED;
+  if (o.variant >= 6)  // 2 or 4 wavefronts per frame: 2^(K-1) >= 128 or 256 states
+    for (int c = 0; c < n_codes; ++c)
+      if (codes[c].K < (o.variant == 6 ? 8 : 9)) return MIVIT_EUNSUPPORTED;
   if (o.radix == 8) {  // one kernel, and at least 8 states
     if (o.variant != 0) return MIVIT_EUNSUPPORTED;
     for (int c = 0; c < n_codes; ++c)
@@ -1070,13 +1085,16 @@ mivit_status mivit_plan_describe(const mivit_plan* p, char* buf, int32_t len) {
     for (const PlanGroup& g : q.groups) {
       // the rotating kernels run a wave table; the others one wavefront per item
       const bool table = g.kern == kKernRot2 || g.kern == kKernRot4P || g.kern == kKernRot4Q;
+      const int wpf = g.kern == kKernWide ? waves_per_frame(q.ch) : 1;
       std::snprintf(line, sizeof line,
                     "%scode %d: K=%d beta=%d, %s forward, variant %d, %s, %d items, %d wavefronts",
                     s.empty() ? "" : "; ", q.code, g.K, g.beta, kern_name(g.kern), q.ch.variant,
                     g.counter >= 0 ? "persistent work queue"
                     : table        ? "one wavefront per table entry"
+                    : wpf == 2     ? "two wavefronts per item"
+                    : wpf == 4     ? "four wavefronts per item"
                                    : "one wavefront per item",
-                    g.count, table ? g.n_waves : g.count);
+                    g.count, table ? g.n_waves : wpf * g.count);
       s += line;
     }
   }

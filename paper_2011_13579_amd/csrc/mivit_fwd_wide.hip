@@ -130,10 +130,31 @@ __device__ __forceinline__ typename Ty<DT>::T partner_fetch(typename Ty<DT>::T x
 template <int DT, int R>
 struct Wave {
   using T = typename Ty<DT>::T;
-  T pm[R];           // metric of the state at position 64 r + lane
-  uint32_t acc[R];   // decisions of position 64 r + lane in the current block
+  T pm[R];           // metric of the state at position 64 (R w + r) + lane
+  uint32_t acc[R];   // decisions of that position in the current block
   uint32_t pend[R];  // the previous block's decision words, not yet stored
+  // several wavefronts per frame: LDS exchange area of the frame, the
+  // number of wavefronts, this one's index w in the frame, and the exchange
+  // buffer in use
+  T* xch;
+  int nw, fw, xb;
 };
+
+// All wavefronts of a frame at one point, LDS writes before it visible to
+// LDS reads after it (one wavefront: program order suffices).
+template <int WPF>
+__device__ __forceinline__ void frame_sync() {
+  // (any WPF > 1: the frame is the workgroup)
+  if constexpr (WPF == 1) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  }
+}
 
 
 // The larger of two metrics: v_max for floats too, so that the select does
@@ -174,7 +195,32 @@ __device__ __forceinline__ void stage(Wave<DT, R>& W, const typename Ty<DT>::T (
   using T = typename Ty<DT>::T;
   T nv[R];
   uint64_t d[R];  // lanes whose odd previous state won
-  if constexpr (own_partner<DT, Q>()) {
+  if constexpr (Q >= 6 && (1 << (Q - 6)) >= R) {
+    // bit Q is bit wb of the wavefront index (several per frame): the
+    // wavefronts with that bit clear hold the even previous states, their
+    // partners (index ^ wb) the odd ones, at the same register and lane;
+    // each writes its metrics to the exchange buffer and reads its partner's
+    constexpr int wb = (1 << (Q - 6)) / R;
+    const int lane = threadIdx.x & 63;
+    const int nw = W.nw;
+    T* mine = W.xch + (nw * W.xb + W.fw) * (64 * R);
+    const T* theirs = W.xch + (nw * W.xb + (W.fw ^ wb)) * (64 * R);
+#pragma unroll
+    for (int r = 0; r < R; ++r) mine[64 * r + lane] = W.pm[r];
+    frame_sync<2>();
+    const bool odd = (W.fw & wb) != 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const T other = theirs[64 * r + lane];
+      const T e = odd ? other : W.pm[r], o = odd ? W.pm[r] : other;
+      const T ce = e + bm[r], co = o - bm[r];
+      nv[r] = tmax(ce, co);
+      d[r] = __builtin_amdgcn_ballot_w64(co > ce);
+    }
+    // double buffered: the next exchange writes the other buffer, and the
+    // one after it comes after a barrier that follows these reads
+    W.xb ^= 1;
+  } else if constexpr (own_partner<DT, Q>()) {
     // lanes with bit Q set hold the odd previous state
     constexpr uint64_t odd = Q == 2 ? 0xF0F0F0F0F0F0F0F0ull : 0xFF00FF00FF00FF00ull;
 #pragma unroll
@@ -283,6 +329,7 @@ struct Ctx {
   int32_t* v_start;  // split part after the first: boundary record to fill at t_store
   int64_t* m_start;
   uint8_t* pend_dst;  // where the pending decision words go, or null
+  int pos0;           // first position held by this wavefront (64 R w)
 };
 
 // Store one block's decision words: four groups of 8 stages, group g of the
@@ -300,15 +347,13 @@ __device__ __forceinline__ void store_block(uint8_t* dst, const uint32_t (&a)[R]
 // One block of up to 32 stages starting at tb; BI its index in the period
 // of the phase pattern.  lv: this lane's soft values of stage tb + lane
 // (lanes < 32), replaced by those of the next block.
-template <int KM1, int DT, int BETA, int BI>
-__device__ __forceinline__ void one_block(Wave<DT, 1 << (KM1 - 6)>& W, Ctx& cx,
-                                          typename Ty<DT>::T* bmt,
+template <int KM1, int DT, int BETA, int BI, int R>
+__device__ __forceinline__ void one_block(Wave<DT, R>& W, Ctx& cx, typename Ty<DT>::T* bmt,
                                           const typename Ty<DT>::In* llr,
                                           typename Ty<DT>::T (&lv)[BETA],
-                                          const int (&pat)[KM1][1 << (KM1 - 6)],
-                                          uint64_t* sv, int tb) {
+                                          const int (&pat)[KM1][R], uint64_t* sv, int tb) {
   using T = typename Ty<DT>::T;
-  constexpr int R = 1 << (KM1 - 6), NP = 1 << BETA;
+  constexpr int NP = 1 << BETA;
   const int n = min(32, cx.S - tb);
   if (cx.lane < 32) {
 #pragma unroll
@@ -360,7 +405,7 @@ __device__ __forceinline__ void one_block(Wave<DT, 1 << (KM1 - 6)>& W, Ctx& cx,
   // last block
   cx.pend_dst = nullptr;
   if (tb >= cx.t_store) {
-    cx.pend_dst = (uint8_t*)sv + (int64_t)(tb >> 3) * (1 << KM1) + cx.lane;
+    cx.pend_dst = (uint8_t*)sv + (int64_t)(tb >> 3) * (1 << KM1) + cx.pos0 + cx.lane;
 #pragma unroll
     for (int r = 0; r < R; ++r) W.pend[r] = n == 32 ? W.acc[r] : W.acc[r] << (32 - n);
   }
@@ -369,18 +414,16 @@ __device__ __forceinline__ void one_block(Wave<DT, 1 << (KM1 - 6)>& W, Ctx& cx,
   wave_sync();
 }
 
-template <int KM1, int DT, int BETA, int BI, int NB>
-__device__ __forceinline__ void super_block(Wave<DT, 1 << (KM1 - 6)>& W, Ctx& cx,
-                                            typename Ty<DT>::T* bmt,
+template <int KM1, int DT, int BETA, int BI, int NB, int R>
+__device__ __forceinline__ void super_block(Wave<DT, R>& W, Ctx& cx, typename Ty<DT>::T* bmt,
                                             const typename Ty<DT>::In* llr,
                                             typename Ty<DT>::T (&lv)[BETA],
-                                            const int (&pat)[KM1][1 << (KM1 - 6)],
-                                            uint64_t* sv, int t0) {
+                                            const int (&pat)[KM1][R], uint64_t* sv, int t0) {
   if constexpr (BI < NB) {
     const int tb = t0 + 32 * BI;
     if (tb < cx.S) {
-      one_block<KM1, DT, BETA, BI>(W, cx, bmt, llr, lv, pat, sv, tb);
-      super_block<KM1, DT, BETA, BI + 1, NB>(W, cx, bmt, llr, lv, pat, sv, t0);
+      one_block<KM1, DT, BETA, BI, R>(W, cx, bmt, llr, lv, pat, sv, tb);
+      super_block<KM1, DT, BETA, BI + 1, NB, R>(W, cx, bmt, llr, lv, pat, sv, t0);
     }
   }
 }
@@ -395,7 +438,14 @@ constexpr int kWideWaves = 4;  // independent wavefronts (frames) per workgroup
 // runs `warm` stages from all-zero metrics before it_begin and keeps no
 // decisions from them; a part before the last leaves its end metrics in a
 // boundary record, the last part its own metric, which the check completes.
-template <int KM1, int DT, int BETA>
+//
+// WPF = 2 or 4 (float metrics, whole frames only): WPF wavefronts per
+// frame, a workgroup each, wavefront w holding positions 64 (R w + r) +
+// lane with R = 2^(K-1) / (64 WPF); the stages whose phase is a wavefront
+// bit exchange the metrics through LDS, the others run as with one
+// wavefront.  A lone long frame runs its stages with 1/WPF of the
+// instructions per wavefront.
+template <int KM1, int DT, int BETA, int WPF>
 __global__ __launch_bounds__(64 * wide::kWideWaves, 3) void k_fwd_wide(
     const DevCode* __restrict__ codes, const Item* __restrict__ items,
     const SplitUnit* __restrict__ units, int n_units, const int32_t* dev_count, int kind,
@@ -405,54 +455,67 @@ __global__ __launch_bounds__(64 * wide::kWideWaves, 3) void k_fwd_wide(
   using namespace wide;
   using T = typename Ty<DT>::T;
   using In = typename Ty<DT>::In;
-  constexpr int R = 1 << (KM1 - 6), NS = 1 << KM1, NP = 1 << BETA;
+  static_assert(WPF == 1 || ((WPF == 2 || WPF == 4) && !Ty<DT>::kInt && (1 << (KM1 - 6)) >= WPF),
+                "several wavefronts per frame: float metrics, at least one register each");
+  constexpr int R = (1 << (KM1 - 6)) / WPF, NS = 1 << KM1, NP = 1 << BETA;
+  constexpr int FPB = WPF == 1 ? kWideWaves : 1;  // frames per workgroup
   constexpr int SUPER = 32 * KM1 / gcd_c(32, KM1);  // lcm(32, K-1)
   __shared__ T bmt_all[kWideWaves][32 * NP];
-  __shared__ T xpm_all[kWideWaves][NS];
+  __shared__ T xpm_all[FPB][NS];
+  __shared__ T xch_all[WPF > 1 ? 2 * WPF * 64 * R : 1];
+  __shared__ T red_v[WPF];
+  __shared__ int red_s[WPF];
   const int wid = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
+  const int fw = WPF == 1 ? 0 : wid;  // wavefront within the frame
   if (dev_count) n_units = min(n_units, __builtin_amdgcn_readfirstlane(*dev_count));
-  const int u = blockIdx.x * kWideWaves + wid;
-  if (u >= n_units) return;  // no workgroup barriers: safe to leave
+  const int u = WPF == 1 ? blockIdx.x * kWideWaves + wid : blockIdx.x;
+  // every wavefront of a frame leaves together: the barriers are per frame
+  if (u >= n_units) return;
   const SplitUnit U = units[u];
   const Item it = items[U.first];
   const DevCode c = codes[it.code];
   const In* llr = (const In*)llr_v + it.llr_off;
   uint64_t* sv = surv + it.surv_off;
   T* bmt = bmt_all[wid];
-  T* xpm = xpm_all[wid];
+  T* xpm = xpm_all[WPF == 1 ? wid : 0];
   const bool first_part = kind == 0 && U.part == 0;
   const bool split = U.n_parts > 1;
   const int s0 = U.it_begin - U.warm;  // a multiple of SUPER: phases start at 0
 
-  // table offset (pattern) of position 64 r + lane at each phase: the even
-  // previous state's branch into the state held there after the stage
+  // table offset (pattern) of position 64 (R w + r) + lane at each phase: the
+  // even previous state's branch into the state held there after the stage
   int pat[KM1][R];
 #pragma unroll
   for (int q = 0; q < KM1; ++q) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      // the new state at position p = 64r + lane, and the previous state
-      // whose branch the stage's metric table entry gives: the even one, or
-      // in own/partner form the one at p (odd when bit q of p is set)
-      const int j = rotr(64 * r + lane, (q + 1) % KM1, KM1);
+      // the new state at position p, and the previous state whose branch
+      // the stage's metric table entry gives: the even one, or in
+      // own/partner form the one at p (odd when bit q of p is set)
+      const int j = rotr(64 * (R * fw + r) + lane, (q + 1) % KM1, KM1);
       const bool op = (q == 2 || q == 3) && !Ty<DT>::kInt;
       const int own = op ? ((lane >> q) & 1) : 0;
       pat[q][r] = branch_out(c, ((j << 1) | own) & (NS - 1), j >> (KM1 - 1));
     }
   }
   Wave<DT, R> W;
+  W.xch = xch_all;
+  W.nw = WPF;
+  W.fw = fw;
+  W.xb = 0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     if (first_part)
-      W.pm[r] = (it.start_known && (r != 0 || lane != 0)) ? Ty<DT>::unreachable() : (T)0;
+      W.pm[r] = (it.start_known && (R * fw + r != 0 || lane != 0)) ? Ty<DT>::unreachable()
+                                                                   : (T)0;
     else if (kind == 0)
       W.pm[r] = (T)0;  // a later part: all-zero metrics (unknown start)
     else
       W.pm[r] = Ty<DT>::from(bounds[U.bnd + U.part - 1].v_end[64 * r + lane]);  // repair
     W.acc[r] = 0;
   }
-  Ctx cx{0, U.it_end, lane, U.it_begin, nullptr, nullptr, nullptr};
+  Ctx cx{0, U.it_end, lane, U.it_begin, nullptr, nullptr, nullptr, 64 * R * fw};
   if (kind == 0 && U.part > 0) {
     cx.v_start = bounds[U.bnd + U.part - 1].v_start;
     cx.m_start = &bounds[U.bnd + U.part - 1].m_start;
@@ -464,7 +527,7 @@ __global__ __launch_bounds__(64 * wide::kWideWaves, 3) void k_fwd_wide(
     for (int b = 0; b < BETA; ++b) lv[b] = ok ? (T)llr[(int64_t)(s0 + lane) * BETA + b] : (T)0;
   }
   for (int t0 = s0; t0 < cx.S; t0 += SUPER)
-    super_block<KM1, DT, BETA, 0, SUPER / 32>(W, cx, bmt, llr, lv, pat, sv, t0);
+    super_block<KM1, DT, BETA, 0, SUPER / 32, R>(W, cx, bmt, llr, lv, pat, sv, t0);
   if (cx.pend_dst) store_block<KM1, R>(cx.pend_dst, W.pend);
 
   if constexpr (Ty<DT>::kInt) {
@@ -487,7 +550,7 @@ __global__ __launch_bounds__(64 * wide::kWideWaves, 3) void k_fwd_wide(
   int bs = NS;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int s = rotr(64 * r + lane, S % KM1, KM1);
+    const int s = rotr(64 * (R * fw + r) + lane, S % KM1, KM1);
     xpm[s] = W.pm[r];
     if (W.pm[r] > bv || (W.pm[r] == bv && s < bs)) {
       bv = W.pm[r];
@@ -503,8 +566,26 @@ __global__ __launch_bounds__(64 * wide::kWideWaves, 3) void k_fwd_wide(
       bs = os;
     }
   }
-  wave_sync();
-  if (lane == 0) {
+  if constexpr (WPF > 1) {
+    // the best of the wavefronts' best states, ties to the lower index
+    if (lane == 0) {
+      red_v[fw] = bv;
+      red_s[fw] = bs;
+    }
+    frame_sync<WPF>();
+#pragma unroll
+    for (int k = 0; k < WPF; ++k) {
+      const T ov = red_v[k];
+      const int os = red_s[k];
+      if (ov > bv || (ov == bv && os < bs)) {
+        bv = ov;
+        bs = os;
+      }
+    }
+  } else {
+    frame_sync<WPF>();
+  }
+  if (lane == 0 && fw == 0) {
     const int js = it.end_state >= 0 ? it.end_state : bs;
     const T vj = xpm[js];
     item_end[it.slot] = js;
@@ -569,21 +650,44 @@ __global__ __launch_bounds__(64 * wide::kWideWaves) void k_wide_check(
 
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st);
 
-hipError_t launch_fwd_wide(int K, int beta, int dt, const DevCode* codes, const Item* items,
+hipError_t launch_fwd_wide(int K, int beta, int dt, int wpf, const DevCode* codes,
+                           const Item* items,
                            const SplitUnit* units, int n_units, const void* llr, uint64_t* surv,
                            void* metric, int32_t* end_out, int32_t* item_end, WideBound* bounds,
                            int64_t* last_m, const SplitUnit* split, int n_split, int64_t* rep_m0,
                            SplitUnit* rep_units, int32_t* rep_count, hipStream_t st) {
   if (n_units <= 0) return hipSuccess;
   if (n_split > 0 && dt != 1) return hipErrorInvalidValue;  // split frames: int8 only
+  if (wpf != 1 && ((wpf != 2 && !(wpf == 4 && K == 9)) || dt != 0)) return hipErrorInvalidValue;
   const dim3 block(64 * wide::kWideWaves);
   const dim3 grid((n_units + wide::kWideWaves - 1) / wide::kWideWaves);
+  if (wpf > 1) {  // float32 whole frames: a workgroup of wpf wavefronts per frame
+#define MV_WIDE2(KM1, B, W)                                                                      \
+  hipLaunchKernelGGL((k_fwd_wide<KM1, 0, B, W>), dim3(n_units), dim3(64 * W), 0, st, codes,      \
+                     items, units, n_units, (const int32_t*)nullptr, 0, bounds, last_m,          \
+                     (const int64_t*)nullptr, llr, surv, metric, end_out, item_end);             \
+  return hipGetLastError()
+    switch (K * 64 + beta * 8 + wpf) {
+      case 8 * 64 + 2 * 8 + 2: MV_WIDE2(7, 2, 2);
+      case 8 * 64 + 3 * 8 + 2: MV_WIDE2(7, 3, 2);
+      case 8 * 64 + 4 * 8 + 2: MV_WIDE2(7, 4, 2);
+      case 9 * 64 + 2 * 8 + 2: MV_WIDE2(8, 2, 2);
+      case 9 * 64 + 3 * 8 + 2: MV_WIDE2(8, 3, 2);
+      case 9 * 64 + 4 * 8 + 2: MV_WIDE2(8, 4, 2);
+      case 9 * 64 + 2 * 8 + 4: MV_WIDE2(8, 2, 4);
+      case 9 * 64 + 3 * 8 + 4: MV_WIDE2(8, 3, 4);
+      case 9 * 64 + 4 * 8 + 4: MV_WIDE2(8, 4, 4);
+      default: return hipErrorInvalidValue;
+    }
+#undef MV_WIDE2
+  }
   const dim3 grid_rep((n_split + wide::kWideWaves - 1) / wide::kWideWaves);
   hipError_t e = hipSuccess;
 #define MV_WIDE(KM1, D, B)                                                                       \
   do {                                                                                           \
-    hipLaunchKernelGGL((k_fwd_wide<KM1, D, B>), grid, block, 0, st, codes, items, units, n_units, \
-                       (const int32_t*)nullptr, 0, bounds, last_m, (const int64_t*)nullptr, llr,  \
+    hipLaunchKernelGGL((k_fwd_wide<KM1, D, B, 1>), grid, block, 0, st, codes, items, units,     \
+                       n_units, (const int32_t*)nullptr, 0, bounds, last_m,                       \
+                       (const int64_t*)nullptr, llr,                                              \
                        surv, metric, end_out, item_end);                                          \
     e = hipGetLastError();                                                                        \
     if (e != hipSuccess || n_split <= 0) return e;                                                \
@@ -594,7 +698,7 @@ hipError_t launch_fwd_wide(int K, int beta, int dt, const DevCode* codes, const 
                        rep_count, (int64_t*)metric);                                              \
     e = hipGetLastError();                                                                        \
     if (e != hipSuccess) return e;                                                                \
-    hipLaunchKernelGGL((k_fwd_wide<KM1, D, B>), grid_rep, block, 0, st, codes, items,            \
+    hipLaunchKernelGGL((k_fwd_wide<KM1, D, B, 1>), grid_rep, block, 0, st, codes, items,         \
                        (const SplitUnit*)rep_units, n_split, (const int32_t*)rep_count, 1, bounds,\
                        last_m, (const int64_t*)rep_m0, llr, surv, metric, end_out, item_end);     \
     return hipGetLastError();                                                                     \

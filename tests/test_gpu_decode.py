@@ -279,13 +279,17 @@ def test_kernel_variants_agree(dtype, variant):
         np.testing.assert_array_equal(metric.cpu().numpy()[:16], om)
 
 
-@pytest.mark.parametrize("dtype", ["f32", "i8", "f16"])
+@pytest.mark.parametrize("dtype,variant", [("f32", 0), ("f32", 6), ("f32", 7), ("i8", 0),
+                                           ("f16", 0)],
+                         ids=["f32", "f32-two-waves", "f32-four-waves", "i8", "f16"])
 @pytest.mark.parametrize("code", [Code.from_octal(8, ["247", "371"]), CODE_K9], ids=cid)
-def test_wide_kernel_long_and_ragged(code, dtype):
-    """K = 8, 9 in registers (one frame per wavefront): frames of 1 to 5000
-    stages (partial last blocks, every phase), known and unknown starts, best
-    and zero ends, equal to the oracle; int8 frames cross many range-control
-    steps."""
+def test_wide_kernel_long_and_ragged(code, dtype, variant):
+    """K = 8, 9 in registers (one frame per wavefront, or two or four with
+    variants 6 and 7): frames of 1 to 5000 stages (partial last blocks,
+    every phase), known and unknown starts, best and zero ends, equal to the
+    oracle; int8 frames cross many range-control steps."""
+    if variant == 7 and code.K != 9:
+        pytest.skip("four wavefronts per frame: K = 9 only")
     rng = np.random.default_rng(700 + code.K)
     lens = [0, 1, 2, 7, 8, 9, 31, 32, 33, 255, 1000, 4999]
     cases = [(S, sk, ez) for S in lens for sk in (0, 1) for ez in (0, 1)
@@ -307,9 +311,11 @@ def test_wide_kernel_long_and_ragged(code, dtype):
     else:
         llr = rng.normal(0, 2.5, off).astype(np.float32 if dtype == "f32" else np.float16)
         ref, mode = llr.astype(np.float32), oracle.F32
-    print("wide", cid(code), dtype, flush=True)
-    plan = mv.Plan([code], fr, dtype, 2)
+    print("wide", cid(code), dtype, variant, flush=True)
+    plan = mv.Plan([code], fr, dtype, 2, variant=variant)
     assert "registers" in plan.describe()
+    assert ("two wavefronts per item" in plan.describe()) == (variant == 6)
+    assert ("four wavefronts per item" in plan.describe()) == (variant == 7)
     t = torch.from_numpy(llr).to(DEV)
     w, m, e = plan.decode(t)
     torch.cuda.synchronize()
@@ -502,7 +508,10 @@ def test_mixed_codes_batch(dtype, mode):
     print(desc, flush=True)
     assert desc.count("code ") == 3
     # the K=9 rate-1/3 part never runs a rotating wave table
-    assert "K=9 beta=3" in desc and "one wavefront per item" in desc
+    k9 = [part for part in desc.split("; ") if "K=9 beta=3" in part]
+    assert len(k9) == 1
+    assert any(w + " per item" in k9[0]
+               for w in ("one wavefront", "two wavefronts", "four wavefronts"))
     if mode == "persistent":
         assert "persistent work queue" in desc
     _check_mixed(codes, plan, fr, ofr, llr, dtype, n_bits)
