@@ -296,6 +296,7 @@ def other_configs(torch, mv):
             torch.cuda.synchronize()
         c1[name] = {"gpu_us": round(gpu * 1e3, 1),
                     "call_and_sync_us": round((time.perf_counter() - t0) / 50 * 1e6, 1)}
+        plan.close()
     out["single_frame_1024"] = c1
     # one 2^26-bit stream, 4 dB, int8, chunks of 2048 with 64 stages of overlap
     n = 1 << 26
@@ -349,6 +350,29 @@ def other_configs(torch, mv):
         c4[dt] = {"ms": round(ms, 3), "gbit_s": round(nn.sum() / ms / 1e6, 2),
                   "tops": round(ops / ms / 1e9, 2), "roofline_ms": round(ops / peak / 1e9, 3),
                   "frac": round(ops / ms / 1e9 / peak, 3), "plan": plan.describe()}
+        plan.close()
+        # each code's frames alone (autotuned): the parts the batch overlaps
+        alone = {}
+        for ci, cd in enumerate(codes):
+            sub = frm[mb.code_idx == ci]
+            p1 = mv.Plan(codes, sub, dt, 0, autotune=True, graph=True)
+            o1 = p1.empty_outputs(dev)
+            alone["K%d" % cd.K] = round(_gpu_ms(torch, lambda: p1.decode(inputs[dt], *o1), 5), 3)
+            p1.close()
+        c4[dt]["parts_alone_ms"] = alone
+    # the longest frame alone (K=9 r1/3, 16346 stages): the float32 bound,
+    # with its states over one, two or four wavefronts
+    lf9 = {}
+    one9 = frm[int(np.argmax(S)):][:1].copy()
+    assert codes[int(one9[0]["code"])] is CODE_K9
+    one9["code"] = 0
+    for name, dt, var in (("f32_1wave", "f32", 0), ("f32_2waves", "f32", 6),
+                          ("f32_4waves", "f32", 7), ("i8_split", "i8", 0)):
+        p1 = mv.Plan([CODE_K9], one9, dt, 2, variant=var)
+        o1 = p1.empty_outputs(dev)
+        lf9[name] = round(_gpu_ms(torch, lambda: p1.decode(inputs[dt], *o1), 5), 3)
+        p1.close()
+    c4["longest_frame_ms"] = lf9
     out["mixed_10000"] = c4
     del inputs
     # backward: 2048 x 1024 bits, 2 dB, float32
@@ -365,6 +389,7 @@ def other_configs(torch, mv):
                                  "backward_bytes": int(lf.numel() * 4 + bits.numel() * 4),
                                  "backward_tb_s": round((lf.numel() * 4 + bits.numel() * 4)
                                                         / bwd / 1e9, 2)}
+    plan.close()
     return out
 
 
@@ -397,6 +422,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    # the other workloads first, each plan closed after use: a multi-code
+    # plan's parts run concurrently only while the runtime gives their
+    # streams distinct hardware queues, which fewer live streams makes likely
+    configs = other_configs(torch, mv) if args.configs else None
     plans = {}
     results = {}
     decoded = {}
@@ -469,8 +498,8 @@ def main():
                               "HBM"},
         "variants": results,
     }
-    if args.configs:
-        line["configs"] = other_configs(torch, mv)
+    if configs is not None:
+        line["configs"] = configs
     if args.pcie and "i8r4" in plans:
         line["pcie_inclusive"] = pcie_pipeline(torch, mv, plans["i8r4"], llr_i8)
     if not args.no_cpu:
