@@ -126,7 +126,9 @@ typedef struct {
                        a wavefront bit exchanging through LDS (float32
                        only; else MIVIT_EUNSUPPORTED): a long frame's
                        serial chain runs with fewer instructions per
-                       wavefront */
+                       wavefront; 8: radix 2 with K = 8 or 9, int8, beta
+                       <= 3, two states per register in packed 16-bit
+                       metrics (else MIVIT_EUNSUPPORTED) */
   uint32_t flags;   /* MIVIT_PLAN_* scheduling options, below */
   int32_t reserved[2]; /* must be zero */
 } mivit_opts;

@@ -30,7 +30,7 @@ hipError_t launch_fwd_rot(int K, int beta, int dt, int mode, const DevCode* code
                           const Item* items, const int2* waves, int n_waves, const void* llr,
                           uint64_t* surv, void* metric, int32_t* end_out, int32_t* item_end,
                           int32_t* counter, int grid_limit, hipStream_t st);
-hipError_t launch_fwd_wide(int K, int beta, int dt, int wpf, const DevCode* codes,
+hipError_t launch_fwd_wide(int K, int beta, int dt, int wpf, bool packed, const DevCode* codes,
                            const Item* items,
                            const SplitUnit* units, int n_units, const void* llr, uint64_t* surv,
                            void* metric, int32_t* end_out, int32_t* item_end, WideBound* bounds,
@@ -615,7 +615,8 @@ hipError_t part_forward(const mivit_plan* p, const Part& q, const void* llr, voi
       e = launch_fwd_r4_mfma(q.mg, p->d_codes, q.d_items + g.first, g.count, (const int8_t*)llr,
                              q.d_surv, (int64_t*)metric, end_state, q.d_item_end, st);
     else if (g.kern == kKernWide)
-      e = launch_fwd_wide(g.K, g.beta, dt, waves_per_frame(q.ch), p->d_codes, q.d_items,
+      e = launch_fwd_wide(g.K, g.beta, dt, waves_per_frame(q.ch), q.ch.variant == 8,
+                          p->d_codes, q.d_items,
                           q.d_units, q.n_units, llr, q.d_surv, metric, end_state, q.d_item_end,
                           q.d_wbounds, q.d_last_m,
                           q.d_split, q.n_split, q.d_rep_m0, q.d_rep_units, q.d_rep_count, st);
@@ -699,6 +700,7 @@ std::vector<Choice> candidates(const mivit_code& c, int dtype, int radix) {
       add(2, 1, false);  // LDS exchanges (generic kernel)
       if (dtype == MIVIT_F32) add(2, 6, false);  // registers, two wavefronts per frame
       if (dtype == MIVIT_F32 && c.K == 9) add(2, 7, false);  // four wavefronts per frame
+      if (i8 && c.beta <= 3) add(2, 8, false);  // two states per register, 16-bit
     }
   }
   if (i8 && (radix == 0 || radix == 4)) {
@@ -785,10 +787,13 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
   if (o.radix != 0 && o.radix != 2 && o.radix != 4 && o.radix != 8) return MIVIT_EINVAL;
   if ((o.radix == 4 || o.radix == 8) && o.dtype != MIVIT_I8) return MIVIT_EINVAL;
   if (o.chunk < 0 || o.overlap < 0 || (o.chunk > 0 && o.chunk % 32 != 0)) return MIVIT_EINVAL;
-  if (o.variant < 0 || o.variant > 7) return MIVIT_EINVAL;
+  if (o.variant < 0 || o.variant > 8) return MIVIT_EINVAL;
   if (o.variant >= 3 && o.variant <= 5 && (o.radix != 4 || o.dtype != MIVIT_I8))
     return MIVIT_EUNSUPPORTED;
-  if (o.variant >= 6 && ((o.radix != 0 && o.radix != 2) || o.dtype != MIVIT_F32))
+  if ((o.variant == 6 || o.variant == 7) &&
+      ((o.radix != 0 && o.radix != 2) || o.dtype != MIVIT_F32))
+    return MIVIT_EUNSUPPORTED;
+  if (o.variant == 8 && ((o.radix != 0 && o.radix != 2) || o.dtype != MIVIT_I8))
     return MIVIT_EUNSUPPORTED;
   if (o.flags & ~(MIVIT_PLAN_GRAPH | MIVIT_PLAN_AUTOTUNE | MIVIT_PLAN_PERSISTENT |
                   MIVIT_PLAN_NO_SPLIT))
@@ -808,9 +813,12 @@ mivit_status mivit_plan_create(mivit_plan** out, const mivit_code* codes, int32_
   if (o.variant == 5)
     for (int c = 0; c < n_codes; ++c)
       if (!quad_ok(codes[c])) return MIVIT_EUNSUPPORTED;
-  if (o.variant >= 6)  // 2 or 4 wavefronts per frame: 2^(K-1) >= 128 or 256 states
+  if (o.variant == 6 || o.variant == 7)  // 2 or 4 wavefronts per frame: 128 or 256 states
     for (int c = 0; c < n_codes; ++c)
       if (codes[c].K < (o.variant == 6 ? 8 : 9)) return MIVIT_EUNSUPPORTED;
+  if (o.variant == 8)  // two states per register, 16-bit metrics: K = 8, 9 and beta <= 3
+    for (int c = 0; c < n_codes; ++c)
+      if (codes[c].K < 8 || codes[c].beta > 3) return MIVIT_EUNSUPPORTED;
   if (o.radix == 8) {  // one kernel, and at least 8 states
     if (o.variant != 0) return MIVIT_EUNSUPPORTED;
     for (int c = 0; c < n_codes; ++c)
@@ -1086,6 +1094,7 @@ mivit_status mivit_plan_describe(const mivit_plan* p, char* buf, int32_t len) {
       // the rotating kernels run a wave table; the others one wavefront per item
       const bool table = g.kern == kKernRot2 || g.kern == kKernRot4P || g.kern == kKernRot4Q;
       const int wpf = g.kern == kKernWide ? waves_per_frame(q.ch) : 1;
+      const bool two16 = g.kern == kKernWide && q.ch.variant == 8;
       std::snprintf(line, sizeof line,
                     "%scode %d: K=%d beta=%d, %s forward, variant %d, %s, %d items, %d wavefronts",
                     s.empty() ? "" : "; ", q.code, g.K, g.beta, kern_name(g.kern), q.ch.variant,
@@ -1093,6 +1102,7 @@ mivit_status mivit_plan_describe(const mivit_plan* p, char* buf, int32_t len) {
                     : table        ? "one wavefront per table entry"
                     : wpf == 2     ? "two wavefronts per item"
                     : wpf == 4     ? "four wavefronts per item"
+                    : two16        ? "one wavefront per item, two states per register"
                                    : "one wavefront per item",
                     g.count, table ? g.n_waves : wpf * g.count);
       s += line;

@@ -602,6 +602,428 @@ __global__ __launch_bounds__(64 * wide::kWideWaves, 3) void k_fwd_wide(
   }
 }
 
+namespace wide {
+
+// Packed 16-bit form of the int8 kernel (variant 8): two positions per
+// VGPR, p = 64 (v + V h) + lane in half h of VGPR v, V = 2^(K-1) / 128.
+//
+// A half holds c = 2 (PM - base) + tag, the metric doubled with the tie tag
+// of the stage's winner in its low bit.  Branch metrics enter biased by
+// 128 beta so that every candidate is an addition: the even previous state
+// adds 2 (bm + bias) + 1, the odd one 2 (-bm + bias) (its branch has the
+// opposite value, the corollary of §IV).  Every path gains the bias once
+// per stage, which the metric offset takes back.  The larger sum wins
+// (v_pk_max_u16); among equal metrics the even state's tag 1 wins, which is
+// the strict comparison with ties to the lower index, and the winner's tag
+// is 1 - d.  After the add-compare-select the tag is moved into the decision
+// word and cleared.
+//
+// Range: the metrics of a frame's states differ by at most
+// 2 (K-1) 128 beta (the spread bound of integer Viterbi metrics), and every
+// kPkRenorm stages the metric of state 0 is moved to `off`; in between the
+// halves grow by at most 4 bias per stage.  Unreachable start states begin
+// at 0, below state 0's 2 off, and lose to it within K - 1 stages.
+constexpr int kPkRenorm = 16;
+template <int KM1, int BETA>
+struct Pk {
+  static constexpr int bias = 128 * BETA;
+  static constexpr int spread = 2 * KM1 * BETA * 128;
+  static constexpr int off = spread + 1024;
+  static_assert(2 * (off + spread) + kPkRenorm * 4 * bias + 1 < 65536, "16-bit range");
+  static_assert(2 * off > KM1 * 4 * bias, "unreachable start states must lose");
+};
+
+template <int V>
+struct PkWave {
+  uint32_t pm[V];      // the two halves' doubled metrics, tags clear
+  uint32_t acc[V];     // decisions of the current group of 8 stages (bits 0-7, 16-23)
+  uint32_t blk[2][V];  // the block's finished groups, low and high halves
+  uint32_t pend[2 * V];  // the previous block's decision words (positions 64 r + lane)
+  int64_t off64;       // PM = c / 2 + off64
+};
+
+__device__ __forceinline__ uint32_t pk_max16(uint32_t a, uint32_t b) {
+  typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
+                                                                __builtin_bit_cast(u16x2, b)));
+}
+__device__ __forceinline__ uint32_t pk_add16(uint32_t a, uint32_t b) {  // per half, mod 2^16
+  typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) + __builtin_bit_cast(u16x2, b));
+}
+
+// One stage at phase Q on candidates e + we, o + wo of every VGPR; the sums
+// stay below 2^16 in each half, so 32-bit adds (which take DPP operands)
+// cannot carry across.
+template <int KM1, int V, int Q>
+__device__ __forceinline__ void pk_stage(PkWave<V>& W, const uint32_t (&we)[V],
+                                         const uint32_t (&wo)[V]) {
+  uint32_t m[V];
+  if constexpr (Q < 6) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      int e, o;
+      pair_fetch<Q, 1>((int)W.pm[v], e, o);
+      m[v] = pk_max16((uint32_t)e + we[v], (uint32_t)o + wo[v]);
+    }
+  } else if constexpr (Q < KM1 - 1) {
+    constexpr int vb = 1 << (Q - 6);  // a VGPR bit: both previous states in the lane
+#pragma unroll
+    for (int v = 0; v < V; ++v) m[v] = pk_max16(W.pm[v & ~vb] + we[v], W.pm[v | vb] + wo[v]);
+  } else {
+    // the half bit: the low half holds the even previous state, the high
+    // half the odd one, for both new states of the VGPR
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const uint32_t e = __builtin_amdgcn_perm(W.pm[v], W.pm[v], 0x01000100u);
+      const uint32_t o = __builtin_amdgcn_perm(W.pm[v], W.pm[v], 0x03020302u);
+      m[v] = pk_max16(e + we[v], o + wo[v]);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const uint32_t t = m[v] & 0x00010001u;
+    W.pm[v] = m[v] ^ t;
+    W.acc[v] = (W.acc[v] << 1) | t;
+  }
+}
+
+// A finished group of 8 stages: its byte goes below the earlier groups of
+// the block (low half: acc byte 0, high half: acc byte 2).
+template <int V>
+__device__ __forceinline__ void pk_group(PkWave<V>& W) {
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    W.blk[0][v] = __builtin_amdgcn_perm(W.blk[0][v], W.acc[v], 0x06050400u);
+    W.blk[1][v] = __builtin_amdgcn_perm(W.blk[1][v], W.acc[v], 0x06050402u);
+    W.acc[v] = 0;
+  }
+}
+
+// Range control: state 0 (low half of VGPR 0, lane 0) to 2 off.
+template <int KM1, int BETA, int V>
+__device__ __forceinline__ void pk_renorm(PkWave<V>& W) {
+  const uint32_t ref = __builtin_amdgcn_readfirstlane(W.pm[0]) & 0xFFFFu;
+  const uint32_t k = (uint32_t)(2 * Pk<KM1, BETA>::off - (int)ref) & 0xFFFFu;
+#pragma unroll
+  for (int v = 0; v < V; ++v) W.pm[v] = pk_add16(W.pm[v], k * 0x10001u);
+  W.off64 += (int64_t)(ref >> 1) - Pk<KM1, BETA>::off;
+}
+
+template <int KM1, int BETA, int V, int P0, int K>
+__device__ __forceinline__ void pk_fetch(uint32_t (&we)[V], uint32_t (&wo)[V],
+                                         const uint32_t* tbl, const int (&pat)[KM1][V]) {
+  constexpr int Q = (P0 + K) % KM1, NP = 1 << BETA;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    we[v] = tbl[K * 2 * NP + pat[Q][v]];
+    wo[v] = tbl[K * 2 * NP + NP + pat[Q][v]];
+  }
+}
+
+template <int KM1, int BETA, int V, int P0, int K0>
+__device__ __forceinline__ void pk_stages_full(PkWave<V>& W, const uint32_t* tbl,
+                                               const int (&pat)[KM1][V],
+                                               uint32_t (&qe)[kPrefetch][V],
+                                               uint32_t (&qo)[kPrefetch][V]) {
+  if constexpr (K0 < 32) {
+    constexpr int Q = (P0 + K0) % KM1;
+    uint32_t we[V], wo[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      we[v] = qe[K0 % kPrefetch][v];
+      wo[v] = qo[K0 % kPrefetch][v];
+    }
+    if constexpr (K0 + kPrefetch < 32)
+      pk_fetch<KM1, BETA, V, P0, K0 + kPrefetch>(qe[K0 % kPrefetch], qo[K0 % kPrefetch], tbl, pat);
+    pk_stage<KM1, V, Q>(W, we, wo);
+    if constexpr (K0 % 8 == 7) pk_group<V>(W);
+    if constexpr (K0 + 1 == kPkRenorm) pk_renorm<KM1, BETA, V>(W);
+    __builtin_amdgcn_sched_barrier(0);
+    pk_stages_full<KM1, BETA, V, P0, K0 + 1>(W, tbl, pat, qe, qo);
+  }
+}
+
+template <int KM1, int BETA, int V, int P0, int K>
+__device__ __forceinline__ void pk_prefetch(uint32_t (&qe)[kPrefetch][V],
+                                            uint32_t (&qo)[kPrefetch][V], const uint32_t* tbl,
+                                            const int (&pat)[KM1][V]) {
+  if constexpr (K < kPrefetch) {
+    pk_fetch<KM1, BETA, V, P0, K>(qe[K], qo[K], tbl, pat);
+    pk_prefetch<KM1, BETA, V, P0, K + 1>(qe, qo, tbl, pat);
+  }
+}
+
+template <int KM1, int BETA, int V, int Q>
+__device__ __forceinline__ void pk_stage_dyn(PkWave<V>& W, const uint32_t* row,
+                                             const int (&pat)[KM1][V], int q) {
+  if constexpr (Q < KM1) {
+    if (q == Q) {
+      constexpr int NP = 1 << BETA;
+      uint32_t we[V], wo[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        we[v] = row[pat[Q][v]];
+        wo[v] = row[NP + pat[Q][v]];
+      }
+      pk_stage<KM1, V, Q>(W, we, wo);
+    } else {
+      pk_stage_dyn<KM1, BETA, V, Q + 1>(W, row, pat, q);
+    }
+  }
+}
+
+struct PkCtx {
+  int S, lane, t_store;
+  int32_t* v_start;  // split part after the first: boundary record to fill at t_store
+  int64_t* m_start;
+  uint8_t* pend_dst;
+  const DevCode* code;
+};
+
+// One block of up to 32 stages starting at tb (BI: its index in the period
+// of the phase pattern); lv holds this lane's soft values of stage tb + lane
+// (lanes < 32) and is replaced by those of the next block.
+template <int KM1, int BETA, int BI, int V>
+__device__ __forceinline__ void pk_block(PkWave<V>& W, PkCtx& cx, uint32_t* tbl,
+                                         const int8_t* llr, int (&lv)[BETA],
+                                         const int (&pat)[KM1][V], uint64_t* sv, int tb) {
+  constexpr int NP = 1 << BETA, NS = 1 << KM1, bias = Pk<KM1, BETA>::bias;
+  constexpr int P0 = (32 * BI) % KM1;
+  const int n = min(32, cx.S - tb);
+  if (cx.lane < 32) {
+    // stage tb + lane: its phase, and the pattern difference between the
+    // two halves of a VGPR there (the half bit of the position flips one
+    // bit b of the new state j, so bit b + 1 of the encoder register j << 1)
+    const int q = (P0 + cx.lane) % KM1;
+    const int b = (2 * KM1 - 2 - q) % KM1 + 1;
+    int dx = 0;
+#pragma unroll
+    for (int i = 0; i < BETA; ++i) dx |= (int)((cx.code->gen[i] >> b) & 1u) << i;
+    // bm[x] of pattern x, bh[x] of pattern x ^ dx (the soft values whose
+    // bit is set in dx enter with the other sign)
+    int bm[NP], bh[NP];
+#pragma unroll
+    for (int x = 0; x < NP / 2; ++x) {
+      int sum = 0, sum_h = 0;
+#pragma unroll
+      for (int i = 0; i < BETA; ++i) {
+        const int l = ((x >> i) & 1) ? -lv[i] : lv[i];
+        sum += l;
+        sum_h += ((dx >> i) & 1) ? -l : l;
+      }
+      bm[x] = sum;
+      bm[NP - 1 - x] = -sum;
+      bh[x] = sum_h;
+      bh[NP - 1 - x] = -sum_h;
+    }
+    uint32_t* row = tbl + cx.lane * 2 * NP;
+#pragma unroll
+    for (int x = 0; x < NP; ++x) {
+      row[x] = (uint32_t)(2 * (bm[x] + bias) + 1) | ((uint32_t)(2 * (bh[x] + bias) + 1) << 16);
+      row[NP + x] = (uint32_t)(2 * (bias - bm[x])) | ((uint32_t)(2 * (bias - bh[x])) << 16);
+    }
+  }
+  {
+    const int t = tb + 32 + cx.lane;
+    const bool ok = cx.lane < 32 && t < cx.S;
+#pragma unroll
+    for (int i = 0; i < BETA; ++i) lv[i] = ok ? (int)llr[(int64_t)t * BETA + i] : 0;
+  }
+  if (cx.pend_dst) store_block<KM1, 2 * V>(cx.pend_dst, W.pend);
+  if (tb > 0) pk_renorm<KM1, BETA, V>(W);
+  if (cx.v_start && tb == cx.t_store) {
+    // a later part of a split frame, at the end of its warm-up
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      cx.v_start[64 * v + cx.lane] = (int32_t)(W.pm[v] & 0xFFFFu) / 2 - Pk<KM1, BETA>::off;
+      cx.v_start[64 * (v + V) + cx.lane] = (int32_t)(W.pm[v] >> 16) / 2 - Pk<KM1, BETA>::off;
+    }
+    if (cx.lane == 0) *cx.m_start = W.off64 + Pk<KM1, BETA>::off;
+  }
+  // every candidate carries the bias once per stage: the block's total
+  W.off64 -= (int64_t)bias * n;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    W.acc[v] = 0;
+    W.blk[0][v] = 0;
+    W.blk[1][v] = 0;
+  }
+  wave_sync();
+  if (n == 32) {
+    uint32_t qe[kPrefetch][V], qo[kPrefetch][V];
+    pk_prefetch<KM1, BETA, V, P0, 0>(qe, qo, tbl, pat);
+    pk_stages_full<KM1, BETA, V, P0, 0>(W, tbl, pat, qe, qo);
+  } else {
+#pragma unroll 1
+    for (int k = 0; k < n; ++k) {
+      pk_stage_dyn<KM1, BETA, V, 0>(W, tbl + k * 2 * NP, pat, (P0 + k) % KM1);
+      if ((k & 7) == 7) pk_group<V>(W);
+      if (k + 1 == kPkRenorm && n > kPkRenorm) pk_renorm<KM1, BETA, V>(W);
+    }
+    if (n & 7) {
+      // the last, partial group: its first stage to bit 7 of the byte
+      const int sh = 8 - (n & 7);
+#pragma unroll
+      for (int v = 0; v < V; ++v) W.acc[v] <<= sh;
+      pk_group<V>(W);
+    }
+  }
+  // this block's decision words, group g in byte 3 - g, the tags inverted
+  // into decisions, stages past the block's end zero; stored at the next
+  // block's start or after the last block
+  cx.pend_dst = nullptr;
+  if (tb >= cx.t_store) {
+    const int groups = (n + 7) >> 3;
+    const uint32_t valid = n == 32 ? 0xFFFFFFFFu : ~(0xFFFFFFFFu >> n);
+    cx.pend_dst = (uint8_t*)sv + (int64_t)(tb >> 3) * NS + cx.lane;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const uint32_t w = groups == 4 ? W.blk[h][v] : W.blk[h][v] << (8 * (4 - groups));
+        W.pend[V * h + v] = ~w & valid;
+      }
+    }
+  }
+  wave_sync();
+}
+
+template <int KM1, int BETA, int BI, int NB, int V>
+__device__ __forceinline__ void pk_super(PkWave<V>& W, PkCtx& cx, uint32_t* tbl,
+                                         const int8_t* llr, int (&lv)[BETA],
+                                         const int (&pat)[KM1][V], uint64_t* sv, int t0) {
+  if constexpr (BI < NB) {
+    const int tb = t0 + 32 * BI;
+    if (tb < cx.S) {
+      pk_block<KM1, BETA, BI, V>(W, cx, tbl, llr, lv, pat, sv, tb);
+      pk_super<KM1, BETA, BI + 1, NB, V>(W, cx, tbl, llr, lv, pat, sv, t0);
+    }
+  }
+}
+
+}  // namespace wide
+
+// The packed form of the int8 kernel for kind 0 units (whole items or parts
+// of split frames; repairs run the 32-bit kernel, whose decisions and
+// records are the same).  Outputs as k_fwd_wide's.
+template <int KM1, int BETA>
+__global__ __launch_bounds__(64 * wide::kWideWaves, 3) void k_fwd_wpk(
+    const DevCode* __restrict__ codes, const Item* __restrict__ items,
+    const SplitUnit* __restrict__ units, int n_units, WideBound* bounds, int64_t* last_m,
+    const int8_t* __restrict__ llr_all, uint64_t* __restrict__ surv, int64_t* metric,
+    int32_t* end_out, int32_t* item_end) {
+  using namespace wide;
+  using P = Pk<KM1, BETA>;
+  constexpr int V = (1 << (KM1 - 6)) / 2, NS = 1 << KM1, NP = 1 << BETA;
+  constexpr int SUPER = 32 * KM1 / gcd_c(32, KM1);  // lcm(32, K-1)
+  static_assert(SUPER % kPkRenorm == 0, "range control at fixed stages of the period");
+  __shared__ uint32_t tbl_all[kWideWaves][32 * 2 * NP];
+  __shared__ int32_t xpm_all[kWideWaves][NS];
+  const int wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int u = blockIdx.x * kWideWaves + wid;
+  if (u >= n_units) return;  // no workgroup barriers: safe to leave
+  const SplitUnit U = units[u];
+  const Item it = items[U.first];
+  const DevCode c = codes[it.code];
+  const int8_t* llr = llr_all + it.llr_off;
+  uint64_t* sv = surv + it.surv_off;
+  uint32_t* tbl = tbl_all[wid];
+  int32_t* xpm = xpm_all[wid];
+  const bool split = U.n_parts > 1;
+  const int s0 = U.it_begin - U.warm;  // a multiple of SUPER: phases start at 0
+
+  // table offset (pattern) of the low position 64 v + lane of each VGPR at
+  // each phase: the even previous state's branch into the new state there
+  int pat[KM1][V];
+#pragma unroll
+  for (int q = 0; q < KM1; ++q) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int j = rotr(64 * v + lane, (q + 1) % KM1, KM1);
+      pat[q][v] = branch_out(c, (j << 1) & (NS - 1), j >> (KM1 - 1));
+    }
+  }
+  PkWave<V> W;
+  const uint32_t all = (uint32_t)(2 * P::off) * 0x10001u;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    // a known start: state 0 (low half of VGPR 0, lane 0) at 2 off, the
+    // others unreachable at 0; else (and for later parts) all at 2 off
+    W.pm[v] = (U.part == 0 && it.start_known) ? ((v == 0 && lane == 0) ? (uint32_t)(2 * P::off) : 0u)
+                                               : all;
+  }
+  W.off64 = -(int64_t)P::off;
+  PkCtx cx{U.it_end, lane, U.it_begin, nullptr, nullptr, nullptr, &c};
+  if (U.part > 0) {
+    cx.v_start = bounds[U.bnd + U.part - 1].v_start;
+    cx.m_start = &bounds[U.bnd + U.part - 1].m_start;
+  }
+  int lv[BETA];
+  {
+    const bool ok = lane < 32 && s0 + lane < cx.S;
+#pragma unroll
+    for (int i = 0; i < BETA; ++i) lv[i] = ok ? (int)llr[(int64_t)(s0 + lane) * BETA + i] : 0;
+  }
+  for (int t0 = s0; t0 < cx.S; t0 += SUPER)
+    pk_super<KM1, BETA, 0, SUPER / 32, V>(W, cx, tbl, llr, lv, pat, sv, t0);
+  if (cx.pend_dst) store_block<KM1, 2 * V>(cx.pend_dst, W.pend);
+
+  if (split && U.part < U.n_parts - 1) {
+    // the end of a part before the last: range control relative to state 0,
+    // then the boundary record
+    const int32_t ref = (int32_t)(__builtin_amdgcn_readfirstlane(W.pm[0]) & 0xFFFFu) / 2;
+    WideBound& B = bounds[U.bnd + U.part];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      B.v_end[64 * v + lane] = (int32_t)(W.pm[v] & 0xFFFFu) / 2 - ref;
+      B.v_end[64 * (v + V) + lane] = (int32_t)(W.pm[v] >> 16) / 2 - ref;
+    }
+    if (lane == 0) B.m_end = W.off64 + ref;
+    return;
+  }
+
+  // final metrics: position p holds state rotr(p, S mod (K-1)); best state
+  // with ties to the lowest index
+  const int S = cx.S;
+  int bv = -(1 << 30);
+  int bs = NS;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int s = rotr(64 * (v + V * h) + lane, S % KM1, KM1);
+      const int val = (int)((h ? W.pm[v] >> 16 : W.pm[v] & 0xFFFFu) >> 1) - P::off;
+      xpm[s] = val;
+      if (val > bv || (val == bv && s < bs)) {
+        bv = val;
+        bs = s;
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int ov = __shfl_xor(bv, o);
+    const int os = __shfl_xor(bs, o);
+    if (ov > bv || (ov == bv && os < bs)) {
+      bv = ov;
+      bs = os;
+    }
+  }
+  wave_sync();
+  if (lane == 0) {
+    const int js = it.end_state >= 0 ? it.end_state : bs;
+    item_end[it.slot] = js;
+    if (it.frame >= 0 && end_out) end_out[it.frame] = js;
+    const int64_t local = (int64_t)xpm[js] + W.off64 + P::off;
+    if (split)
+      last_m[it.slot] = local;  // completed by the check
+    else if (it.frame >= 0 && metric)
+      metric[it.frame] = local;
+  }
+}
+
 // The check after a split forward pass of the K = 8, 9 kernel, one wavefront
 // per split frame (its part-0 unit): boundary k is exact when part k's
 // range-controlled metrics at its end equal part k+1's after its warm-up at
@@ -650,7 +1072,7 @@ __global__ __launch_bounds__(64 * wide::kWideWaves) void k_wide_check(
 
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st);
 
-hipError_t launch_fwd_wide(int K, int beta, int dt, int wpf, const DevCode* codes,
+hipError_t launch_fwd_wide(int K, int beta, int dt, int wpf, bool packed, const DevCode* codes,
                            const Item* items,
                            const SplitUnit* units, int n_units, const void* llr, uint64_t* surv,
                            void* metric, int32_t* end_out, int32_t* item_end, WideBound* bounds,
@@ -659,6 +1081,7 @@ hipError_t launch_fwd_wide(int K, int beta, int dt, int wpf, const DevCode* code
   if (n_units <= 0) return hipSuccess;
   if (n_split > 0 && dt != 1) return hipErrorInvalidValue;  // split frames: int8 only
   if (wpf != 1 && ((wpf != 2 && !(wpf == 4 && K == 9)) || dt != 0)) return hipErrorInvalidValue;
+  if (packed && (dt != 1 || wpf != 1 || beta > 3)) return hipErrorInvalidValue;
   const dim3 block(64 * wide::kWideWaves);
   const dim3 grid((n_units + wide::kWideWaves - 1) / wide::kWideWaves);
   if (wpf > 1) {  // float32 whole frames: a workgroup of wpf wavefronts per frame
@@ -685,10 +1108,17 @@ hipError_t launch_fwd_wide(int K, int beta, int dt, int wpf, const DevCode* code
   hipError_t e = hipSuccess;
 #define MV_WIDE(KM1, D, B)                                                                       \
   do {                                                                                           \
-    hipLaunchKernelGGL((k_fwd_wide<KM1, D, B, 1>), grid, block, 0, st, codes, items, units,     \
-                       n_units, (const int32_t*)nullptr, 0, bounds, last_m,                       \
-                       (const int64_t*)nullptr, llr,                                              \
-                       surv, metric, end_out, item_end);                                          \
+    if constexpr (D == 1 && B <= 3) {                                                             \
+      if (packed)                                                                                 \
+        hipLaunchKernelGGL((k_fwd_wpk<KM1, B>), grid, block, 0, st, codes, items, units, n_units, \
+                           bounds, last_m, (const int8_t*)llr, surv, (int64_t*)metric, end_out,    \
+                           item_end);                                                             \
+    }                                                                                             \
+    if (!packed)                                                                                  \
+      hipLaunchKernelGGL((k_fwd_wide<KM1, D, B, 1>), grid, block, 0, st, codes, items, units,     \
+                         n_units, (const int32_t*)nullptr, 0, bounds, last_m,                     \
+                         (const int64_t*)nullptr, llr,                                            \
+                         surv, metric, end_out, item_end);                                        \
     e = hipGetLastError();                                                                        \
     if (e != hipSuccess || n_split <= 0) return e;                                                \
     e = launch_zero_i32(rep_count, 1, st);                                                        \

@@ -24,7 +24,7 @@ hipError_t launch_fwd_rot(int K, int beta, int dt, int mode, const DevCode* code
                           const Item* items, const int2* waves, int n_waves, const void* llr,
                           uint64_t* surv, void* metric, int32_t* end_out, int32_t* item_end,
                           int32_t* counter, int grid_limit, hipStream_t st);
-hipError_t launch_fwd_wide(int K, int beta, int dt, int wpf, const DevCode* codes,
+hipError_t launch_fwd_wide(int K, int beta, int dt, int wpf, bool packed, const DevCode* codes,
                            const Item* items,
                            const SplitUnit* units, int n_units, const void* llr, uint64_t* surv,
                            void* metric, int32_t* end_out, int32_t* item_end, WideBound* bounds,
@@ -218,7 +218,7 @@ extern "C" mivit_status mivit_decode_uniform_noalloc(const void* llr, int32_t dt
     if (e == hipSuccess)
       e = launch_tb_seg(kLayoutRotR2, d_code, items, n_frames, surv, item_end, bits, kWarm, st);
   } else {
-    e = launch_fwd_wide(c.K, c.beta, dtype, 1, d_code, items, (const SplitUnit*)waves, n_frames, llr,
+    e = launch_fwd_wide(c.K, c.beta, dtype, 1, false, d_code, items, (const SplitUnit*)waves, n_frames, llr,
                         surv, metric, nullptr, item_end, nullptr, nullptr, nullptr, 0, nullptr,
                         nullptr, nullptr, st);
     if (e == hipSuccess)

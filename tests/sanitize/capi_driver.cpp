@@ -87,7 +87,7 @@ int main() {
   struct { int dtype, radix, chunk, overlap, variant; uint32_t flags; } bad[] = {
       {3, 0, 0, 0, 0, 0},  {-1, 0, 0, 0, 0, 0}, {0, 3, 0, 0, 0, 0},   {0, 16, 0, 0, 0, 0},
       {0, 4, 0, 0, 0, 0},  {2, 4, 0, 0, 0, 0},  {0, 8, 0, 0, 0, 0},   {2, 8, 0, 0, 0, 0},
-      {0, 0, -1, 0, 0, 0}, {0, 0, 100, 0, 0, 0}, {0, 0, 0, -1, 0, 0}, {0, 0, 0, 0, 8, 0},
+      {0, 0, -1, 0, 0, 0}, {0, 0, 100, 0, 0, 0}, {0, 0, 0, -1, 0, 0}, {0, 0, 0, 0, 9, 0},
       {0, 0, 0, 0, 0, 16}, {0, 0, 0, 0, 0, 1u << 31},
   };
   for (const auto& b : bad) {
@@ -128,6 +128,11 @@ int main() {
     expect("variant 6, K = 7", plan({k7}, {frame()}, o), MIVIT_EUNSUPPORTED);
     o.variant = 7;
     expect("variant 7, K = 8", plan({code(8, {0247, 0371})}, {frame()}, o), MIVIT_EUNSUPPORTED);
+    o.variant = 8;
+    expect("variant 8, float32", plan({code(9, {0557, 0663, 0711})}, {frame()}, o),
+           MIVIT_EUNSUPPORTED);
+    o.dtype = MIVIT_I8;
+    expect("variant 8, K = 7", plan({k7}, {frame()}, o), MIVIT_EUNSUPPORTED);
   }
 
   // null handles and pointers

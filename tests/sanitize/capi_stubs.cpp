@@ -22,7 +22,7 @@ hipError_t launch_fwd_rot(int, int, int, int, const DevCode*, const Item*, const
                           hipStream_t) {
   return hipErrorInvalidValue;
 }
-hipError_t launch_fwd_wide(int, int, int, int, const DevCode*, const Item*, const SplitUnit*, int,
+hipError_t launch_fwd_wide(int, int, int, int, bool, const DevCode*, const Item*, const SplitUnit*, int,
                            const void*, uint64_t*, void*, int32_t*, int32_t*, WideBound*, int64_t*,
                            const SplitUnit*, int, int64_t*, SplitUnit*, int32_t*, hipStream_t) {
   return hipErrorInvalidValue;

@@ -108,7 +108,7 @@ def test_overlapping_outputs():
     dict(dtype=3), dict(dtype=-1), dict(radix=3), dict(radix=16), dict(radix=4, dtype=0),
     dict(radix=4, dtype=2), dict(radix=8, dtype=0), dict(radix=8, dtype=2),
     dict(chunk=-1), dict(chunk=100),
-    dict(overlap=-1), dict(variant=8), dict(flags=16), dict(flags=1 << 31),
+    dict(overlap=-1), dict(variant=9), dict(flags=16), dict(flags=1 << 31),
 ])
 def test_bad_opts(opts):
     assert _plan_status([K7], _frame(), **opts) == _capi.MIVIT_EINVAL
@@ -241,7 +241,7 @@ def test_mfma_variant_rejections():
                         variant=3) == _capi.MIVIT_EUNSUPPORTED
     assert _plan_status([_code(9, [0o557, 0o663, 0o711])], fr, dtype=1, radix=4,
                         variant=3) == _capi.MIVIT_EUNSUPPORTED
-    assert _plan_status([K7], fr, dtype=1, radix=4, variant=8) == _capi.MIVIT_EINVAL
+    assert _plan_status([K7], fr, dtype=1, radix=4, variant=9) == _capi.MIVIT_EINVAL
     # variant 4 (packed, one state per lane): int8 radix 4, K = 5 or 7 rate 1/2 only
     assert _plan_status([K7], fr, dtype=1, radix=2, variant=4) == _capi.MIVIT_EUNSUPPORTED
     assert _plan_status([_code(9, [0o557, 0o663, 0o711])], fr, dtype=1, radix=4,
@@ -254,7 +254,8 @@ def test_mfma_variant_rejections():
 
 def test_wide_wavefront_variant_rejections():
     """Variants 6 and 7 (two or four wavefronts per frame) take float32 soft
-    values, radix 2 and codes with K >= 8 (6) or K = 9 (7)."""
+    values, radix 2 and codes with K >= 8 (6) or K = 9 (7); variant 8 (packed
+    16-bit) takes int8, radix 2, K >= 8 and at most three outputs."""
     fr = _frame()
     K8 = _code(8, [0o247, 0o371])
     K9 = _code(9, [0o557, 0o663, 0o711])
@@ -264,3 +265,9 @@ def test_wide_wavefront_variant_rejections():
     assert _plan_status([K9], fr, dtype=1, radix=2, variant=6) == _capi.MIVIT_EUNSUPPORTED
     assert _plan_status([K9], fr, dtype=2, radix=2, variant=7) == _capi.MIVIT_EUNSUPPORTED
     assert _plan_status([K9], fr, dtype=0, radix=4, variant=7) == _capi.MIVIT_EINVAL
+    # variant 8 (two states per register, 16-bit): int8, radix 2, K >= 8, beta <= 3
+    assert _plan_status([K9], fr, dtype=0, radix=2, variant=8) == _capi.MIVIT_EUNSUPPORTED
+    assert _plan_status([K7], fr, dtype=1, radix=2, variant=8) == _capi.MIVIT_EUNSUPPORTED
+    assert _plan_status([K9], fr, dtype=1, radix=4, variant=8) == _capi.MIVIT_EUNSUPPORTED
+    assert _plan_status([_code(9, [0o557, 0o663, 0o711, 0o755])], fr, dtype=1, radix=2,
+                        variant=8) == _capi.MIVIT_EUNSUPPORTED

@@ -211,6 +211,36 @@ def test_int8_extremes(code):
             np.testing.assert_array_equal(metric.cpu().numpy()[:F], om)
 
 
+@pytest.mark.parametrize("code", [Code.from_octal(8, ["247", "371"]), CODE_K9], ids=cid)
+def test_int8_extremes_wide(code):
+    """Saturated soft values and long runs of one value (the largest growth
+    per stage and the widest spread) through the K = 8, 9 radix-2 kernel, in
+    32-bit metrics and in packed 16-bit metrics (variant 8), split in time
+    and whole: bits and metrics equal the oracle."""
+    rng = np.random.default_rng(91 + code.K)
+    n, F = 6000, 4
+    S = n + code.K - 1
+    pick = rng.integers(0, 4, size=(F, S * code.beta))
+    vals = np.array([127, -127, -128, 0], np.int16)[pick]
+    runs = rng.integers(0, 2, size=(F, 1)) * rng.integers(-128, 128, size=(F, S * code.beta))
+    q = np.where(rng.random((F, S * code.beta)) < 0.3, runs, vals).astype(np.int8)
+    q[1] = -128  # one frame of a single value
+    q[2] = 127
+    ob, om, _ = oracle.decode_uniform(code, q, n, True, oracle.I64)
+    fr = mv.uniform_frames(code, F, n, True)
+    for variant in (0, 8):
+        for split in (True, False):
+            print("extremes wide", cid(code), variant, split, flush=True)
+            plan = mv.Plan([code], fr, "i8", 2, variant=variant, split=split)
+            words, metric, _ = plan.decode(torch.from_numpy(q).to(DEV))
+            torch.cuda.synchronize()
+            nw = (n + 31) // 32
+            bits = mv.unpack_bits(words.cpu().numpy()[: F * nw].reshape(F, nw), n)
+            np.testing.assert_array_equal(bits, ob)
+            np.testing.assert_array_equal(metric.cpu().numpy()[:F], om)
+            plan.close()
+
+
 @pytest.mark.parametrize("code", [CODE_K5, CODE_K7], ids=cid)
 def test_int8_windows(code):
     """Chunked windows (unknown start, best end, emitted cores that differ
@@ -280,13 +310,15 @@ def test_kernel_variants_agree(dtype, variant):
 
 
 @pytest.mark.parametrize("dtype,variant", [("f32", 0), ("f32", 6), ("f32", 7), ("i8", 0),
-                                           ("f16", 0)],
-                         ids=["f32", "f32-two-waves", "f32-four-waves", "i8", "f16"])
+                                           ("i8", 8), ("f16", 0)],
+                         ids=["f32", "f32-two-waves", "f32-four-waves", "i8", "i8-packed16",
+                              "f16"])
 @pytest.mark.parametrize("code", [Code.from_octal(8, ["247", "371"]), CODE_K9], ids=cid)
 def test_wide_kernel_long_and_ragged(code, dtype, variant):
     """K = 8, 9 in registers (one frame per wavefront, or two or four with
-    variants 6 and 7): frames of 1 to 5000 stages (partial last blocks,
-    every phase), known and unknown starts, best and zero ends, equal to the
+    variants 6 and 7; variant 8: int8 in packed 16-bit metrics, two states
+    per register): frames of 1 to 5000 stages (partial last blocks, every
+    phase), known and unknown starts, best and zero ends, equal to the
     oracle; int8 frames cross many range-control steps."""
     if variant == 7 and code.K != 9:
         pytest.skip("four wavefronts per frame: K = 9 only")
@@ -1036,13 +1068,15 @@ def test_r4_split_in_time_matches_oracle(eb, code, variant):
 
 @pytest.mark.parametrize("code", [CODE_K9, Code.from_octal(8, ["247", "371"])], ids=cid)
 @pytest.mark.parametrize("eb", [0.0, 2.0])
-def test_wide_split_in_time_matches_oracle(code, eb):
+@pytest.mark.parametrize("variant", [0, 8], ids=["int32", "packed16"])
+def test_wide_split_in_time_matches_oracle(code, eb, variant):
     """int8 K = 8, 9 frames much longer than the rest of the batch are split
     in time by the radix-2 register kernel (later parts warm up from all-zero
     metrics, a check compares the range-controlled metrics at every boundary
     and repairs the frames that disagree): bits, metrics and end states equal
     the oracle, terminated, free-end and unknown-start frames, at 0 dB (many
-    repairs) and 2 dB; the unsplit plan agrees."""
+    repairs) and 2 dB; the unsplit plan agrees.  Variant 8 runs the packed
+    16-bit form (two states per register; repairs run the 32-bit kernel)."""
     from workload import int8_scale_for
     rng = np.random.default_rng(int(9100 + code.K + 10 * eb))
     beta = code.beta
@@ -1065,8 +1099,8 @@ def test_wide_split_in_time_matches_oracle(code, eb):
     ob, om, oend, _ = oracle.decode_frames([code], ofr, llr, oracle.I64, nb)
     t = torch.from_numpy(llr).to(DEV)
     for split in (True, False):
-        print("wide split", cid(code), eb, split, flush=True)
-        plan = mv.Plan([code], fr, "i8", 2, split=split)
+        print("wide split", cid(code), eb, split, variant, flush=True)
+        plan = mv.Plan([code], fr, "i8", 2, split=split, variant=variant)
         w, m, e = plan.decode(t)
         torch.cuda.synchronize()
         bits = mv.unpack_bits(w.cpu().numpy()[: nb // 32], nb)
