@@ -313,7 +313,9 @@ def test_kernel_variants_agree(dtype, variant):
                                            ("i8", 8), ("f16", 0)],
                          ids=["f32", "f32-two-waves", "f32-four-waves", "i8", "i8-packed16",
                               "f16"])
-@pytest.mark.parametrize("code", [Code.from_octal(8, ["247", "371"]), CODE_K9], ids=cid)
+@pytest.mark.parametrize("code", [Code.from_octal(8, ["247", "371"]), CODE_K9,
+                                  Code.from_octal(9, ["561", "753"]),
+                                  Code.from_octal(8, ["225", "331", "367"])], ids=cid)
 def test_wide_kernel_long_and_ragged(code, dtype, variant):
     """K = 8, 9 in registers (one frame per wavefront, or two or four with
     variants 6 and 7; variant 8: int8 in packed 16-bit metrics, two states
