@@ -141,11 +141,11 @@ struct Wave {
 };
 
 // All wavefronts of a frame at one point, LDS writes before it visible to
-// LDS reads after it (one wavefront: program order suffices).
-template <int WPF>
+// LDS reads after it.  One wavefront per frame: program order suffices;
+// several (kWorkgroup): the frame is the workgroup, a barrier.
+template <bool kWorkgroup>
 __device__ __forceinline__ void frame_sync() {
-  // (any WPF > 1: the frame is the workgroup)
-  if constexpr (WPF == 1) {
+  if constexpr (!kWorkgroup) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -207,7 +207,7 @@ __device__ __forceinline__ void stage(Wave<DT, R>& W, const typename Ty<DT>::T (
     const T* theirs = W.xch + (nw * W.xb + (W.fw ^ wb)) * (64 * R);
 #pragma unroll
     for (int r = 0; r < R; ++r) mine[64 * r + lane] = W.pm[r];
-    frame_sync<2>();
+    frame_sync<true>();
     const bool odd = (W.fw & wb) != 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -572,7 +572,7 @@ __global__ __launch_bounds__(64 * wide::kWideWaves, 3) void k_fwd_wide(
       red_v[fw] = bv;
       red_s[fw] = bs;
     }
-    frame_sync<WPF>();
+    frame_sync<(WPF > 1)>();
 #pragma unroll
     for (int k = 0; k < WPF; ++k) {
       const T ov = red_v[k];
@@ -583,7 +583,7 @@ __global__ __launch_bounds__(64 * wide::kWideWaves, 3) void k_fwd_wide(
       }
     }
   } else {
-    frame_sync<WPF>();
+    frame_sync<(WPF > 1)>();
   }
   if (lane == 0 && fw == 0) {
     const int js = it.end_state >= 0 ? it.end_state : bs;
