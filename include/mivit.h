@@ -191,6 +191,17 @@ mivit_status mivit_plan_create(mivit_plan** plan, const mivit_code* codes, int32
                                const mivit_frame* frames, int32_t n_frames,
                                const mivit_opts* opts);
 
+/* mivit_plan_create on a given device (the plan's device argument of the
+ * boundary): device >= 0 builds the plan there, with that device made
+ * current for the call and the caller's current device restored after it;
+ * device < 0 means the current device.  Every later call on the plan runs on
+ * its device whatever device is current then.  Errors: MIVIT_EINVAL
+ * (plan NULL, device not below the device count), those of
+ * mivit_plan_create, MIVIT_EHIP (the device count cannot be read). */
+mivit_status mivit_plan_create_on(mivit_plan** plan, int32_t device, const mivit_code* codes,
+                                  int32_t n_codes, const mivit_frame* frames, int32_t n_frames,
+                                  const mivit_opts* opts);
+
 /* Decode every frame of the plan (forward procedure, then traceback).
  *   llr        device, float32, float16 or int8 per the plan's dtype, read-only
  *   bits       device uint32 words; frame f writes the words covering

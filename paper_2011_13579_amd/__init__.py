@@ -80,7 +80,7 @@ def _dptr(t) -> int:
 
 
 class Plan:
-    """A fixed batch of frames (see mivit_plan_create).
+    """A fixed batch of frames (see mivit_plan_create and mivit_plan_create_on).
 
     frames: numpy array of FRAME_DTYPE (llr_offset, bit_offset, n_stages,
     out_begin, n_out, code, flags).
@@ -88,7 +88,8 @@ class Plan:
 
     def __init__(self, codes: Sequence, frames: np.ndarray, dtype: str = "f32", radix: int = 0,
                  chunk: int = 0, overlap: int = 0, variant: int = 0, graph: bool = False,
-                 autotune: bool = False, persistent: bool = False, split: bool = True):
+                 autotune: bool = False, persistent: bool = False, split: bool = True,
+                 device=None):
         lib = _capi.load()
         self.codes = [_as_code(c) for c in codes]
         self.frames = np.ascontiguousarray(frames, dtype=FRAME_DTYPE)
@@ -102,10 +103,18 @@ class Plan:
                       (_capi.MIVIT_PLAN_PERSISTENT if persistent else 0) |
                       (0 if split else _capi.MIVIT_PLAN_NO_SPLIT))
         h = ctypes.c_void_p()
-        st = lib.mivit_plan_create(ctypes.byref(h), arr, len(self.codes),
-                                   self.frames.ctypes.data if len(self.frames) else None,
-                                   len(self.frames), ctypes.byref(opts))
-        _capi.check(st, "mivit_plan_create")
+        # device: None (or a torch device without an index) for the current
+        # device, else a device index or a torch device (mivit_plan_create_on)
+        if device is None:
+            dev = -1
+        elif isinstance(device, int):
+            dev = device
+        else:
+            dev = -1 if device.index is None else int(device.index)
+        st = lib.mivit_plan_create_on(ctypes.byref(h), dev, arr, len(self.codes),
+                                      self.frames.ctypes.data if len(self.frames) else None,
+                                      len(self.frames), ctypes.byref(opts))
+        _capi.check(st, "mivit_plan_create_on")
         self._h = h
         self._lib = lib
         info = _capi.PlanInfo()

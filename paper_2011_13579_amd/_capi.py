@@ -15,7 +15,7 @@ MIVIT_START_KNOWN, MIVIT_END_ZERO = 1, 2
 
 # every symbol include/mivit.h declares
 EXPORTS = (
-    "mivit_plan_create", "mivit_decode", "mivit_forward", "mivit_traceback", "mivit_decode_grad", "mivit_plan_destroy",
+    "mivit_plan_create", "mivit_plan_create_on", "mivit_decode", "mivit_forward", "mivit_traceback", "mivit_decode_grad", "mivit_plan_destroy",
     "mivit_plan_get_info", "mivit_plan_describe", "mivit_quantize_i8", "mivit_strerror",
     "mivit_version", "mivit_pipe_create", "mivit_pipe_run", "mivit_pipe_destroy",
     "mivit_stream_create", "mivit_stream_push", "mivit_stream_finish", "mivit_stream_destroy",
@@ -89,6 +89,9 @@ def load(path: str = LIB_PATH):
     lib.mivit_plan_create.restype = ctypes.c_int
     lib.mivit_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Code), i32,
                                       ctypes.c_void_p, i32, ctypes.POINTER(Opts)]
+    lib.mivit_plan_create_on.restype = ctypes.c_int
+    lib.mivit_plan_create_on.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(Code), i32,
+                                         ctypes.c_void_p, i32, ctypes.POINTER(Opts)]
     lib.mivit_decode.restype = ctypes.c_int
     lib.mivit_decode.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.mivit_forward.restype = ctypes.c_int

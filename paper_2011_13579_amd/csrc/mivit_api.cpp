@@ -1006,6 +1006,25 @@ mivit_status mivit_traceback(mivit_plan* p, uint32_t* bits, void* stream) {
                               (hipStream_t)stream));
 }
 
+mivit_status mivit_plan_create_on(mivit_plan** out, int32_t device, const mivit_code* codes,
+                                  int32_t n_codes, const mivit_frame* frames, int32_t n_frames,
+                                  const mivit_opts* opts) {
+  if (!out) return MIVIT_EINVAL;
+  *out = nullptr;
+  if (device < 0) return mivit_plan_create(out, codes, n_codes, frames, n_frames, opts);
+  clear_stale_error();
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess) {
+    clear_stale_error();
+    return MIVIT_EHIP;
+  }
+  if (device >= count) return MIVIT_EINVAL;
+  // the plan is built, and records its device, with that device current;
+  // the caller's current device is restored
+  DeviceGuard guard(device);
+  return mivit_plan_create(out, codes, n_codes, frames, n_frames, opts);
+}
+
 mivit_status mivit_decode(mivit_plan* p, const void* llr, uint32_t* bits, void* metric,
                           int32_t* end_state, void* stream) {
   if (!p) return MIVIT_EINVAL;

@@ -138,6 +138,8 @@ int main() {
   // null handles and pointers
   expect("plan_create null", mivit_plan_create(nullptr, nullptr, 0, nullptr, 0, nullptr),
          MIVIT_EINVAL);
+  expect("plan_create_on null", mivit_plan_create_on(nullptr, 0, nullptr, 0, nullptr, 0, nullptr),
+         MIVIT_EINVAL);
   expect("decode null", mivit_decode(nullptr, nullptr, nullptr, nullptr, nullptr, nullptr),
          MIVIT_EINVAL);
   expect("grad null", mivit_decode_grad(nullptr, nullptr, nullptr, nullptr, nullptr),

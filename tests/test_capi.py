@@ -271,3 +271,10 @@ def test_wide_wavefront_variant_rejections():
     assert _plan_status([K9], fr, dtype=1, radix=4, variant=8) == _capi.MIVIT_EUNSUPPORTED
     assert _plan_status([_code(9, [0o557, 0o663, 0o711, 0o755])], fr, dtype=1, radix=2,
                         variant=8) == _capi.MIVIT_EUNSUPPORTED
+
+
+def test_plan_create_on_rejects_null_handle():
+    """mivit_plan_create_on validates its output pointer before any device
+    call (no GPU needed)."""
+    lib = _capi.load()
+    assert lib.mivit_plan_create_on(None, 0, None, 0, None, 0, None) == _capi.MIVIT_EINVAL

@@ -1112,3 +1112,26 @@ def test_wide_split_in_time_matches_oracle(code, eb, variant):
             a, n = int(ofr[k]["bit_offset"]), int(ofr[k]["n_out"])
             np.testing.assert_array_equal(bits[a:a + n], ob[a:a + n])
         plan.close()
+
+
+def test_plan_on_explicit_device():
+    """mivit_plan_create_on: a plan built on device 0 by index or torch device
+    decodes as the oracle does and leaves the current device as it was; a
+    device index at or beyond the device count is refused."""
+    rng = np.random.default_rng(4242)
+    n, F = 300, 5
+    q = rng.integers(-40, 41, size=(F, (n + CODE_K7.K - 1) * CODE_K7.beta)).astype(np.int8)
+    ob, om, _ = oracle.decode_uniform(CODE_K7, q, n, True, oracle.I64)
+    before = torch.cuda.current_device()
+    for dev in (0, torch.device("cuda:0")):
+        plan = mv.Plan([CODE_K7], mv.uniform_frames(CODE_K7, F, n, True), "i8", 4, device=dev)
+        assert torch.cuda.current_device() == before
+        words, metric, _ = plan.decode(torch.from_numpy(q).to(DEV))
+        torch.cuda.synchronize()
+        nw = (n + 31) // 32
+        np.testing.assert_array_equal(mv.unpack_bits(words.cpu().numpy()[: F * nw].reshape(F, nw), n), ob)
+        np.testing.assert_array_equal(metric.cpu().numpy()[:F], om)
+        plan.close()
+    with pytest.raises(mv._capi.MivitError):
+        mv.Plan([CODE_K7], mv.uniform_frames(CODE_K7, F, n, True), "i8", 4,
+                device=torch.cuda.device_count())
